@@ -1,0 +1,104 @@
+/*
+ * lme_oracle.h -- plain FP64 CPU oracle for Lindblad master-equation evolution.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path; it is
+ * called by the tests, by the smoke check and by the CPU-baseline leg of the
+ * benchmark, and by nothing else.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * Paper: Johansson, Nation, Nori, "QuTiP: An open-source Python framework for
+ * the dynamics of open quantum systems" (arXiv:1110.0573).
+ *   - Lindblad equation: Sec. 3.1, Eq. (master_equation), hbar = 1 (Sec. 2,
+ *     Eq. (twolevel) convention), C_n = sqrt(gamma_n) A_n.
+ *   - Time-dependent Hamiltonian as a sum of terms: Sec. 4.6 (Landau-Zener
+ *     callback H0 + t*H1), generalised here to H0 + sum_j u_j(t) H_j with
+ *     piecewise-constant u_j.
+ *   - Expectation values at the output times: Sec. 4 (odesolve with e_ops).
+ *
+ * Storage conventions (all arrays are host memory, owned by the caller):
+ *   - complex numbers are two consecutive doubles (re, im);
+ *   - a density matrix is n*n complex numbers, row-major: rho[i*n + j];
+ *   - operators are CSR: row_ptr[n+1], col[nnz], val[2*nnz].
+ *
+ * Return codes: ORC_OK and the ORC_E* values below.
+ */
+#ifndef LME_ORACLE_H
+#define LME_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_OK = 0,
+  ORC_EINVAL = 1,          /* malformed argument                              */
+  ORC_EGRID = 2,           /* output time / control edge off the RK4 grid      */
+  ORC_EMAXSTEPS = 3,       /* adaptive: step budget exhausted                  */
+  ORC_ESTEPUNDERFLOW = 4,  /* adaptive: step size fell below h_min             */
+  ORC_ENONFINITE = 5,      /* NaN/Inf met in the state or the error norm       */
+  ORC_ENOMEM = 6
+};
+
+typedef struct {
+  int32_t n, nnz;
+  const int32_t *row_ptr, *col;
+  const double *val;               /* 2*nnz doubles */
+} orc_csr;
+
+typedef struct {
+  int32_t n;
+  orc_csr H0;
+  int32_t n_ctrl;  const orc_csr *Hc;   /* control Hamiltonians H_j            */
+  int32_t n_c;     const orc_csr *C;    /* collapse operators C_k              */
+  int32_t n_e;     const orc_csr *E;    /* expectation operators               */
+  int32_t n_seg;   const double *edges; /* n_seg+1 increasing times            */
+  const double *u;                      /* u[j*n_seg + s]: amplitude of H_j on
+                                           [edges[s], edges[s+1])            */
+} orc_system;
+
+/* out = L(t) y, the right-hand side of the Lindblad equation. */
+int orc_apply_L(const orc_system *s, double t, const double *y, double *out);
+/* out = L(t)^dagger x, adjoint w.r.t. the Hilbert-Schmidt inner product. */
+int orc_apply_Ldag(const orc_system *s, double t, const double *x, double *out);
+/* Tr(E_m rho) for every expectation operator; out[2*m], out[2*m+1]. */
+int orc_expect(const orc_system *s, const double *rho, double *out);
+
+/* Classic fixed-step RK4 from tlist[0] to tlist[n_t-1] in nsteps equal steps.
+ * expect: [n_e][n_t] complex (may be NULL when n_e == 0);
+ * states: [n_t][n*n] complex or NULL. */
+int orc_rk4(const orc_system *s, const double *rho0, int32_t n_t,
+            const double *tlist, int32_t nsteps, double *expect, double *states);
+
+/* Dormand-Prince 5(4) with per-step error control; steps stop exactly on every
+ * output time and control edge.  h_log (may be NULL) receives the accepted step
+ * sizes, at most h_log_cap of them.  counts[0] = accepted, counts[1] = rejected. */
+int orc_dopri5(const orc_system *s, const double *rho0, int32_t n_t,
+               const double *tlist, double rtol, double atol, double h0,
+               double h_min, int64_t max_steps, double *expect, double *states,
+               int64_t *counts, double *h_log, int64_t h_log_cap);
+
+/* One Dormand-Prince step from (t, y) with step h: y5 = fifth-order solution,
+ * err = h * sum_i (b_i - bhat_i) k_i (the embedded error estimate). */
+int orc_dopri5_step(const orc_system *s, double t, double h, const double *y,
+                    double *y5, double *err);
+
+/* Fixed-step RK4 cost J = Re Tr(O rho(t1)) and its exact gradient with
+ * respect to the piecewise-constant amplitudes, grad[j*n_seg + s], by the
+ * discrete adjoint of the RK4 map. */
+int orc_rk4_cost_grad(const orc_system *s, const double *rho0, const double *O,
+                      double t0, double t1, int32_t nsteps, double *cost,
+                      double *grad);
+
+/* RK4 over many independent instances on n_threads host threads (dynamic
+ * scheduling); used for timing the oracle on the host. rc[b] per instance. */
+int orc_rk4_batch(int32_t n_inst, const orc_system *systems,
+                  const double *const *rho0, int32_t n_t, const double *tlist,
+                  int32_t nsteps, double *const *expect, int32_t n_threads,
+                  int32_t *rc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
