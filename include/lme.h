@@ -1,0 +1,212 @@
+/*
+ * lme.h -- C ABI of the MI355X (gfx950) Lindblad master-equation library.
+ *
+ * What is computed (Johansson, Nation & Nori, arXiv:1110.0573):
+ *   Sec. 3.1, Eq. (master_equation), hbar = 1:
+ *     drho/dt = L(t) rho = -i[H(t), rho]
+ *               + sum_k ( C_k rho C_k^+ - 1/2 rho C_k^+ C_k - 1/2 C_k^+ C_k rho )
+ *   with H(t) = H0 + sum_j u_j(t) H_j (Sec. 4.6 gives a time-dependent
+ *   Hamiltonian as constant operators times scalar functions of time; here
+ *   the u_j are piecewise constant on a fixed set of segment edges).
+ *   Sec. 4 (odesolve): the solver returns expectation values Tr(E rho(t)) at
+ *   every requested output time, the first output time being the initial
+ *   time, or the density matrices themselves.
+ * The paper names no integrator.  Two are provided: classic fixed-step RK4
+ * and the adaptive Dormand-Prince 5(4) pair.
+ *
+ * Conventions used throughout:
+ *   - complex numbers are two consecutive doubles (re, im) ("complex128");
+ *   - a density matrix of dimension n is n*n complex128, row-major
+ *     (element (i, j) at i*n + j);
+ *   - a batch of instances (possibly of different n) is one packed device
+ *     buffer: instance b occupies [offset[b], offset[b] + n_b^2) in units of
+ *     complex128, offsets in instance order without gaps (lme_layout);
+ *   - operators are handed over as host CSR (lme_csr) and COPIED at create:
+ *     the caller may free them as soon as lme_create* returns;
+ *   - every device pointer argument is caller-owned device memory
+ *     (e.g. a torch tensor's data_ptr()); the library only reads or writes it
+ *     on the given HIP stream, asynchronously; it must stay valid until the
+ *     work queued on that stream has completed;
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *
+ * Errors: every entry point returns an lme_status.  Arguments are validated
+ * on the host before any HIP call is made, so a malformed argument never
+ * reaches the GPU.  lme_last_error() gives a human-readable message for the
+ * last failing call on the calling thread.  No C++ exception crosses the ABI.
+ * Failures that can only be detected on the device during integration
+ * (step budget, step underflow, non-finite values) are reported per instance
+ * through the optional `status_dev` array.
+ *
+ * Thread safety: distinct handles may be used concurrently; one handle must
+ * not be used by two host threads at the same time.
+ */
+#ifndef LME_H
+#define LME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LME_ABI_VERSION 1
+
+typedef enum lme_status {
+  LME_OK = 0,
+  LME_EINVAL = 1,          /* malformed argument (CSR, sizes, options, times) */
+  LME_EGRID = 2,           /* RK4: an output time or a control edge is not on
+                              the uniform step grid                          */
+  LME_EMAXSTEPS = 3,       /* adaptive: max_steps attempts used up (device)   */
+  LME_ESTEPUNDERFLOW = 4,  /* adaptive: step size fell below h_min (device)   */
+  LME_ENONFINITE = 5,      /* NaN/Inf in an error norm or expectation (device)*/
+  LME_ENOMEM = 6,          /* host or device allocation failed                */
+  LME_EHIP = 7,            /* a HIP runtime call failed (no device, launch)   */
+  LME_ENOTSUP = 8          /* valid input outside what this build supports    */
+} lme_status;
+
+typedef struct lme_ctx *lme_handle;
+
+typedef enum lme_method { LME_RK4 = 0, LME_DOPRI5 = 1 } lme_method;
+
+/* Which kernel family integrates the batch. */
+typedef enum lme_path {
+  LME_PATH_AUTO = 0,       /* resident when every instance fits, else streamed */
+  LME_PATH_RESIDENT = 1,   /* one workgroup owns a pack of instances for the
+                              whole integration; stage input held in LDS      */
+  LME_PATH_STREAMED = 2    /* one grid-wide kernel per stage; state in HBM    */
+} lme_path;
+
+/* Form of the Liouvillian application used by lme_apply. */
+typedef enum lme_form {
+  LME_FORM_OPERATOR = 0,   /* sparse H, C_k applied to the dense n x n matrix */
+  LME_FORM_SUPEROP = 1     /* explicit n^2 x n^2 CSR superoperator SpMV       */
+} lme_form;
+
+/* Square sparse matrix in CSR form, host memory.
+ *   row_ptr[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
+ *   col[nnz] (0 <= col < n; duplicates within a row are summed),
+ *   val[2*nnz] complex128.  Explicit zeros are dropped at create. */
+typedef struct lme_csr {
+  int32_t n;
+  int32_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const double *val;
+} lme_csr;
+
+/* One open system.  H0 (Hermitian), the batch-wide number n_ctrl of control
+ * Hamiltonians H_ctrl[n_ctrl] (Hermitian), n_c collapse operators C[n_c]
+ * (arbitrary; n_c may differ between instances) and the batch-wide number
+ * n_e of expectation operators E[n_e] (arbitrary).  All of dimension n. */
+typedef struct lme_instance {
+  const lme_csr *H0;
+  const lme_csr *H_ctrl;
+  int32_t n_c;
+  const lme_csr *C;
+  const lme_csr *E;
+} lme_instance;
+
+/* Piecewise-constant control segments shared by the batch: u_j(t) takes its
+ * segment value on [edges[s], edges[s+1]) and is 0 outside [edges[0],
+ * edges[n_seg]).  A step never straddles an edge: with RK4 every edge inside
+ * the integration interval must lie on the step grid (else LME_EGRID); the
+ * adaptive stepper stops on every edge.  Within one step the amplitudes of
+ * the segment holding the step's midpoint are used. */
+typedef struct lme_segments {
+  int32_t n_seg;           /* 0: no controls                                  */
+  const double *edges;     /* host, [n_seg+1], strictly increasing            */
+} lme_segments;
+
+typedef struct lme_options {
+  int32_t method;          /* lme_method                                      */
+  int32_t path;            /* lme_path                                        */
+  int32_t nsteps;          /* RK4: equal steps from tlist[0] to tlist[n_t-1];
+                              every output time must be on this grid          */
+  int32_t block;           /* resident path: threads per workgroup
+                              (256, 512 or 1024); 0 = tuned default           */
+  double rtol, atol;       /* DOPRI5: per-element tolerance
+                              atol + rtol*max(|rho|, |rho_new|)               */
+  double h0;               /* DOPRI5: first step; <= 0 selects it
+                              automatically (Hairer-Norsett-Wanner rule)      */
+  double h_min;            /* DOPRI5: smallest allowed step                   */
+  int64_t max_steps;       /* DOPRI5: attempts (accepted + rejected) per
+                              instance                                        */
+} lme_options;
+
+/* Fills defaults: RK4, AUTO path, nsteps 0 (must be set), block 0,
+ * rtol 1e-6, atol 1e-9, h0 0, h_min 0, max_steps 10^7. */
+void lme_default_options(lme_options *opt);
+
+/* Create a handle for a batch of n_inst independent systems.
+ *   inst[n_inst]: the systems (host, copied);
+ *   n_ctrl, n_e: batch-wide counts of control and expectation operators;
+ *   seg: control segments (NULL or n_seg == 0 when n_ctrl == 0);
+ *   u_host: default control amplitudes, host, [n_inst][n_ctrl][n_seg]
+ *           (NULL = all zero); lme_evolve may override them per call.
+ * Builds the operator tables (A = -iH0 - 1/2 sum_k C_k^+ C_k, the control
+ * terms -iH_j, the jump tables and their adjoints) and uploads them to the
+ * current HIP device.  *out receives the handle (NULL on failure).
+ * Errors: LME_EINVAL, LME_ENOTSUP (an operator row with more than 64
+ * non-zeros, or n > 4096), LME_ENOMEM, LME_EHIP. */
+int lme_create_batch(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
+                     int32_t n_e, const lme_segments *seg, const double *u_host,
+                     lme_handle *out);
+
+/* Single-instance form of lme_create_batch:
+ *   lme_create(H0, {H_j}, segments + amplitudes, {C_k}, {E_m}). */
+int lme_create(const lme_csr *H0, int32_t n_ctrl, const lme_csr *H_ctrl,
+               const lme_segments *seg, const double *u_host, int32_t n_c,
+               const lme_csr *C, int32_t n_e, const lme_csr *E, lme_handle *out);
+
+/* Releases the handle and every device buffer it owns.  NULL is a no-op.
+ * Work already queued on a stream that uses the handle must have completed. */
+void lme_destroy(lme_handle h);
+
+/* Message for the last failing call made by this host thread ("" if none). */
+const char *lme_last_error(void);
+
+/* Number of instances, total packed state size (complex128 elements), and
+ * the per-instance layout: offsets[n_inst] (elements) and dims[n_inst].
+ * Either output array may be NULL. */
+int lme_layout(lme_handle h, int32_t *n_inst, int64_t *state_elems,
+               int64_t *offsets, int32_t *dims);
+
+/* Time integration (Sec. 4, odesolve) of every instance from tlist[0].
+ *   opt: method and its parameters (see lme_options);
+ *   n_t, tlist: host, strictly increasing output times (n_t >= 1);
+ *   rho0_dev: packed initial states (complex128, lme_layout);
+ *   u_dev: device [n_inst][n_ctrl][n_seg] control amplitudes, or NULL to
+ *          use those given at create;
+ * outputs (each may be NULL):
+ *   expect_dev: complex128 [n_inst][n_e][n_t], Tr(E_m rho(tlist[k]));
+ *   states_dev: complex128 [n_t][state_elems], rho at every output time;
+ *   rho_out_dev: complex128 [state_elems], rho at tlist[n_t-1];
+ *   counts_dev: int64 [n_inst][2], accepted and rejected steps;
+ *   status_dev: int32 [n_inst], LME_OK or the device-detected failure of
+ *               that instance (LME_EMAXSTEPS, LME_ESTEPUNDERFLOW,
+ *               LME_ENONFINITE); a failed instance stops integrating and
+ *               its later outputs are left untouched.
+ * The call is asynchronous on `stream` except that the adaptive stepper on
+ * the streamed path polls a device flag from the host between step batches.
+ * Host-side errors: LME_EINVAL, LME_EGRID, LME_ENOTSUP, LME_ENOMEM, LME_EHIP. */
+int lme_evolve(lme_handle h, const lme_options *opt, int32_t n_t,
+               const double *tlist, const void *rho0_dev, const double *u_dev,
+               void *expect_dev, void *states_dev, void *rho_out_dev,
+               int64_t *counts_dev, int32_t *status_dev, void *stream);
+
+/* One application of the Liouvillian (Eq. (master_equation)) or, with
+ * adjoint != 0, of its adjoint under the Hilbert-Schmidt inner product
+ * L^+ x = i[H, x] + sum_k (C_k^+ x C_k - 1/2 {C_k^+ C_k, x}),
+ * to every instance of a packed batch at time t:
+ *   out_dev = L(t) y_dev   (both complex128, packed; must not overlap).
+ *   form: LME_FORM_OPERATOR or LME_FORM_SUPEROP (the latter assembles the
+ *         n^2 x n^2 CSR superoperator on first use; forward only).
+ *   u_dev: as in lme_evolve (NULL = amplitudes given at create). */
+int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
+              const double *u_dev, const void *y_dev, void *out_dev,
+              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

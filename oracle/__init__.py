@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIBPATH):
         return _LIBPATH
     tmp = _LIBPATH + f".tmp{os.getpid()}"
-    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-Wall", "-shared", "-fPIC",
+    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-shared", "-fPIC",
            "-o", tmp, _SRC, "-lm", "-lpthread"]
     subprocess.run(cmd, check=True, cwd=_HERE)
     os.replace(tmp, _LIBPATH)

@@ -1,0 +1,774 @@
+// lme_host.cpp -- host side of the C ABI declared in include/lme.h.
+//
+// Validation, operator pre-fold, batch planning and kernel launches.  Every
+// argument is checked before the first HIP call, so malformed input is
+// rejected even on a machine without a GPU.
+//
+// Pre-fold (Eq. (master_equation), hbar = 1):  L y = A y + y A^+ +
+// sum_k C_k y C_k^+ with A = -i H0 - 1/2 sum_k C_k^+ C_k + sum_j u_j (-i H_j).
+// A, -i H_j and C_k are stored as diagonal + ELL tables (lme_internal.h);
+// their conjugate transposes give the adjoint L^+.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lme.h"
+#include "lme_internal.h"
+
+using cd = std::complex<double>;
+using lme::InstDesc;
+using lme::PackDesc;
+
+extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap);
+extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb);
+extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
+                                              int n_packs, int lds, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
+                                                    int lds, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char *what) {
+  return fail(LME_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// small host sparse matrix (rows of (col, value), sorted, merged)
+// ---------------------------------------------------------------------------
+struct Sparse {
+  int n = 0;
+  std::vector<std::vector<std::pair<int, cd>>> rows;
+
+  explicit Sparse(int n_ = 0) : n(n_), rows(n_) {}
+  void add(int i, int j, cd v) { rows[i].emplace_back(j, v); }
+  void finalize() {
+    for (auto &r : rows) {
+      std::sort(r.begin(), r.end(),
+                [](const std::pair<int, cd> &a, const std::pair<int, cd> &b) {
+                  return a.first < b.first;
+                });
+      std::vector<std::pair<int, cd>> m;
+      for (auto &e : r) {
+        if (!m.empty() && m.back().first == e.first)
+          m.back().second += e.second;
+        else
+          m.push_back(e);
+      }
+      r.clear();
+      for (auto &e : m)
+        if (e.second != cd(0.0, 0.0)) r.push_back(e);
+    }
+  }
+  Sparse dagger() const {
+    Sparse t(n);
+    for (int i = 0; i < n; ++i)
+      for (auto &e : rows[i]) t.add(e.first, i, std::conj(e.second));
+    t.finalize();
+    return t;
+  }
+  void axpy(cd a, const Sparse &B) {  // this += a * B
+    for (int i = 0; i < n; ++i)
+      for (auto &e : B.rows[i]) add(i, e.first, a * e.second);
+  }
+  int width_offdiag() const {
+    int w = 0;
+    for (int i = 0; i < n; ++i) {
+      int c = 0;
+      for (auto &e : rows[i]) c += (e.first != i);
+      w = std::max(w, c);
+    }
+    return w;
+  }
+  int width() const {
+    int w = 0;
+    for (auto &r : rows) w = std::max(w, (int)r.size());
+    return w;
+  }
+};
+
+// C^+ C: (C^+ C)_il = sum_r conj(C_ri) C_rl
+static Sparse dag_times_self(const Sparse &C) {
+  Sparse out(C.n);
+  for (int r = 0; r < C.n; ++r)
+    for (auto &a : C.rows[r])
+      for (auto &b : C.rows[r]) out.add(a.first, b.first, std::conj(a.second) * b.second);
+  out.finalize();
+  return out;
+}
+
+static int check_csr(const lme_csr *m, int n, const char *what, int b, Sparse *out) {
+  if (!m) return fail(LME_EINVAL, "instance %d: %s is NULL", b, what);
+  if (m->n != n) return fail(LME_EINVAL, "instance %d: %s has n=%d, expected %d", b, what, m->n, n);
+  if (m->nnz < 0 || !m->row_ptr || (m->nnz > 0 && (!m->col || !m->val)))
+    return fail(LME_EINVAL, "instance %d: %s has missing arrays", b, what);
+  if (m->row_ptr[0] != 0 || m->row_ptr[n] != m->nnz)
+    return fail(LME_EINVAL, "instance %d: %s row_ptr does not span [0, nnz]", b, what);
+  Sparse s(n);
+  for (int i = 0; i < n; ++i) {
+    if (m->row_ptr[i + 1] < m->row_ptr[i])
+      return fail(LME_EINVAL, "instance %d: %s row_ptr decreases at row %d", b, what, i);
+    for (int p = m->row_ptr[i]; p < m->row_ptr[i + 1]; ++p) {
+      const int c = m->col[p];
+      if (c < 0 || c >= n)
+        return fail(LME_EINVAL, "instance %d: %s column %d out of range", b, what, c);
+      const double re = m->val[2 * p], im = m->val[2 * p + 1];
+      if (!std::isfinite(re) || !std::isfinite(im))
+        return fail(LME_EINVAL, "instance %d: %s has a non-finite value", b, what);
+      s.add(i, c, cd(re, im));
+    }
+  }
+  s.finalize();
+  *out = std::move(s);
+  return LME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int upload(const void *src, size_t n, const char *what) {
+    release();
+    if (n == 0) return LME_OK;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e == hipErrorOutOfMemory ? fail(LME_ENOMEM, "hipMalloc(%s, %zu B) failed", what, n)
+                                      : hip_fail(e, what);
+    }
+    bytes = n;
+    e = hipMemcpy(p, src, n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return LME_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct Plan {
+  int T = 0, EPT = 0, adjoint = 0, cap = 0;
+  std::vector<PackDesc> packs;
+  std::vector<int32_t> order;
+  int max_lds = 0;
+  DevBuf d_packs, d_order;
+};
+
+struct lme_ctx {
+  int32_t n_inst = 0, n_ctrl = 0, n_e = 0, n_seg = 0;
+  std::vector<double> edges;
+  std::vector<InstDesc> inst;
+  std::vector<int64_t> offsets;
+  std::vector<int32_t> dims;
+  int64_t state_elems = 0;
+  int device = 0;
+  int lds_limit = 0;
+  // host copies of the pools, uploaded on first device use
+  std::vector<uint8_t> ops, adj, eops;
+  std::vector<double> u_default;
+  bool on_device = false;
+  DevBuf d_inst, d_ops, d_adj, d_eops, d_u;
+  std::vector<Plan *> plans;
+  // step tables of the last evolve call (content-cached)
+  std::vector<int32_t> steps_key;
+  DevBuf d_steps;
+  ~lme_ctx() {
+    for (Plan *p : plans) delete p;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// op blobs
+// ---------------------------------------------------------------------------
+struct Ell {
+  std::vector<cd> val;     // [w][n]
+  std::vector<int32_t> col;
+};
+
+static Ell to_ell(const Sparse &S, int w, bool offdiag_only) {
+  Ell e;
+  const int n = S.n;
+  e.val.assign((size_t)w * n, cd(0.0, 0.0));
+  e.col.resize((size_t)w * n);
+  for (int i = 0; i < n; ++i) {
+    int slot = 0;
+    for (int s = 0; s < w; ++s) e.col[(size_t)s * n + i] = i;
+    for (auto &x : S.rows[i]) {
+      if (offdiag_only && x.first == i) continue;
+      e.val[(size_t)slot * n + i] = x.second;
+      e.col[(size_t)slot * n + i] = x.first;
+      ++slot;
+    }
+  }
+  return e;
+}
+
+static std::vector<cd> diag_of(const Sparse &S) {
+  std::vector<cd> d(S.n, cd(0.0, 0.0));
+  for (int i = 0; i < S.n; ++i)
+    for (auto &x : S.rows[i])
+      if (x.first == i) d[i] = x.second;
+  return d;
+}
+
+static void put_cd(std::vector<uint8_t> &blob, int off, const std::vector<cd> &v) {
+  std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(cd));
+}
+static void put_i32(std::vector<uint8_t> &blob, int off, const std::vector<int32_t> &v) {
+  std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(int32_t));
+}
+
+// Blob of (A, {B_j}, {C_k}) with A, B_j already folded.
+static std::vector<uint8_t> make_blob(const Sparse &A, const std::vector<Sparse> &B,
+                                      const std::vector<Sparse> &J, lme::Signature *sig) {
+  const int n = A.n;
+  int wo = A.width_offdiag(), wb = 0, wc = 0;
+  for (auto &b : B) wb = std::max(wb, b.width_offdiag());
+  for (auto &c : J) wc = std::max(wc, c.width());
+  sig->n = n;
+  sig->wo = wo;
+  sig->nb = (int)B.size();
+  sig->wb = wb;
+  sig->nc = (int)J.size();
+  sig->wc = wc;
+  const lme::BlobLayout L = lme::blob_layout(n, wo, sig->nb, wb, sig->nc, wc);
+  std::vector<uint8_t> blob((size_t)L.bytes, 0);
+  put_cd(blob, L.offD, diag_of(A));
+  Ell o = to_ell(A, wo, true);
+  put_cd(blob, L.offOval, o.val);
+  put_i32(blob, L.offOcol, o.col);
+  for (int k = 0; k < sig->nc; ++k) {
+    Ell e = to_ell(J[k], wc, false);
+    put_cd(blob, L.offJval + 16 * k * wc * n, e.val);
+    put_i32(blob, L.offJcol + 4 * k * wc * n, e.col);
+  }
+  for (int q = 0; q < sig->nb; ++q) {
+    put_cd(blob, L.offDB + 16 * q * n, diag_of(B[q]));
+    Ell e = to_ell(B[q], wb, true);
+    put_cd(blob, L.offOBval + 16 * q * wb * n, e.val);
+    put_i32(blob, L.offOBcol + 4 * q * wb * n, e.col);
+  }
+  return blob;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy / layout
+// ---------------------------------------------------------------------------
+extern "C" void lme_default_options(lme_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof *opt);
+  opt->method = LME_RK4;
+  opt->path = LME_PATH_AUTO;
+  opt->rtol = 1e-6;
+  opt->atol = 1e-9;
+  opt->max_steps = 10000000;
+}
+
+extern "C" const char *lme_last_error(void) { return g_err.c_str(); }
+
+static int create_impl(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl, int32_t n_e,
+                       const lme_segments *seg, const double *u_host, lme_handle *out) {
+  if (!out) return fail(LME_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_inst < 1 || !inst) return fail(LME_EINVAL, "n_inst must be >= 1 with a valid array");
+  if (n_ctrl < 0 || n_e < 0) return fail(LME_EINVAL, "n_ctrl and n_e must be >= 0");
+  int32_t n_seg = 0;
+  std::vector<double> edges;
+  if (seg && seg->n_seg > 0) {
+    if (!seg->edges) return fail(LME_EINVAL, "segments: edges is NULL");
+    n_seg = seg->n_seg;
+    edges.assign(seg->edges, seg->edges + n_seg + 1);
+    for (int q = 0; q <= n_seg; ++q)
+      if (!std::isfinite(edges[q])) return fail(LME_EINVAL, "segments: non-finite edge");
+    for (int q = 0; q < n_seg; ++q)
+      if (!(edges[q + 1] > edges[q])) return fail(LME_EINVAL, "segments: edges not increasing");
+  } else if (seg && seg->n_seg < 0) {
+    return fail(LME_EINVAL, "segments: n_seg < 0");
+  }
+  if (u_host && n_ctrl > 0 && n_seg > 0)
+    for (int64_t i = 0; i < (int64_t)n_inst * n_ctrl * n_seg; ++i)
+      if (!std::isfinite(u_host[i])) return fail(LME_EINVAL, "u_host has a non-finite value");
+
+  auto *h = new (std::nothrow) lme_ctx;
+  if (!h) return fail(LME_ENOMEM, "out of host memory");
+  std::unique_ptr<lme_ctx> guard(h);
+  h->n_inst = n_inst;
+  h->n_ctrl = n_ctrl;
+  h->n_e = n_e;
+  h->n_seg = n_seg;
+  h->edges = edges;
+  h->inst.resize(n_inst);
+  h->offsets.resize(n_inst);
+  h->dims.resize(n_inst);
+
+  std::vector<uint8_t> ops, adj, eops;
+  for (int b = 0; b < n_inst; ++b) {
+    const lme_instance &I = inst[b];
+    if (!I.H0) return fail(LME_EINVAL, "instance %d: H0 is NULL", b);
+    const int n = I.H0->n;
+    if (n < 1) return fail(LME_EINVAL, "instance %d: n must be >= 1", b);
+    if (n > lme::kMaxDim) return fail(LME_ENOTSUP, "instance %d: n=%d exceeds %d", b, n, lme::kMaxDim);
+    if (I.n_c < 0 || (I.n_c > 0 && !I.C)) return fail(LME_EINVAL, "instance %d: bad collapse list", b);
+    if (n_ctrl > 0 && !I.H_ctrl) return fail(LME_EINVAL, "instance %d: H_ctrl is NULL", b);
+    if (n_e > 0 && !I.E) return fail(LME_EINVAL, "instance %d: E is NULL", b);
+    Sparse H, tmp;
+    int rc = check_csr(I.H0, n, "H0", b, &H);
+    if (rc) return rc;
+    std::vector<Sparse> Hc(n_ctrl), C(I.n_c), E(n_e);
+    for (int j = 0; j < n_ctrl; ++j)
+      if ((rc = check_csr(&I.H_ctrl[j], n, "H_ctrl", b, &Hc[j]))) return rc;
+    for (int k = 0; k < I.n_c; ++k)
+      if ((rc = check_csr(&I.C[k], n, "C", b, &C[k]))) return rc;
+    for (int m = 0; m < n_e; ++m)
+      if ((rc = check_csr(&I.E[m], n, "E", b, &E[m]))) return rc;
+
+    // A0 = -i H0 - 1/2 sum_k C_k^+ C_k ;  B_j = -i H_j
+    Sparse A(n);
+    A.axpy(cd(0.0, -1.0), H);
+    for (auto &c : C) A.axpy(cd(-0.5, 0.0), dag_times_self(c));
+    A.finalize();
+    std::vector<Sparse> B(n_ctrl, Sparse(n)), Bt, Ct;
+    for (int j = 0; j < n_ctrl; ++j) {
+      B[j].axpy(cd(0.0, -1.0), Hc[j]);
+      B[j].finalize();
+      Bt.push_back(B[j].dagger());
+    }
+    for (auto &c : C) Ct.push_back(c.dagger());
+    Sparse At = A.dagger();
+    for (auto *S : {&A, &At}) {
+      if (S->width_offdiag() > lme::kMaxWidth)
+        return fail(LME_ENOTSUP, "instance %d: operator row wider than %d", b, lme::kMaxWidth);
+    }
+    for (auto &c : C)
+      if (c.width() > lme::kMaxWidth || c.dagger().width() > lme::kMaxWidth)
+        return fail(LME_ENOTSUP, "instance %d: collapse operator row wider than %d", b, lme::kMaxWidth);
+    for (auto &x : B)
+      if (x.width_offdiag() > lme::kMaxWidth || x.dagger().width_offdiag() > lme::kMaxWidth)
+        return fail(LME_ENOTSUP, "instance %d: control operator row wider than %d", b, lme::kMaxWidth);
+
+    InstDesc &d = h->inst[b];
+    std::vector<uint8_t> fb = make_blob(A, B, C, &d.fwd);
+    std::vector<uint8_t> ab = make_blob(At, Bt, Ct, &d.adj);
+    d.n = n;
+    d.fwd_bytes = (int32_t)fb.size();
+    d.adj_bytes = (int32_t)ab.size();
+    d.ops_off = (int64_t)ops.size();
+    d.adj_off = (int64_t)adj.size();
+    ops.insert(ops.end(), fb.begin(), fb.end());
+    adj.insert(adj.end(), ab.begin(), ab.end());
+
+    // expectation operators: full ELL, Ecol[m][we][n], Eval[m][we][n]
+    int we = 1;
+    for (auto &e : E) we = std::max(we, e.width());
+    if (we > lme::kMaxWidth) return fail(LME_ENOTSUP, "instance %d: e-op row wider than %d", b, lme::kMaxWidth);
+    d.we = we;
+    d.eops_off = (int64_t)eops.size();
+    std::vector<uint8_t> eb((size_t)lme::eops_bytes(n, we, n_e), 0);
+    for (int m = 0; m < n_e; ++m) {
+      Ell e = to_ell(E[m], we, false);
+      std::memcpy(eb.data() + 4 * (size_t)m * we * n, e.col.data(), e.col.size() * 4);
+      std::memcpy(eb.data() + lme::eops_val_offset(n, we, n_e) + 16 * (size_t)m * we * n,
+                  e.val.data(), e.val.size() * 16);
+    }
+    eb.resize((size_t)lme::align16((int32_t)eb.size()));
+    eops.insert(eops.end(), eb.begin(), eb.end());
+
+    d.rho_off = h->state_elems;
+    h->offsets[b] = h->state_elems;
+    h->dims[b] = n;
+    h->state_elems += (int64_t)n * n;
+  }
+
+  h->ops.swap(ops);
+  h->adj.swap(adj);
+  h->eops.swap(eops);
+  if (n_ctrl > 0 && n_seg > 0) {
+    h->u_default.assign((size_t)n_inst * n_ctrl * n_seg, 0.0);
+    if (u_host) std::memcpy(h->u_default.data(), u_host, h->u_default.size() * sizeof(double));
+  }
+  *out = guard.release();
+  return LME_OK;
+}
+
+extern "C" int lme_create_batch(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
+                                int32_t n_e, const lme_segments *seg, const double *u_host,
+                                lme_handle *out) {
+  try {
+    return create_impl(n_inst, inst, n_ctrl, n_e, seg, u_host, out);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+extern "C" int lme_create(const lme_csr *H0, int32_t n_ctrl, const lme_csr *H_ctrl,
+                          const lme_segments *seg, const double *u_host, int32_t n_c,
+                          const lme_csr *C, int32_t n_e, const lme_csr *E, lme_handle *out) {
+  lme_instance I;
+  I.H0 = H0;
+  I.H_ctrl = H_ctrl;
+  I.n_c = n_c;
+  I.C = C;
+  I.E = E;
+  return lme_create_batch(1, &I, n_ctrl, n_e, seg, u_host, out);
+}
+
+extern "C" void lme_destroy(lme_handle h) { delete h; }
+
+extern "C" int lme_layout(lme_handle h, int32_t *n_inst, int64_t *state_elems,
+                          int64_t *offsets, int32_t *dims) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (n_inst) *n_inst = h->n_inst;
+  if (state_elems) *state_elems = h->state_elems;
+  if (offsets) std::memcpy(offsets, h->offsets.data(), h->offsets.size() * sizeof(int64_t));
+  if (dims) std::memcpy(dims, h->dims.data(), h->dims.size() * sizeof(int32_t));
+  return LME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// first device use: bind the current device and upload the operator pools
+// ---------------------------------------------------------------------------
+static int ensure_device(lme_ctx *h) {
+  hipError_t e;
+  if (h->on_device) {
+    e = hipSetDevice(h->device);
+    return e == hipSuccess ? LME_OK : hip_fail(e, "hipSetDevice");
+  }
+  e = hipGetDevice(&h->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  int lds = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS)");
+  h->lds_limit = lds;
+  int rc;
+  if ((rc = h->d_inst.upload(h->inst.data(), h->inst.size() * sizeof(InstDesc), "instances"))) return rc;
+  if ((rc = h->d_ops.upload(h->ops.data(), h->ops.size(), "op pool"))) return rc;
+  if ((rc = h->d_adj.upload(h->adj.data(), h->adj.size(), "adjoint op pool"))) return rc;
+  if ((rc = h->d_eops.upload(h->eops.data(), h->eops.size(), "e-op pool"))) return rc;
+  if (!h->u_default.empty() &&
+      (rc = h->d_u.upload(h->u_default.data(), h->u_default.size() * sizeof(double), "controls")))
+    return rc;
+  h->on_device = true;
+  return LME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planning: group instances by operator signature, fill packs
+// ---------------------------------------------------------------------------
+static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, Plan **out) {
+  for (Plan *p : h->plans)
+    if (p->T == T && p->EPT == EPT && p->adjoint == adjoint && p->cap == cap) {
+      *out = p;
+      return LME_OK;
+    }
+  auto key = [&](const InstDesc &d) {
+    const lme::Signature &s = adjoint ? d.adj : d.fwd;
+    return std::make_tuple(s.n, s.wo, s.nb, s.wb, s.nc, s.wc);
+  };
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int32_t>> groups;
+  for (int b = 0; b < h->n_inst; ++b) groups[key(h->inst[b])].push_back(b);
+
+  std::unique_ptr<Plan> p(new Plan);
+  p->T = T;
+  p->EPT = EPT;
+  p->adjoint = adjoint;
+  p->cap = cap;
+  for (auto &g : groups) {
+    const InstDesc &d0 = h->inst[g.second[0]];
+    const lme::Signature &s = adjoint ? d0.adj : d0.fwd;
+    const int blob = adjoint ? d0.adj_bytes : d0.fwd_bytes;
+    const int n2 = s.n * s.n;
+    // at most kMaxPack instances (the kernels encode the pack slot in 10 bits)
+    int64_t m_max = std::min<int64_t>(cap / n2, lme::kMaxPack);
+    const int64_t per_inst = 16LL * n2 + blob + 8LL * s.nb + 12;
+    m_max = std::min<int64_t>(m_max, std::max<int64_t>(0, (h->lds_limit - 48) / per_inst));
+    while (m_max > 0 && lme_internal_pack_lds_bytes(s.n, (int)m_max, blob, s.nb) > h->lds_limit)
+      --m_max;
+    if (m_max < 1)
+      return fail(LME_ENOTSUP, "instance of dimension %d does not fit a resident workgroup "
+                  "(%d elements, %d B LDS available)", s.n, cap, h->lds_limit);
+    const int cnt = (int)g.second.size();
+    const int n_packs = (int)((cnt + m_max - 1) / m_max);
+    // spread the group evenly over its packs
+    int done = 0;
+    for (int q = 0; q < n_packs; ++q) {
+      const int m = (cnt - done + (n_packs - q) - 1) / (n_packs - q);
+      PackDesc pk;
+      pk.first = (int32_t)p->order.size();
+      pk.m = m;
+      pk.n = s.n;
+      pk.wo = s.wo;
+      pk.nb = s.nb;
+      pk.wb = s.wb;
+      pk.nc = s.nc;
+      pk.wc = s.wc;
+      pk.blob_bytes = blob;
+      pk.lds_bytes = lme_internal_pack_lds_bytes(s.n, m, blob, s.nb);
+      for (int r = 0; r < m; ++r) p->order.push_back(g.second[done + r]);
+      done += m;
+      p->packs.push_back(pk);
+      p->max_lds = std::max(p->max_lds, pk.lds_bytes);
+    }
+  }
+  // largest work first: the hardware dispatches workgroups roughly in order
+  std::stable_sort(p->packs.begin(), p->packs.end(), [](const PackDesc &a, const PackDesc &b) {
+    return (int64_t)a.m * a.n * a.n > (int64_t)b.m * b.n * b.n;
+  });
+  int rc;
+  if ((rc = p->d_packs.upload(p->packs.data(), p->packs.size() * sizeof(PackDesc), "packs"))) return rc;
+  if ((rc = p->d_order.upload(p->order.data(), p->order.size() * sizeof(int32_t), "order"))) return rc;
+  *out = p.get();
+  h->plans.push_back(p.release());
+  return LME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// time grid
+// ---------------------------------------------------------------------------
+static long grid_index(double t, double t0, double h) {
+  const long m = std::lround((t - t0) / h);
+  if (std::fabs(t - (t0 + (double)m * h)) > 1e-6 * std::fabs(h)) return -1;
+  return m;
+}
+
+// Segment holding time t, or -1.
+static int segment_at(const lme_ctx *h, double t) {
+  if (h->n_seg == 0 || t < h->edges[0] || t >= h->edges[h->n_seg]) return -1;
+  const auto it = std::upper_bound(h->edges.begin(), h->edges.end(), t);
+  return (int)(it - h->edges.begin()) - 1;
+}
+
+static int check_times(int32_t n_t, const double *tlist) {
+  if (n_t < 1 || !tlist) return fail(LME_EINVAL, "need n_t >= 1 output times");
+  for (int k = 0; k < n_t; ++k)
+    if (!std::isfinite(tlist[k])) return fail(LME_EINVAL, "tlist[%d] is not finite", k);
+  for (int k = 1; k < n_t; ++k)
+    if (!(tlist[k] > tlist[k - 1])) return fail(LME_EINVAL, "tlist must be strictly increasing");
+  return LME_OK;
+}
+
+// Builds [seg_of_step[nsteps] | out_step[n_t]] (host only, validates the grid).
+static int rk4_tables(const lme_ctx *h, int32_t n_t, const double *tlist, int32_t nsteps,
+                      double hstep, std::vector<int32_t> *out) {
+  std::vector<int32_t> tab((size_t)nsteps + n_t);
+  const double t0 = tlist[0];
+  tab[nsteps] = 0;
+  for (int k = 1; k < n_t; ++k) {
+    const long m = grid_index(tlist[k], t0, hstep);
+    if (m < 0 || m > nsteps)
+      return fail(LME_EGRID, "output time %.17g is not on the RK4 grid (h = %.17g)", tlist[k], hstep);
+    tab[nsteps + k] = (int32_t)m;
+  }
+  if (n_t > 1 && tab[nsteps + n_t - 1] != nsteps)
+    return fail(LME_EGRID, "last output time is not the end of the grid");
+  const double t1 = tlist[n_t - 1];
+  for (int q = 0; q <= h->n_seg && h->n_seg > 0; ++q) {
+    const double e = h->edges[q];
+    if (e > t0 && e < t1 && grid_index(e, t0, hstep) < 0)
+      return fail(LME_EGRID, "control edge %.17g is not on the RK4 grid", e);
+  }
+  for (int st = 0; st < nsteps; ++st) tab[st] = segment_at(h, t0 + ((double)st + 0.5) * hstep);
+  out->swap(tab);
+  return LME_OK;
+}
+
+// Uploads the step tables unless the previous call used identical ones.
+static int upload_tables(lme_ctx *h, std::vector<int32_t> &tab, hipStream_t s) {
+  if (tab == h->steps_key && h->d_steps.p) return LME_OK;
+  h->d_steps.release();
+  hipError_t e = hipMalloc(&h->d_steps.p, tab.size() * sizeof(int32_t));
+  if (e != hipSuccess) {
+    h->d_steps.p = nullptr;
+    return hip_fail(e, "hipMalloc(step tables)");
+  }
+  h->d_steps.bytes = tab.size() * sizeof(int32_t);
+  e = hipMemcpyAsync(h->d_steps.p, tab.data(), h->d_steps.bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "upload step tables");
+  h->steps_key.swap(tab);
+  return LME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// evolve
+// ---------------------------------------------------------------------------
+static int pick_rk4_config(const lme_ctx *h, int block, int *T, int *EPT) {
+  int max_n2 = 0;
+  for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
+  int Ts[64], Es[64];
+  const int nc = lme_internal_rk4_configs(Ts, Es, 64);
+  const int want_T = block > 0 ? block : 512;
+  int best = -1;
+  for (int i = 0; i < nc; ++i)
+    if (Ts[i] == want_T && Ts[i] * Es[i] >= max_n2 && (best < 0 || Es[i] < Es[best])) best = i;
+  if (best < 0 && block <= 0)  // any block size that fits
+    for (int i = 0; i < nc; ++i)
+      if (Ts[i] * Es[i] >= max_n2 && (best < 0 || Ts[i] * Es[i] < Ts[best] * Es[best])) best = i;
+  if (best < 0)
+    return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the resident RK4 "
+                "workgroup capacity for block %d", max_n2, want_T);
+  *T = Ts[best];
+  *EPT = Es[best];
+  return LME_OK;
+}
+
+static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
+                       const void *rho0_dev, const double *u_dev, void *expect_dev,
+                       void *states_dev, void *rho_out_dev, int64_t *counts_dev,
+                       int32_t *status_dev, void *stream) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (!opt) return fail(LME_EINVAL, "options are NULL");
+  if (!rho0_dev) return fail(LME_EINVAL, "rho0 is NULL");
+  int rc = check_times(n_t, tlist);
+  if (rc) return rc;
+  if (opt->path < LME_PATH_AUTO || opt->path > LME_PATH_STREAMED)
+    return fail(LME_EINVAL, "unknown path %d", opt->path);
+  if (opt->block != 0 && opt->block != 256 && opt->block != 512 && opt->block != 1024)
+    return fail(LME_EINVAL, "block must be 0, 256, 512 or 1024");
+  if (opt->method == LME_DOPRI5)
+    return fail(LME_ENOTSUP, "adaptive stepping is not available in this build");
+  if (opt->method != LME_RK4) return fail(LME_EINVAL, "unknown method %d", opt->method);
+  if (n_t > 1 && opt->nsteps < 1) return fail(LME_EINVAL, "RK4 needs nsteps >= 1");
+  if (opt->path == LME_PATH_STREAMED)
+    return fail(LME_ENOTSUP, "the streamed RK4 path is not available in this build");
+  const int32_t nsteps = n_t > 1 ? opt->nsteps : 0;
+  const double hstep = n_t > 1 ? (tlist[n_t - 1] - tlist[0]) / nsteps : 0.0;
+  std::vector<int32_t> tab;
+  if ((rc = rk4_tables(h, n_t, tlist, nsteps, hstep, &tab))) return rc;
+  int T, EPT;
+  if ((rc = pick_rk4_config(h, opt->block, &T, &EPT))) return rc;
+
+  // validation done: from here on the device is used
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = ensure_device(h))) return rc;
+  if ((rc = upload_tables(h, tab, s))) return rc;
+  hipError_t e;
+  Plan *plan;
+  if ((rc = plan_packs(h, T, EPT, 0, T * EPT, &plan))) return rc;
+
+  lme::Rk4Args a;
+  std::memset(&a, 0, sizeof a);
+  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
+  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+  a.ops = static_cast<const uint8_t *>(h->d_ops.p);
+  a.adjoint = 0;
+  a.eops = static_cast<const uint8_t *>(h->d_eops.p);
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_ctrl = h->n_ctrl;
+  a.n_seg = h->n_seg;
+  a.n_e = h->n_e;
+  a.n_t = n_t;
+  a.seg_of_step = static_cast<const int32_t *>(h->d_steps.p);
+  a.out_step = static_cast<const int32_t *>(h->d_steps.p) + nsteps;
+  a.nsteps = nsteps;
+  a.h = hstep;
+  a.state_elems = h->state_elems;
+  a.rho0 = static_cast<const double *>(rho0_dev);
+  a.rho_out = static_cast<double *>(rho_out_dev);
+  a.states = static_cast<double *>(states_dev);
+  a.expect = static_cast<double *>(expect_dev);
+  a.counts = counts_dev;
+  a.status = status_dev;
+  e = lme_internal_launch_rk4(T, EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
+  if (e != hipSuccess) return hip_fail(e, "launch resident RK4");
+  return LME_OK;
+}
+
+extern "C" int lme_evolve(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
+                          const void *rho0_dev, const double *u_dev, void *expect_dev,
+                          void *states_dev, void *rho_out_dev, int64_t *counts_dev,
+                          int32_t *status_dev, void *stream) {
+  try {
+    return evolve_impl(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
+                       counts_dev, status_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// single application
+// ---------------------------------------------------------------------------
+static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, const double *u_dev,
+                      const void *y_dev, void *out_dev, void *stream) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (!y_dev || !out_dev) return fail(LME_EINVAL, "y and out must be device pointers");
+  if (y_dev == out_dev) return fail(LME_EINVAL, "y and out must not overlap");
+  if (!std::isfinite(t)) return fail(LME_EINVAL, "t is not finite");
+  if (form != LME_FORM_OPERATOR && form != LME_FORM_SUPEROP)
+    return fail(LME_EINVAL, "unknown form %d", form);
+  if (form == LME_FORM_SUPEROP)
+    return fail(LME_ENOTSUP, "the superoperator form is not available in this build");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  hipError_t e;
+  Plan *plan;
+  rc = plan_packs(h, 256, 0, adjoint ? 1 : 0, 1 << 30, &plan);
+  if (rc) return rc;
+  lme::ApplyArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
+  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+  a.adjoint = adjoint ? 1 : 0;
+  a.ops = static_cast<const uint8_t *>(adjoint ? h->d_adj.p : h->d_ops.p);
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_ctrl = h->n_ctrl;
+  a.n_seg = h->n_seg;
+  a.seg = segment_at(h, t);
+  a.y = static_cast<const double *>(y_dev);
+  a.out = static_cast<double *>(out_dev);
+  e = lme_internal_launch_apply_lds(&a, (int)plan->packs.size(), plan->max_lds, s);
+  if (e != hipSuccess) return hip_fail(e, "launch apply");
+  return LME_OK;
+}
+
+extern "C" int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
+                         const double *u_dev, const void *y_dev, void *out_dev, void *stream) {
+  try {
+    return apply_impl(h, form, adjoint, t, u_dev, y_dev, out_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}

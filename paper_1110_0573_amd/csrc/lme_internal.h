@@ -1,0 +1,132 @@
+// lme_internal.h -- data layout shared by the host planner and the gfx950
+// kernels of the Lindblad library.  Not part of the public ABI.
+//
+// Operator form of the Liouvillian (Eq. (master_equation), hbar = 1):
+//   L y = A y + y A^+ + sum_k C_k y C_k^+ ,   A = -i H - 1/2 sum_k C_k^+ C_k,
+// with H = H0 + sum_j u_j H_j, so A = A0 + sum_j u_j B_j, B_j = -i H_j.
+// The adjoint L^+ x = A^+ x + x A + sum_k C_k^+ x C_k has the same shape with
+// (A, B_j, C_k) replaced by (A^+, B_j^+, C_k^+); one kernel serves both.
+//
+// Each instance's operators are packed into one byte blob ("op blob") that a
+// workgroup copies verbatim into LDS:
+//   D     [n]          complex  diagonal of A0
+//   Oval  [wo][n]      complex  off-diagonal entries of A0, ELL, slot-major
+//   Ocol  [wo][n]      int32    their columns (padding: col = row, val = 0)
+//   Jval  [nc][wc][n]  complex  every entry of C_k, ELL
+//   Jcol  [nc][wc][n]  int32
+//   DB    [nb][n]      complex  diagonal of B_j
+//   OBval [nb][wb][n]  complex  off-diagonal of B_j, ELL
+//   OBcol [nb][wb][n]  int32
+// Sections start on 16-byte boundaries.  ELL slot-major order puts rows i and
+// i+1 of one slot next to each other, so a wave reading consecutive rows
+// reads consecutive addresses.
+#pragma once
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#define LME_HD __host__ __device__
+#else
+#define LME_HD
+#endif
+
+namespace lme {
+
+constexpr int kMaxWidth = 64;       // max non-zeros per operator row
+constexpr int kMaxDim = 4096;
+constexpr int kMaxPack = 1023;   // instances per resident pack (10-bit slot field)
+
+LME_HD inline int32_t align16(int32_t x) { return (x + 15) & ~15; }
+
+struct BlobLayout {
+  int32_t n, wo, nb, wb, nc, wc;
+  int32_t offD, offOval, offOcol, offJval, offJcol, offDB, offOBval, offOBcol;
+  int32_t bytes;
+};
+
+LME_HD inline BlobLayout blob_layout(int32_t n, int32_t wo, int32_t nb, int32_t wb,
+                                     int32_t nc, int32_t wc) {
+  BlobLayout L;
+  L.n = n; L.wo = wo; L.nb = nb; L.wb = wb; L.nc = nc; L.wc = wc;
+  int32_t o = 0;
+  L.offD = o;     o = align16(o + 16 * n);
+  L.offOval = o;  o = align16(o + 16 * wo * n);
+  L.offOcol = o;  o = align16(o + 4 * wo * n);
+  L.offJval = o;  o = align16(o + 16 * nc * wc * n);
+  L.offJcol = o;  o = align16(o + 4 * nc * wc * n);
+  L.offDB = o;    o = align16(o + 16 * nb * n);
+  L.offOBval = o; o = align16(o + 16 * nb * wb * n);
+  L.offOBcol = o; o = align16(o + 4 * nb * wb * n);
+  L.bytes = o;
+  return L;
+}
+
+// Expectation operators of one instance: Ecol[m][we][n] int32 then
+// Eval[m][we][n] complex (ELL of every entry, padding val = 0, col = row).
+LME_HD inline int64_t eops_val_offset(int32_t n, int32_t we, int32_t n_e) {
+  return align16(4 * n_e * we * n);
+}
+LME_HD inline int64_t eops_bytes(int32_t n, int32_t we, int32_t n_e) {
+  return eops_val_offset(n, we, n_e) + 16LL * n_e * we * n;
+}
+
+// Operator signature: instances sharing it have identically laid-out blobs.
+struct Signature {
+  int32_t n, wo, nb, wb, nc, wc;
+};
+
+struct InstDesc {
+  int64_t rho_off;    // complex elements into the packed state
+  int64_t ops_off;    // bytes into the forward op pool
+  int64_t adj_off;    // bytes into the adjoint op pool
+  int64_t eops_off;   // bytes into the expectation-op pool
+  int32_t n, we;      // dimension, expectation-op ELL width
+  Signature fwd, adj;
+  int32_t fwd_bytes, adj_bytes;
+};
+
+// A pack: m instances with one signature, integrated by one workgroup.
+struct PackDesc {
+  int32_t first;      // index into the instance order array
+  int32_t m;          // instances in the pack
+  int32_t n, wo, nb, wb, nc, wc;
+  int32_t blob_bytes; // per instance
+  int32_t lds_bytes;  // total dynamic LDS this pack needs
+};
+
+// Per-call arguments of the resident RK4 kernel.
+struct Rk4Args {
+  const PackDesc *packs;
+  const int32_t *order;     // pack slot -> instance index
+  const InstDesc *inst;
+  const uint8_t *ops;       // op pool (forward or adjoint)
+  int32_t adjoint;          // use adj_off instead of ops_off
+  const uint8_t *eops;
+  const double *u;          // [n_inst][n_ctrl][n_seg] or null
+  int32_t n_ctrl, n_seg, n_e, n_t;
+  const int32_t *seg_of_step;  // [nsteps] segment index or -1
+  const int32_t *out_step;     // [n_t] step index after which output k is due
+  int32_t nsteps;
+  double h;
+  int64_t state_elems;
+  const double *rho0;       // complex128 packed (interleaved)
+  double *rho_out;
+  double *states;           // [n_t][state_elems]
+  double *expect;           // [n_inst][n_e][n_t]
+  int64_t *counts;          // [n_inst][2]
+  int32_t *status;          // [n_inst]
+};
+
+// Per-call arguments of the one-shot Liouvillian application.
+struct ApplyArgs {
+  const PackDesc *packs;
+  const int32_t *order;
+  const InstDesc *inst;
+  const uint8_t *ops;
+  int32_t adjoint;
+  const double *u;
+  int32_t n_ctrl, n_seg, seg;
+  const double *y;
+  double *out;
+};
+
+}  // namespace lme

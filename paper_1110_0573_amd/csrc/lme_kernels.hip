@@ -1,0 +1,420 @@
+// lme_kernels.hip -- gfx950 kernels of the Lindblad library.
+//
+// All arithmetic is FP64 complex.  The Liouvillian is applied in operator
+// form (Eq. (master_equation), hbar = 1):
+//   k_ij = (A y + y A^+ + sum_k C_k y C_k^+)_ij
+//        = (D_i + conj(D_j)) y_ij
+//          + sum_w O_iw y[col_iw][j] + sum_w conj(O_jw) y[i][col_jw]
+//          + sum_q u_q (same three terms for B_q = -i H_q)
+//          + sum_k sum_{w,v} J_kiw conj(J_kjv) y[col_kiw][col_kjv]
+// where A = D + O (diagonal + off-diagonal ELL).  Every term is a gather from
+// the stage input y, which the resident kernels keep in LDS.
+#include <hip/hip_runtime.h>
+
+#include "lme_internal.h"
+
+namespace lme {
+
+// ---------------------------------------------------------------------------
+// complex helpers (double2 = re, im)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// c + a * b
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+// c + conj(a) * b
+__device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+// c + s * a  (s real)
+__device__ __forceinline__ double2 caxpy(double s, double2 a, double2 c) {
+  return make_double2(fma(s, a.x, c.x), fma(s, a.y, c.y));
+}
+__device__ __forceinline__ bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+// ---------------------------------------------------------------------------
+// operator view of one instance's op blob
+// ---------------------------------------------------------------------------
+struct OpView {
+  const double2 *D, *Oval, *Jval, *DB, *OBval;
+  const int32_t *Ocol, *Jcol, *OBcol;
+  int n, wo, nb, wb, nc, wc;
+};
+
+__device__ __forceinline__ OpView make_view(const uint8_t *blob, const BlobLayout &L) {
+  OpView v;
+  v.D = reinterpret_cast<const double2 *>(blob + L.offD);
+  v.Oval = reinterpret_cast<const double2 *>(blob + L.offOval);
+  v.Ocol = reinterpret_cast<const int32_t *>(blob + L.offOcol);
+  v.Jval = reinterpret_cast<const double2 *>(blob + L.offJval);
+  v.Jcol = reinterpret_cast<const int32_t *>(blob + L.offJcol);
+  v.DB = reinterpret_cast<const double2 *>(blob + L.offDB);
+  v.OBval = reinterpret_cast<const double2 *>(blob + L.offOBval);
+  v.OBcol = reinterpret_cast<const int32_t *>(blob + L.offOBcol);
+  v.n = L.n; v.wo = L.wo; v.nb = L.nb; v.wb = L.wb; v.nc = L.nc; v.wc = L.wc;
+  return v;
+}
+
+// (A y + y A^+)_ij restricted to a diagonal + ELL operator (D, Oval, Ocol).
+__device__ __forceinline__ double2 two_sided(const double2 *D, const double2 *Oval,
+                                             const int32_t *Ocol, int wo, int n,
+                                             const double2 *Y, int i, int j, double2 yij) {
+  double2 acc = cmul(cadd(D[i], cconj(D[j])), yij);
+  for (int w = 0; w < wo; ++w) {
+    const int c = Ocol[w * n + i];
+    acc = cfma(Oval[w * n + i], Y[c * n + j], acc);
+  }
+  for (int w = 0; w < wo; ++w) {
+    const int c = Ocol[w * n + j];
+    acc = cfma_conj(Oval[w * n + j], Y[i * n + c], acc);
+  }
+  return acc;
+}
+
+// Element (i, j) of L y for one instance; Y is that instance's n x n stage
+// input, uq its nb control amplitudes for the current step.
+__device__ __forceinline__ double2 lindblad_elem(const OpView &op, const double2 *Y,
+                                                 int i, int j, double2 yij,
+                                                 const double *uq) {
+  const int n = op.n;
+  double2 acc = two_sided(op.D, op.Oval, op.Ocol, op.wo, n, Y, i, j, yij);
+  for (int q = 0; q < op.nb; ++q) {
+    const double u = uq[q];
+    if (u != 0.0) {
+      const double2 t = two_sided(op.DB + q * n, op.OBval + q * op.wb * n,
+                                  op.OBcol + q * op.wb * n, op.wb, n, Y, i, j, yij);
+      acc = caxpy(u, t, acc);
+    }
+  }
+  for (int k = 0; k < op.nc; ++k) {
+    const double2 *Jv = op.Jval + k * op.wc * n;
+    const int32_t *Jc = op.Jcol + k * op.wc * n;
+    for (int w = 0; w < op.wc; ++w) {
+      const double2 vi = Jv[w * n + i];
+      const int ci = Jc[w * n + i];
+      for (int v = 0; v < op.wc; ++v) {
+        const double2 p = cmul(vi, cconj(Jv[v * n + j]));
+        acc = cfma(p, Y[ci * n + Jc[v * n + j]], acc);
+      }
+    }
+  }
+  return acc;
+}
+
+// Copies the m op blobs of a pack into LDS (16-byte vector copies).
+__device__ __forceinline__ void stage_blobs(uint8_t *dst, const PackDesc &pk,
+                                            const int32_t *order, const InstDesc *inst,
+                                            const uint8_t *pool, int adjoint) {
+  const int nvec = pk.blob_bytes / 16;
+  const int total = pk.m * nvec;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int b = idx / nvec, r = idx - b * nvec;
+    const InstDesc &d = inst[order[pk.first + b]];
+    const uint4 *src = reinterpret_cast<const uint4 *>(pool + (adjoint ? d.adj_off : d.ops_off));
+    reinterpret_cast<uint4 *>(dst + (size_t)b * pk.blob_bytes)[r] = src[r];
+  }
+}
+
+// Deterministic butterfly sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+// LDS carve-up of a pack:
+//   Y [E] | blobs [m][blob_bytes] | u [m][nb] | state offsets [m] | ids [m]
+struct PackLds {
+  double2 *Y;
+  uint8_t *blobs;
+  double *u;
+  int64_t *off;
+  int32_t *ids;
+};
+
+__host__ __device__ inline int32_t pack_lds_bytes(int32_t n, int32_t m, int32_t blob_bytes,
+                                                  int32_t nb) {
+  return align16(16 * m * n * n) + m * blob_bytes + align16(8 * m * nb) + align16(8 * m) +
+         align16(4 * m);
+}
+
+__device__ __forceinline__ PackLds carve(uint8_t *smem, const PackDesc &pk) {
+  PackLds p;
+  const int E = pk.m * pk.n * pk.n;
+  p.Y = reinterpret_cast<double2 *>(smem);
+  p.blobs = smem + align16(16 * E);
+  p.u = reinterpret_cast<double *>(p.blobs + (size_t)pk.m * pk.blob_bytes);
+  p.off = reinterpret_cast<int64_t *>(reinterpret_cast<uint8_t *>(p.u) + align16(8 * pk.m * pk.nb));
+  p.ids = reinterpret_cast<int32_t *>(reinterpret_cast<uint8_t *>(p.off) + align16(8 * pk.m));
+  return p;
+}
+
+// Slot coordinates packed in one register: instance-in-pack (10 bits), row
+// and column (11 bits each).  Resident packs hold at most 8192 elements.
+__device__ __forceinline__ uint32_t pack_bij(int b, int i, int j) {
+  return ((uint32_t)b << 22) | ((uint32_t)i << 11) | (uint32_t)j;
+}
+__device__ __forceinline__ int slot_b(uint32_t v) { return (int)(v >> 22); }
+__device__ __forceinline__ int slot_i(uint32_t v) { return (int)((v >> 11) & 2047u); }
+__device__ __forceinline__ int slot_j(uint32_t v) { return (int)(v & 2047u); }
+
+// ---------------------------------------------------------------------------
+// Resident fixed-step RK4: one workgroup integrates one pack for all steps.
+// Thread t owns pack elements f = t + s*T (s < EPT); its rho, the RK4
+// accumulator and the next stage input stay in VGPRs; the current stage
+// input is shared through LDS.  Two barriers per stage, none across
+// workgroups.
+// ---------------------------------------------------------------------------
+template <int T>
+__device__ void write_outputs(const Rk4Args &a, const PackDesc &pk, const PackLds &L,
+                              int k) {
+  const int n = pk.n, n2 = n * n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ntask = pk.m * a.n_e;
+  for (int task = wave; task < ntask; task += T / 64) {
+    const int b = task / a.n_e, e = task - b * a.n_e;
+    const int id = L.ids[b];
+    const InstDesc &d = a.inst[id];
+    const int we = d.we;
+    const int32_t *Ec = reinterpret_cast<const int32_t *>(a.eops + d.eops_off);
+    const double2 *Ev = reinterpret_cast<const double2 *>(
+        a.eops + d.eops_off + eops_val_offset(n, we, a.n_e));
+    const double2 *Y = L.Y + b * n2;
+    double2 part = make_double2(0.0, 0.0);
+    for (int i = lane; i < n; i += 64)
+      for (int w = 0; w < we; ++w) {
+        const int idx = (e * we + w) * n + i;
+        part = cfma(Ev[idx], Y[Ec[idx] * n + i], part);
+      }
+    part = wave_sum(part);
+    if (lane == 0) {
+      double *dst = a.expect + 2 * (((int64_t)id * a.n_e + e) * a.n_t + k);
+      dst[0] = part.x;
+      dst[1] = part.y;
+      if (!cfinite(part) && a.status) a.status[id] = 5;  // LME_ENONFINITE
+    }
+  }
+}
+
+template <int T, int EPT>
+__global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, E = pk.m * n2;
+  const PackLds L = carve(smem, pk);
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  const int tid = threadIdx.x;
+
+  for (int b = tid; b < pk.m; b += T) {
+    const int id = a.order[pk.first + b];
+    L.ids[b] = id;
+    L.off[b] = a.inst[id].rho_off;
+    if (a.status) a.status[id] = 0;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
+  __syncthreads();
+
+  double2 rho[EPT], acc[EPT], yn[EPT];
+  uint32_t bij[EPT];
+  const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int f = tid + s * T;
+    rho[s] = make_double2(0.0, 0.0);
+    bij[s] = 0;
+    if (f < E) {
+      const int b = f / n2, r = f - b * n2;
+      const int i = r / n;
+      bij[s] = pack_bij(b, i, r - i * n);
+      rho[s] = rho0[L.off[b] + r];
+    }
+  }
+
+  const bool want_expect = a.expect != nullptr && a.n_e > 0;
+  int next_out = 0;
+  const double h = a.h;
+  for (int st = 0;; ++st) {
+    // outputs due after st steps (st = 0: the initial state)
+    while (next_out < a.n_t && a.out_step[next_out] == st) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        const int f = tid + s * T;
+        if (f < E) {
+          L.Y[f] = rho[s];
+          if (a.states) {
+            const uint32_t v = bij[s];
+            const int64_t g = L.off[slot_b(v)] + slot_i(v) * n + slot_j(v);
+            reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems + g] = rho[s];
+          }
+        }
+      }
+      __syncthreads();
+      if (want_expect) write_outputs<T>(a, pk, L, next_out);
+      ++next_out;
+    }
+    if (st == a.nsteps) break;
+
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      yn[s] = rho[s];
+      acc[s] = make_double2(0.0, 0.0);
+    }
+    for (int stage = 0; stage < 4; ++stage) {
+      // RK4 tableau: stage inputs rho + c*h*k_prev, weights 1, 2, 2, 1
+      const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
+      const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+      __syncthreads();  // every reader of the previous stage input is done
+      if (stage == 0 && pk.nb > 0) {
+        const int seg = a.seg_of_step[st];
+        for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+          const int b = idx / pk.nb, q = idx - b * pk.nb;
+          L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        const int f = tid + s * T;
+        if (f < E) L.Y[f] = yn[s];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        const int f = tid + s * T;
+        if (f < E) {
+          uint32_t v = bij[s];
+          // opaque to the optimiser: stops per-slot addresses from being
+          // hoisted out of the step loop (which costs ~20 VGPRs per slot)
+          asm volatile("" : "+v"(v));
+          const int b = slot_b(v);
+          const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+          const double2 kv =
+              lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), yn[s], L.u + b * pk.nb);
+          acc[s] = caxpy(wgt, kv, acc[s]);
+          yn[s] = caxpy(cnext, kv, rho[s]);
+        }
+        // keep one slot's temporaries live at a time
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) rho[s] = caxpy(h / 6.0, acc[s], rho[s]);
+  }
+
+  if (a.rho_out) {
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      const int f = tid + s * T;
+      if (f < E) {
+        const uint32_t v = bij[s];
+        reinterpret_cast<double2 *>(a.rho_out)[L.off[slot_b(v)] + slot_i(v) * n + slot_j(v)] =
+            rho[s];
+      }
+    }
+  }
+  if (a.counts)
+    for (int b = tid; b < pk.m; b += T) {
+      a.counts[2 * (int64_t)L.ids[b]] = a.nsteps;
+      a.counts[2 * (int64_t)L.ids[b] + 1] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One application of L (or L^+) to every instance, stage input in LDS.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(T) void apply_lds_kernel(ApplyArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, E = pk.m * n2;
+  const PackLds L = carve(smem, pk);
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  for (int b = threadIdx.x; b < pk.m; b += T) {
+    L.ids[b] = a.order[pk.first + b];
+    L.off[b] = a.inst[L.ids[b]].rho_off;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < pk.m * pk.nb; idx += T) {
+    const int b = idx / pk.nb, q = idx - b * pk.nb;
+    L.u[idx] = a.seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + a.seg] : 0.0;
+  }
+  for (int f = threadIdx.x; f < E; f += T) {
+    const int b = f / n2;
+    L.Y[f] = reinterpret_cast<const double2 *>(a.y)[L.off[b] + (f - b * n2)];
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < E; f += T) {
+    const int b = f / n2, r = f - b * n2;
+    const int i = r / n, j = r - i * n;
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+    const double2 kv = lindblad_elem(op, L.Y + b * n2, i, j, L.Y[f], L.u + b * pk.nb);
+    reinterpret_cast<double2 *>(a.out)[L.off[b] + r] = kv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int T, int EPT>
+static hipError_t launch_rk4_t(const Rk4Args &a, int n_packs, int lds, hipStream_t s) {
+  auto k = rk4_resident_kernel<T, EPT>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(T), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lme
+
+// Resident RK4 configurations: threads per workgroup x elements per thread.
+extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap) {
+  static const int cfg[][2] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}, {256, 32},
+                               {512, 1}, {512, 2}, {512, 4}, {512, 8}, {512, 13}, {512, 16},
+                               {1024, 1}, {1024, 2}, {1024, 4}, {1024, 6}};
+  const int nc = (int)(sizeof(cfg) / sizeof(cfg[0]));
+  for (int i = 0; i < nc && i < cap; ++i) {
+    T[i] = cfg[i][0];
+    EPT[i] = cfg[i][1];
+  }
+  return nc;
+}
+
+extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb) {
+  return lme::pack_lds_bytes(n, m, blob_bytes, nb);
+}
+
+extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
+                                              int n_packs, int lds, hipStream_t s) {
+  using namespace lme;
+#define LME_RK4_CASE(TT, EE) \
+  if (T == TT && EPT == EE) return launch_rk4_t<TT, EE>(*a, n_packs, lds, s);
+  LME_RK4_CASE(256, 1) LME_RK4_CASE(256, 2) LME_RK4_CASE(256, 4) LME_RK4_CASE(256, 8)
+  LME_RK4_CASE(256, 16) LME_RK4_CASE(256, 32)
+  LME_RK4_CASE(512, 1) LME_RK4_CASE(512, 2) LME_RK4_CASE(512, 4) LME_RK4_CASE(512, 8)
+  LME_RK4_CASE(512, 13) LME_RK4_CASE(512, 16)
+  LME_RK4_CASE(1024, 1) LME_RK4_CASE(1024, 2) LME_RK4_CASE(1024, 4) LME_RK4_CASE(1024, 6)
+#undef LME_RK4_CASE
+  return hipErrorInvalidValue;
+}
+
+extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
+                                                    int lds, hipStream_t s) {
+  auto k = lme::apply_lds_kernel<256>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(256), lds, s, *a);
+  return hipGetLastError();
+}

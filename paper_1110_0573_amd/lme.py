@@ -1,0 +1,281 @@
+"""Thin ctypes binding of liblme.so (include/lme.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of liblme.so.  PyTorch provides device memory and the current stream.
+There is no fallback: if liblme.so is missing or no GPU is present, the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "liblme.so")
+
+LME_OK, LME_EINVAL, LME_EGRID, LME_EMAXSTEPS, LME_ESTEPUNDERFLOW, LME_ENONFINITE, \
+    LME_ENOMEM, LME_EHIP, LME_ENOTSUP = range(9)
+STATUS_NAMES = {0: "LME_OK", 1: "LME_EINVAL", 2: "LME_EGRID", 3: "LME_EMAXSTEPS",
+                4: "LME_ESTEPUNDERFLOW", 5: "LME_ENONFINITE", 6: "LME_ENOMEM",
+                7: "LME_EHIP", 8: "LME_ENOTSUP"}
+LME_RK4, LME_DOPRI5 = 0, 1
+LME_PATH_AUTO, LME_PATH_RESIDENT, LME_PATH_STREAMED = 0, 1, 2
+LME_FORM_OPERATOR, LME_FORM_SUPEROP = 0, 1
+
+# every symbol include/lme.h declares
+EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
+           "lme_last_error", "lme_layout", "lme_evolve", "lme_apply"]
+
+
+class LmeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32),
+                ("row_ptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class Instance(C.Structure):
+    _fields_ = [("H0", C.POINTER(Csr)), ("H_ctrl", C.POINTER(Csr)), ("n_c", C.c_int32),
+                ("C", C.POINTER(Csr)), ("E", C.POINTER(Csr))]
+
+
+class Segments(C.Structure):
+    _fields_ = [("n_seg", C.c_int32), ("edges", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("path", C.c_int32), ("nsteps", C.c_int32),
+                ("block", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
+                ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int64)]
+
+
+_LIB = None
+_PD = C.POINTER(C.c_double)
+
+
+def load():
+    """Loads liblme.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with "
+                               "`python -m paper_1110_0573_amd.build`")
+        lib = C.CDLL(LIBPATH)
+        H = C.c_void_p
+        lib.lme_default_options.argtypes = [C.POINTER(Options)]
+        lib.lme_default_options.restype = None
+        lib.lme_create_batch.argtypes = [C.c_int32, C.POINTER(Instance), C.c_int32, C.c_int32,
+                                         C.POINTER(Segments), _PD, C.POINTER(H)]
+        lib.lme_create.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(Csr),
+                                   C.POINTER(Segments), _PD, C.c_int32, C.POINTER(Csr),
+                                   C.c_int32, C.POINTER(Csr), C.POINTER(H)]
+        lib.lme_destroy.argtypes = [H]
+        lib.lme_destroy.restype = None
+        lib.lme_last_error.argtypes = []
+        lib.lme_last_error.restype = C.c_char_p
+        lib.lme_layout.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        lib.lme_evolve.argtypes = [H, C.POINTER(Options), C.c_int32, _PD, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.lme_apply.argtypes = [H, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc, what):
+    if rc != LME_OK:
+        raise LmeError(rc, f"{what}: {load().lme_last_error().decode()}")
+
+
+def default_options(**kw):
+    o = Options()
+    load().lme_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class _CsrKeep:
+    """Builds an lme_csr view of a scipy matrix and keeps its arrays alive."""
+
+    def __init__(self):
+        self.keep = []
+
+    def csr(self, m):
+        m = sp.csr_matrix(m, dtype=np.complex128)
+        m.sort_indices()
+        rp = np.ascontiguousarray(m.indptr, np.int32)
+        ci = np.ascontiguousarray(m.indices, np.int32)
+        va = np.ascontiguousarray(m.data, np.complex128).view(np.float64)
+        self.keep += [rp, ci, va]
+        return Csr(m.shape[0], m.nnz, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                   ci.ctypes.data_as(C.POINTER(C.c_int32)), va.ctypes.data_as(_PD))
+
+    def array(self, ops):
+        arr = (Csr * max(1, len(ops)))(*[self.csr(o) for o in ops])
+        self.keep.append(arr)
+        return arr
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Handle:
+    """A batch of systems uploaded to the current GPU (lme_create_batch).
+
+    ``systems`` is a list of objects with attributes H0, C, E and optionally
+    H_ctrl, edges, u (see :class:`paper_1110_0573_amd.systems.System`).  All
+    systems must share the number of control and expectation operators and,
+    with controls, the segment edges."""
+
+    def __init__(self, systems):
+        lib = load()
+        keep = _CsrKeep()
+        n_inst = len(systems)
+        n_ctrl = len(getattr(systems[0], "H_ctrl", []) or [])
+        n_e = len(systems[0].E)
+        edges = getattr(systems[0], "edges", None) if n_ctrl else None
+        insts = (Instance * n_inst)()
+        for b, s in enumerate(systems):
+            H0 = keep.array([s.H0])
+            insts[b] = Instance(C.cast(H0, C.POINTER(Csr)),
+                                C.cast(keep.array(list(getattr(s, "H_ctrl", []) or [])),
+                                       C.POINTER(Csr)),
+                                len(s.C), C.cast(keep.array(list(s.C)), C.POINTER(Csr)),
+                                C.cast(keep.array(list(s.E)), C.POINTER(Csr)))
+        seg = None
+        u_host = None
+        self.n_seg = 0
+        if edges is not None and n_ctrl:
+            e = np.ascontiguousarray(edges, np.float64)
+            keep.keep.append(e)
+            self.n_seg = len(e) - 1
+            seg = Segments(self.n_seg, e.ctypes.data_as(_PD))
+            u = np.zeros((n_inst, n_ctrl, self.n_seg))
+            for b, s in enumerate(systems):
+                if getattr(s, "u", None) is not None:
+                    u[b] = np.asarray(s.u).reshape(n_ctrl, self.n_seg)
+            u_host = np.ascontiguousarray(u)
+            keep.keep.append(u_host)
+        h = C.c_void_p()
+        rc = lib.lme_create_batch(n_inst, insts, n_ctrl, n_e,
+                                  C.byref(seg) if seg is not None else None,
+                                  u_host.ctypes.data_as(_PD) if u_host is not None else None,
+                                  C.byref(h))
+        _check(rc, "lme_create_batch")
+        self._h = h
+        self.n_inst, self.n_ctrl, self.n_e = n_inst, n_ctrl, n_e
+        ni = C.c_int32()
+        tot = C.c_int64()
+        self.offsets = np.zeros(n_inst, np.int64)
+        self.dims = np.zeros(n_inst, np.int32)
+        _check(lib.lme_layout(h, C.byref(ni), C.byref(tot),
+                              self.offsets.ctypes.data_as(C.POINTER(C.c_int64)),
+                              self.dims.ctypes.data_as(C.POINTER(C.c_int32))), "lme_layout")
+        self.state_elems = int(tot.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lme_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- packed state helpers (marshalling only) ------------------------------
+    def pack(self, mats, device="cuda"):
+        import torch
+        buf = np.zeros(self.state_elems, np.complex128)
+        for b, m in enumerate(mats):
+            n = int(self.dims[b])
+            buf[self.offsets[b]:self.offsets[b] + n * n] = np.asarray(m, np.complex128).reshape(-1)
+        return torch.from_numpy(buf).to(device)
+
+    def unpack(self, t):
+        a = t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
+        out = []
+        for b in range(self.n_inst):
+            n = int(self.dims[b])
+            out.append(a[..., self.offsets[b]:self.offsets[b] + n * n].reshape(a.shape[:-1] + (n, n)))
+        return out
+
+    # -- entry points ----------------------------------------------------------
+    def evolve(self, rho0, tlist, method="rk4", nsteps=0, rtol=1e-6, atol=1e-9, h0=0.0,
+               h_min=0.0, max_steps=10**7, path=LME_PATH_AUTO, block=0, u=None,
+               want_expect=True, want_states=False, want_rho=True, stream=None):
+        """Runs lme_evolve.  rho0: complex128 device tensor [state_elems].
+        Returns a dict of device tensors (expect, states, rho, counts, status)."""
+        import torch
+        dev = rho0.device
+        tl = np.ascontiguousarray(tlist, np.float64)
+        n_t = len(tl)
+        opt = default_options(method=LME_RK4 if method == "rk4" else LME_DOPRI5,
+                              path=path, nsteps=int(nsteps), block=int(block), rtol=rtol,
+                              atol=atol, h0=h0, h_min=h_min, max_steps=int(max_steps))
+        out = {}
+        out["expect"] = (torch.zeros((self.n_inst, self.n_e, n_t), dtype=torch.complex128,
+                                     device=dev) if want_expect and self.n_e else None)
+        out["states"] = (torch.zeros((n_t, self.state_elems), dtype=torch.complex128,
+                                     device=dev) if want_states else None)
+        out["rho"] = (torch.zeros(self.state_elems, dtype=torch.complex128, device=dev)
+                      if want_rho else None)
+        out["counts"] = torch.zeros((self.n_inst, 2), dtype=torch.int64, device=dev)
+        out["status"] = torch.full((self.n_inst,), -1, dtype=torch.int32, device=dev)
+        rc = load().lme_evolve(self._h, C.byref(opt), n_t, tl.ctypes.data_as(_PD),
+                               _ptr(rho0), _ptr(u), _ptr(out["expect"]), _ptr(out["states"]),
+                               _ptr(out["rho"]), _ptr(out["counts"]), _ptr(out["status"]),
+                               _stream_ptr(stream))
+        _check(rc, "lme_evolve")
+        return out
+
+    def apply(self, y, t=0.0, adjoint=False, form=LME_FORM_OPERATOR, u=None, stream=None):
+        """out = L(t) y (or L^+ y) for every instance of the packed batch."""
+        import torch
+        out = torch.empty_like(y)
+        rc = load().lme_apply(self._h, form, 1 if adjoint else 0, float(t), _ptr(u), _ptr(y),
+                              _ptr(out), _stream_ptr(stream))
+        _check(rc, "lme_apply")
+        return out
+
+
+def raw_create_batch(systems, n_ctrl=None, n_e=None):
+    """Calls lme_create_batch and returns (rc, message); for argument-validation
+    tests.  Destroys the handle on success."""
+    lib = load()
+    keep = _CsrKeep()
+    n_ctrl = len(getattr(systems[0], "H_ctrl", []) or []) if n_ctrl is None else n_ctrl
+    n_e = len(systems[0].E) if n_e is None else n_e
+    insts = (Instance * len(systems))()
+    for b, s in enumerate(systems):
+        insts[b] = Instance(C.cast(keep.array([s.H0]), C.POINTER(Csr)),
+                            C.cast(keep.array(list(getattr(s, "H_ctrl", []) or [])),
+                                   C.POINTER(Csr)),
+                            len(s.C), C.cast(keep.array(list(s.C)), C.POINTER(Csr)),
+                            C.cast(keep.array(list(s.E)), C.POINTER(Csr)))
+    h = C.c_void_p()
+    rc = lib.lme_create_batch(len(systems), insts, n_ctrl, n_e, None, None, C.byref(h))
+    msg = lib.lme_last_error().decode()
+    if rc == LME_OK:
+        lib.lme_destroy(h)
+    return rc, msg

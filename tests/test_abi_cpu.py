@@ -1,0 +1,161 @@
+"""The C ABI on a machine without a GPU: the library loads, exports every
+symbol the header declares, and rejects malformed input before any HIP call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1110_0573_amd import lme, systems as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "lme.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lme_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lme.load()
+    declared = header_functions()
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(lme.EXPORTS) == declared
+
+
+def test_default_options():
+    o = lme.default_options()
+    assert o.method == lme.LME_RK4 and o.path == lme.LME_PATH_AUTO
+    assert o.rtol == 1e-6 and o.atol == 1e-9 and o.max_steps == 10**7
+
+
+def _jc():
+    return S.jc_system(3)
+
+
+def _bad(system, attr, value):
+    s = S.System(system.H0, list(system.C), list(system.E), system.rho0)
+    setattr(s, attr, value)
+    return s
+
+
+def test_create_rejects_dimension_mismatch():
+    s = _jc()
+    bad = _bad(s, "C", [sp.identity(5, dtype=np.complex128, format="csr")])
+    rc, msg = lme.raw_create_batch([bad])
+    assert rc == lme.LME_EINVAL and "expected" in msg
+
+
+def test_create_rejects_out_of_range_column():
+    s = _jc()
+    m = sp.csr_matrix(s.H0)
+    # hand-built CSR with a bad column index
+    keep = lme._CsrKeep()
+    rp = np.array(m.indptr, np.int32)
+    ci = np.array(m.indices, np.int32)
+    ci[0] = 99
+    va = np.array(m.data, np.complex128).view(np.float64)
+    csr = lme.Csr(m.shape[0], m.nnz, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                  ci.ctypes.data_as(C.POINTER(C.c_int32)), va.ctypes.data_as(C.POINTER(C.c_double)))
+    inst = lme.Instance(C.pointer(csr), None, 0, None, None)
+    h = C.c_void_p()
+    rc = lme.load().lme_create_batch(1, C.byref(inst), 0, 0, None, None, C.byref(h))
+    assert rc == lme.LME_EINVAL
+    assert "out of range" in lme.load().lme_last_error().decode()
+    del keep
+
+
+def test_create_rejects_decreasing_row_ptr_and_nan():
+    s = _jc()
+    m = sp.csr_matrix(s.H0)
+    rp = np.array(m.indptr, np.int32)
+    rp[2], rp[3] = rp[3], rp[2] - 1 if rp[2] > 0 else 0
+    ci = np.array(m.indices, np.int32)
+    va = np.array(m.data, np.complex128).view(np.float64)
+    csr = lme.Csr(m.shape[0], m.nnz, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                  ci.ctypes.data_as(C.POINTER(C.c_int32)), va.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    inst = lme.Instance(C.pointer(csr), None, 0, None, None)
+    assert lme.load().lme_create_batch(1, C.byref(inst), 0, 0, None, None, C.byref(h)) == lme.LME_EINVAL
+    s2 = _jc()
+    H = sp.csr_matrix(s2.H0).copy()
+    H.data[0] = np.nan
+    rc, msg = lme.raw_create_batch([_bad(s2, "H0", H)])
+    assert rc == lme.LME_EINVAL and "non-finite" in msg
+
+
+def test_create_rejects_empty_batch_and_null_out():
+    lib = lme.load()
+    h = C.c_void_p()
+    assert lib.lme_create_batch(0, None, 0, 0, None, None, C.byref(h)) == lme.LME_EINVAL
+    assert lib.lme_create_batch(1, None, 0, 0, None, None, None) == lme.LME_EINVAL
+
+
+def test_create_rejects_too_wide_rows():
+    n = 80
+    H = sp.csr_matrix(np.ones((n, n), np.complex128))
+    s = S.System(H, [], [], np.eye(n))
+    rc, msg = lme.raw_create_batch([s])
+    assert rc == lme.LME_ENOTSUP
+
+
+def test_destroy_null_is_noop():
+    lme.load().lme_destroy(None)
+
+
+def _handle():
+    w = S.jc_sweep(n_inst=3, nsteps=10, t_end=1.0, n_out=3)
+    return lme.Handle(w.systems), w
+
+
+def test_layout_packs_instances_in_order():
+    h, w = _handle()
+    dims = [s.n for s in w.systems]
+    assert list(h.dims) == dims
+    assert list(h.offsets) == list(np.cumsum([0] + [d * d for d in dims])[:-1])
+    assert h.state_elems == sum(d * d for d in dims)
+
+
+def _evolve_rc(h, tlist, **opt):
+    o = lme.default_options(**opt)
+    tl = np.ascontiguousarray(tlist, np.float64)
+    rc = lme.load().lme_evolve(h._h, C.byref(o), len(tl), tl.ctypes.data_as(C.POINTER(C.c_double)),
+                               C.c_void_p(16), None, None, None, None, None, None, None)
+    return rc, lme.load().lme_last_error().decode()
+
+
+def test_evolve_validation_precedes_device_use():
+    h, w = _handle()
+    assert _evolve_rc(h, [0.0, 0.5, 0.4], nsteps=10)[0] == lme.LME_EINVAL     # not increasing
+    assert _evolve_rc(h, [0.0, 1.0], nsteps=0)[0] == lme.LME_EINVAL           # no steps
+    assert _evolve_rc(h, [0.0, 0.33, 1.0], nsteps=10)[0] == lme.LME_EGRID     # off grid
+    assert _evolve_rc(h, [0.0, 1.0], nsteps=10, block=300)[0] == lme.LME_EINVAL
+    assert _evolve_rc(h, [0.0, np.nan], nsteps=10)[0] == lme.LME_EINVAL
+    assert _evolve_rc(h, [0.0, 1.0], nsteps=10, method=7)[0] == lme.LME_EINVAL
+    rc, msg = _evolve_rc(h, [0.0, 1.0], nsteps=10)
+    import torch
+    if not torch.cuda.is_available():
+        assert rc == lme.LME_EHIP, msg
+
+
+def test_evolve_grid_check_for_control_edges():
+    w = S.jc_drive(n_inst=2, N=3, n_seg=3, t_end=1.0, steps_per_seg=2)
+    h = lme.Handle(w.systems)
+    assert _evolve_rc(h, [0.0, 1.0], nsteps=10)[0] == lme.LME_EGRID   # edges at 1/3, 2/3
+    rc, _ = _evolve_rc(h, [0.0, 1.0], nsteps=6)
+    assert rc in (lme.LME_OK, lme.LME_EHIP)
+
+
+def test_null_handle_is_rejected():
+    lib = lme.load()
+    o = lme.default_options(nsteps=1)
+    tl = np.array([0.0, 1.0])
+    assert lib.lme_evolve(None, C.byref(o), 2, tl.ctypes.data_as(C.POINTER(C.c_double)),
+                          C.c_void_p(16), None, None, None, None, None, None, None) == lme.LME_EINVAL
+    assert lib.lme_apply(None, 0, 0, 0.0, None, C.c_void_p(16), C.c_void_p(32), None) == lme.LME_EINVAL
+    assert lib.lme_layout(None, None, None, None, None) == lme.LME_EINVAL
