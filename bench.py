@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--layout", type=int, default=0)
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
@@ -101,7 +102,7 @@ def main():
 
     def one():
         return h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block,
-                        stream=stream)
+                        layout=args.layout, stream=stream)
 
     for _ in range(args.warmup):
         one()
@@ -135,11 +136,13 @@ def main():
     plain = [lme.Handle([w.systems[i]]) for i in pidx]
     prho = [p.pack([w.systems[i].rho0], device="cuda:0") for p, i in zip(plain, pidx)]
     for p, r in zip(plain, prho):
-        p.evolve(r, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block, stream=stream)
+        p.evolve(r, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block,
+                 layout=args.layout, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for p, r in zip(plain, prho):
-        p.evolve(r, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block, stream=stream)
+        p.evolve(r, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block,
+                 layout=args.layout, stream=stream)
     torch.cuda.synchronize()
     plain_rate = args.plain_sample * w.nsteps / (time.perf_counter() - t1)
 
@@ -160,7 +163,7 @@ def main():
                                "(dims 10..80), fixed-step RK4, 1000 steps, 101 outputs",
                    "instances": n_inst, "rk_steps": w.nsteps, "outputs": len(w.tlist),
                    "state_MB": 16 * h.state_elems / 1e6, "path": "resident",
-                   "block": args.block or "default"},
+                   "block": args.block or "default", "layout": args.layout},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": None, "kernel": "rk4_resident_kernel",

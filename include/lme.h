@@ -76,6 +76,14 @@ typedef enum lme_path {
   LME_PATH_STREAMED = 2    /* one grid-wide kernel per stage; state in HBM    */
 } lme_path;
 
+/* Thread-to-element layout of the resident kernels. */
+typedef enum lme_layout_kind {
+  LME_LAYOUT_AUTO = 0,
+  LME_LAYOUT_ROW = 1,      /* thread t owns elements t, t+T, ... of the pack  */
+  LME_LAYOUT_COLUMN = 2    /* thread owns one column; its operator entries
+                              stay in registers                               */
+} lme_layout_kind;
+
 /* Form of the Liouvillian application used by lme_apply. */
 typedef enum lme_form {
   LME_FORM_OPERATOR = 0,   /* sparse H, C_k applied to the dense n x n matrix */
@@ -122,8 +130,15 @@ typedef struct lme_options {
   int32_t path;            /* lme_path                                        */
   int32_t nsteps;          /* RK4: equal steps from tlist[0] to tlist[n_t-1];
                               every output time must be on this grid          */
-  int32_t block;           /* resident path: threads per workgroup
-                              (256, 512 or 1024); 0 = tuned default           */
+  int32_t block;           /* resident path: threads per workgroup; 0 = tuned
+                              default.  Row layout: 256, 512 or 1024.
+                              Column layout: 512 or 768                       */
+  int32_t layout;          /* resident path, thread-to-element layout:
+                              LME_LAYOUT_AUTO, LME_LAYOUT_ROW (any operator)
+                              or LME_LAYOUT_COLUMN (monomial collapse
+                              operators, at most 2 off-diagonal entries per
+                              row of H, at most 3 collapse operators and 1
+                              control term); both give identical results     */
   double rtol, atol;       /* DOPRI5: per-element tolerance
                               atol + rtol*max(|rho|, |rho_new|)               */
   double h0;               /* DOPRI5: first step; <= 0 selects it
@@ -133,7 +148,7 @@ typedef struct lme_options {
                               instance                                        */
 } lme_options;
 
-/* Fills defaults: RK4, AUTO path, nsteps 0 (must be set), block 0,
+/* Fills defaults: RK4, AUTO path, nsteps 0 (must be set), block 0, layout 0,
  * rtol 1e-6, atol 1e-9, h0 0, h_min 0, max_steps 10^7. */
 void lme_default_options(lme_options *opt);
 

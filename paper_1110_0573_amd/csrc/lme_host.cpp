@@ -34,6 +34,10 @@ extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap);
 extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb);
 extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
                                               int n_packs, int lds, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb,
+                                                     const lme::Rk4Args *a, int n_packs,
+                                                     int lds, hipStream_t s);
+extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s);
 
@@ -181,7 +185,7 @@ struct DevBuf {
 // the handle
 // ---------------------------------------------------------------------------
 struct Plan {
-  int T = 0, EPT = 0, adjoint = 0, cap = 0;
+  int T = 0, EPT = 0, adjoint = 0, cap = 0, column = 0;
   std::vector<PackDesc> packs;
   std::vector<int32_t> order;
   int max_lds = 0;
@@ -490,9 +494,14 @@ static int ensure_device(lme_ctx *h) {
 // ---------------------------------------------------------------------------
 // planning: group instances by operator signature, fill packs
 // ---------------------------------------------------------------------------
-static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, Plan **out) {
+// Row layout (column == 0): packs of up to `cap` elements.
+// Column layout (column == 1): per signature group choose G (threads per
+// column) and m (instances per pack) with m*n*G <= T and ceil(n/G) <= EPT,
+// maximising the fraction of the workgroup's T*ept element slots in use.
+static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, Plan **out) {
   for (Plan *p : h->plans)
-    if (p->T == T && p->EPT == EPT && p->adjoint == adjoint && p->cap == cap) {
+    if (p->T == T && p->EPT == EPT && p->adjoint == adjoint && p->cap == cap &&
+        p->column == column) {
       *out = p;
       return LME_OK;
     }
@@ -508,22 +517,43 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, Plan **o
   p->EPT = EPT;
   p->adjoint = adjoint;
   p->cap = cap;
+  p->column = column;
   for (auto &g : groups) {
     const InstDesc &d0 = h->inst[g.second[0]];
     const lme::Signature &s = adjoint ? d0.adj : d0.fwd;
     const int blob = adjoint ? d0.adj_bytes : d0.fwd_bytes;
-    const int n2 = s.n * s.n;
-    // at most kMaxPack instances (the kernels encode the pack slot in 10 bits)
-    int64_t m_max = std::min<int64_t>(cap / n2, lme::kMaxPack);
-    const int64_t per_inst = 16LL * n2 + blob + 8LL * s.nb + 12;
-    m_max = std::min<int64_t>(m_max, std::max<int64_t>(0, (h->lds_limit - 48) / per_inst));
-    while (m_max > 0 && lme_internal_pack_lds_bytes(s.n, (int)m_max, blob, s.nb) > h->lds_limit)
-      --m_max;
+    const int n = s.n;
+    const int64_t n2 = (int64_t)n * n;
+    const int cnt = (int)g.second.size();
+    auto lds_fit = [&](int64_t m) {
+      // at most kMaxPack instances (the kernels encode the pack slot in 10 bits)
+      m = std::min<int64_t>(m, lme::kMaxPack);
+      const int64_t per_inst = 16 * n2 + blob + 8LL * s.nb + 12;
+      m = std::min<int64_t>(m, std::max<int64_t>(0, (h->lds_limit - 48) / per_inst));
+      while (m > 0 && lme_internal_pack_lds_bytes(n, (int)m, blob, s.nb) > h->lds_limit) --m;
+      return (int)m;
+    };
+    int m_max = 0, G = 0;
+    if (!column) {
+      m_max = lds_fit(cap / n2);
+    } else {
+      double best = -1.0;
+      for (int gg = (n + EPT - 1) / EPT; gg <= n && gg * n <= T; ++gg) {
+        const int ept = (n + gg - 1) / gg;
+        const int m = lds_fit(std::min<int64_t>(T / (gg * n), cnt));
+        if (m < 1) continue;
+        const double eff = (double)m * n2 / ((double)ept * T);
+        if (eff > best + 1e-12) {
+          best = eff;
+          m_max = m;
+          G = gg;
+        }
+      }
+    }
     if (m_max < 1)
       return fail(LME_ENOTSUP, "instance of dimension %d does not fit a resident workgroup "
-                  "(%d elements, %d B LDS available)", s.n, cap, h->lds_limit);
-    const int cnt = (int)g.second.size();
-    const int n_packs = (int)((cnt + m_max - 1) / m_max);
+                  "(%s layout, %d B LDS available)", n, column ? "column" : "row", h->lds_limit);
+    const int n_packs = (cnt + m_max - 1) / m_max;
     // spread the group evenly over its packs
     int done = 0;
     for (int q = 0; q < n_packs; ++q) {
@@ -531,14 +561,16 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, Plan **o
       PackDesc pk;
       pk.first = (int32_t)p->order.size();
       pk.m = m;
-      pk.n = s.n;
+      pk.n = n;
       pk.wo = s.wo;
       pk.nb = s.nb;
       pk.wb = s.wb;
       pk.nc = s.nc;
       pk.wc = s.wc;
       pk.blob_bytes = blob;
-      pk.lds_bytes = lme_internal_pack_lds_bytes(s.n, m, blob, s.nb);
+      pk.lds_bytes = lme_internal_pack_lds_bytes(n, m, blob, s.nb);
+      pk.G = G;
+      pk.ept = G > 0 ? (n + G - 1) / G : 0;
       for (int r = 0; r < m; ++r) p->order.push_back(g.second[done + r]);
       done += m;
       p->packs.push_back(pk);
@@ -647,6 +679,32 @@ static int pick_rk4_config(const lme_ctx *h, int block, int *T, int *EPT) {
   return LME_OK;
 }
 
+// Can every instance use the column-owner kernels?  They need one operator
+// shape across the batch (off-diagonal width of A, number of monomial collapse
+// operators, at most one control term of width <= kColWB) with a compiled
+// instantiation, and n < 256 (row indices are packed 8 bits apiece).
+static bool column_eligible(const lme_ctx *h, int *wo, int *nc, int *nb) {
+  const lme::Signature &s0 = h->inst[0].fwd;
+  for (auto &d : h->inst) {
+    const lme::Signature &s = d.fwd;
+    if (s.wo != s0.wo || s.nc != s0.nc || s.nb != s0.nb) return false;
+    if ((s.nc > 0 && s.wc != 1) || s.nb > 1 || s.wb > lme::kColWB || s.n > 255) return false;
+  }
+  if (!lme_internal_colown_has_shape(s0.wo, s0.nc, s0.nb)) return false;
+  *wo = s0.wo;
+  *nc = s0.nc;
+  *nb = s0.nb;
+  return true;
+}
+
+static bool column_fits(const lme_ctx *h, int T, int EPT) {
+  for (auto &d : h->inst) {
+    const int n = d.n;
+    if ((int64_t)n * ((n + EPT - 1) / EPT) > T) return false;
+  }
+  return true;
+}
+
 static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
                        const void *rho0_dev, const double *u_dev, void *expect_dev,
                        void *states_dev, void *rho_out_dev, int64_t *counts_dev,
@@ -658,8 +716,9 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if (rc) return rc;
   if (opt->path < LME_PATH_AUTO || opt->path > LME_PATH_STREAMED)
     return fail(LME_EINVAL, "unknown path %d", opt->path);
-  if (opt->block != 0 && opt->block != 256 && opt->block != 512 && opt->block != 1024)
-    return fail(LME_EINVAL, "block must be 0, 256, 512 or 1024");
+  if (opt->block != 0 && opt->block != 256 && opt->block != 512 && opt->block != 768 &&
+      opt->block != 1024)
+    return fail(LME_EINVAL, "block must be 0, 256, 512, 768 or 1024");
   if (opt->method == LME_DOPRI5)
     return fail(LME_ENOTSUP, "adaptive stepping is not available in this build");
   if (opt->method != LME_RK4) return fail(LME_EINVAL, "unknown method %d", opt->method);
@@ -670,8 +729,28 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   const double hstep = n_t > 1 ? (tlist[n_t - 1] - tlist[0]) / nsteps : 0.0;
   std::vector<int32_t> tab;
   if ((rc = rk4_tables(h, n_t, tlist, nsteps, hstep, &tab))) return rc;
-  int T, EPT;
-  if ((rc = pick_rk4_config(h, opt->block, &T, &EPT))) return rc;
+  if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
+    return fail(LME_EINVAL, "unknown layout %d", opt->layout);
+  // column layout: T in {512, 768}; row layout: T in {256, 512, 1024}
+  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0;
+  if (opt->layout != LME_LAYOUT_ROW && column_eligible(h, &wo, &nc, &nb)) {
+    for (int c = 1; c >= 0; --c) {   // prefer the 768-thread configuration
+      const int cT = lme::kColCfg[c][0], cE = lme::kColCfg[c][1];
+      if ((opt->block == 0 || opt->block == cT) && column_fits(h, cT, cE)) {
+        T = cT;
+        EPT = cE;
+        column = 1;
+        col_cfg = c;
+        break;
+      }
+    }
+  }
+  if (!column) {
+    if (opt->layout == LME_LAYOUT_COLUMN)
+      return fail(LME_ENOTSUP, "the column layout does not cover these operators / block size");
+    if (opt->block == 768) return fail(LME_EINVAL, "block 768 exists only in the column layout");
+    if ((rc = pick_rk4_config(h, opt->block, &T, &EPT))) return rc;
+  }
 
   // validation done: from here on the device is used
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -679,7 +758,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if ((rc = upload_tables(h, tab, s))) return rc;
   hipError_t e;
   Plan *plan;
-  if ((rc = plan_packs(h, T, EPT, 0, T * EPT, &plan))) return rc;
+  if ((rc = plan_packs(h, T, EPT, 0, T * EPT, column, &plan))) return rc;
 
   lme::Rk4Args a;
   std::memset(&a, 0, sizeof a);
@@ -705,7 +784,11 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   a.expect = static_cast<double *>(expect_dev);
   a.counts = counts_dev;
   a.status = status_dev;
-  e = lme_internal_launch_rk4(T, EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
+  if (column)
+    e = lme_internal_launch_rk4_colown(col_cfg, wo, nc, nb, &a, (int)plan->packs.size(),
+                                       plan->max_lds, s);
+  else
+    e = lme_internal_launch_rk4(T, EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch resident RK4");
   return LME_OK;
 }
@@ -742,7 +825,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   if (rc) return rc;
   hipError_t e;
   Plan *plan;
-  rc = plan_packs(h, 256, 0, adjoint ? 1 : 0, 1 << 30, &plan);
+  rc = plan_packs(h, 256, 0, adjoint ? 1 : 0, 1 << 30, 0, &plan);
   if (rc) return rc;
   lme::ApplyArgs a;
   std::memset(&a, 0, sizeof a);

@@ -91,7 +91,17 @@ struct PackDesc {
   int32_t n, wo, nb, wb, nc, wc;
   int32_t blob_bytes; // per instance
   int32_t lds_bytes;  // total dynamic LDS this pack needs
+  int32_t G;          // column-owner kernels: row groups (threads per column)
+  int32_t ept;        // column-owner kernels: rows per thread, ceil(n / G)
 };
+
+// Column-owner kernels hold one column's operator entries in registers; they
+// take operators with at most these widths (monomial jumps).
+constexpr int kColWO = 2;   // off-diagonal entries per row of A
+constexpr int kColNC = 3;   // collapse operators
+constexpr int kColWB = 2;   // off-diagonal entries per row of a control term
+// (threads per workgroup, rows per thread) of the column-owner kernels
+constexpr int kColCfg[2][2] = {{512, 14}, {768, 9}};
 
 // Per-call arguments of the resident RK4 kernel.
 struct Rk4Args {

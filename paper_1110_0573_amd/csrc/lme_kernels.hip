@@ -330,6 +330,232 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Resident fixed-step RK4, column-owner layout.  The pack's m instances form
+// C = m*n columns; thread t < C*G owns column c = t mod C (instance b, column
+// j) and rows i = g, g+G, g+2G, ... with g = t div C.
+//   * Column-j operator data (conj of D_j, of the off-diagonal entries of row
+//     j of A, of the jump coefficients of row j, and their column indices)
+//     are loaded into registers once.
+//   * Row-i column indices (off-diagonal of A, jump sources) of each owned
+//     row are packed 8 bits apiece into one register, so the y gathers never
+//     wait on an index load; row-i values are LDS reads that all lanes of a
+//     wave share (broadcasts).
+//   * Rows past n are computed on row n-1 and discarded (no branches).
+// The operator shape (off-diagonal width WO, number of monomial collapse
+// operators NC, number of control terms NB with width kColWB) is a template
+// parameter.  Element arithmetic is in the same order as lindblad_elem(), so
+// both layouts give identical bits.
+// ---------------------------------------------------------------------------
+template <int WO, int NC, int NB>
+struct ColData {
+  double2 dj;
+  int ocol[WO > 0 ? WO : 1];
+  double2 oval[WO > 0 ? WO : 1];     // conj(O_jw)
+  int jcol[NC > 0 ? NC : 1];
+  double2 jval[NC > 0 ? NC : 1];     // conj(J_kj)
+  double2 dbj[NB > 0 ? NB : 1];
+  int obcol[NB > 0 ? NB : 1][kColWB];
+  double2 obval[NB > 0 ? NB : 1][kColWB];
+};
+
+template <int WO, int NC, int NB>
+__device__ __forceinline__ void load_column(ColData<WO, NC, NB> &cd, const OpView &op, int j) {
+  const int n = op.n;
+  cd.dj = cconj(op.D[j]);
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    cd.ocol[w] = op.Ocol[w * n + j];
+    cd.oval[w] = cconj(op.Oval[w * n + j]);
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    cd.jcol[k] = op.Jcol[k * n + j];
+    cd.jval[k] = cconj(op.Jval[k * n + j]);
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    cd.dbj[q] = cconj(op.DB[q * n + j]);
+#pragma unroll
+    for (int w = 0; w < kColWB; ++w) {
+      const bool on = w < op.wb;
+      cd.obcol[q][w] = on ? op.OBcol[(q * op.wb + w) * n + j] : j;
+      cd.obval[q][w] = on ? cconj(op.OBval[(q * op.wb + w) * n + j]) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Row-i column indices, 8 bits each: WO off-diagonal columns of A, then the
+// NC jump sources.
+template <int WO, int NC>
+__device__ __forceinline__ uint32_t row_indices(const OpView &op, int i) {
+  const int n = op.n;
+  uint32_t v = 0;
+#pragma unroll
+  for (int w = 0; w < WO; ++w) v |= (uint32_t)op.Ocol[w * n + i] << (8 * w);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v |= (uint32_t)op.Jcol[k * n + i] << (8 * (WO + k));
+  return v;
+}
+
+__device__ __forceinline__ int field8(uint32_t v, int f) { return (int)((v >> (8 * f)) & 255u); }
+
+// (L y)_ij with the column-j data in registers; same operation order as
+// lindblad_elem().
+template <int WO, int NC, int NB>
+__device__ __forceinline__ double2 lindblad_col(const OpView &op, const ColData<WO, NC, NB> &cd,
+                                                const double2 *Y, int i, uint32_t ri, int j,
+                                                double2 yij, const double *uq) {
+  const int n = op.n;
+  const double2 *Yrow = Y + i * n;
+  double2 acc = cmul(cadd(op.D[i], cd.dj), yij);
+#pragma unroll
+  for (int w = 0; w < WO; ++w) acc = cfma(op.Oval[w * n + i], Y[field8(ri, w) * n + j], acc);
+#pragma unroll
+  for (int w = 0; w < WO; ++w) acc = cfma(cd.oval[w], Yrow[cd.ocol[w]], acc);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const double u = uq[q];
+    if (u != 0.0) {
+      const int wb = op.wb;
+      const double2 *OB = op.OBval + q * wb * n;
+      const int32_t *OC = op.OBcol + q * wb * n;
+      double2 t = cmul(cadd(op.DB[q * n + i], cd.dbj[q]), yij);
+#pragma unroll
+      for (int w = 0; w < kColWB; ++w)
+        if (w < wb) t = cfma(OB[w * n + i], Y[OC[w * n + i] * n + j], t);
+#pragma unroll
+      for (int w = 0; w < kColWB; ++w)
+        if (w < wb) t = cfma(cd.obval[q][w], Yrow[cd.obcol[q][w]], t);
+      acc = caxpy(u, t, acc);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double2 p = cmul(op.Jval[k * n + i], cd.jval[k]);
+    acc = cfma(p, Y[field8(ri, WO + k) * n + cd.jcol[k]], acc);
+  }
+  return acc;
+}
+
+template <int T, int EPT, int WO, int NC, int NB>
+__global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, C = pk.m * n, G = pk.G, ept = pk.ept;
+  const PackLds L = carve(smem, pk);
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  const int tid = threadIdx.x;
+
+  for (int b = tid; b < pk.m; b += T) {
+    const int id = a.order[pk.first + b];
+    L.ids[b] = id;
+    L.off[b] = a.inst[id].rho_off;
+    if (a.status) a.status[id] = 0;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
+  __syncthreads();
+
+  const bool active = tid < C * G;
+  const int g = active ? tid / C : 0;
+  const int c = active ? tid - g * C : 0;
+  const int b = c / n, j = c - b * n;
+  const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+  double2 *Yb = L.Y + b * n2;
+  ColData<WO, NC, NB> cd;
+  load_column<WO, NC, NB>(cd, op, j);
+
+  // Slot r holds row g + r*G; past n the row is clamped to n-1 (computed,
+  // never stored).  Rows are re-derived from an opaque copy of g wherever
+  // they are used, so no per-row address lives across stages in a register.
+  auto row_of = [&](int gg, int r) { return min(gg + r * G, n - 1); };
+  auto owns = [&](int gg, int r) { return active && r < ept && gg + r * G < n; };
+
+  double2 rho[EPT], acc[EPT], yn[EPT];
+  uint32_t ridx[EPT];
+  const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    ridx[r] = row_indices<WO, NC>(op, row_of(g, r));
+    rho[r] = owns(g, r) ? rho0[L.off[b] + row_of(g, r) * n + j] : make_double2(0.0, 0.0);
+  }
+
+  const bool want_expect = a.expect != nullptr && a.n_e > 0;
+  int next_out = 0;
+  const double h = a.h;
+  for (int st = 0;; ++st) {
+    while (next_out < a.n_t && a.out_step[next_out] == st) {
+      __syncthreads();
+      int gg = g;
+      asm volatile("" : "+v"(gg));
+#pragma unroll
+      for (int r = 0; r < EPT; ++r)
+        if (owns(gg, r)) {
+          const int i = row_of(gg, r);
+          Yb[i * n + j] = rho[r];
+          if (a.states)
+            reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems + L.off[b] +
+                                                  i * n + j] = rho[r];
+        }
+      __syncthreads();
+      if (want_expect) write_outputs<T>(a, pk, L, next_out);
+      ++next_out;
+    }
+    if (st == a.nsteps) break;
+
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+      yn[r] = rho[r];
+      acc[r] = make_double2(0.0, 0.0);
+    }
+    for (int stage = 0; stage < 4; ++stage) {
+      const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
+      const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+      __syncthreads();
+      if (stage == 0 && NB > 0) {
+        const int seg = a.seg_of_step[st];
+        for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+          const int bb = idx / pk.nb, q = idx - bb * pk.nb;
+          L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+        }
+      }
+      int gg = g;
+      asm volatile("" : "+v"(gg));
+#pragma unroll
+      for (int r = 0; r < EPT; ++r)
+        if (owns(gg, r)) Yb[row_of(gg, r) * n + j] = yn[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) {
+        if (r < ept) {
+          uint32_t ri = ridx[r];
+          int i = row_of(gg, r);
+          asm volatile("" : "+v"(i), "+v"(ri));
+          const double2 kv = lindblad_col<WO, NC, NB>(op, cd, Yb, i, ri, j, yn[r],
+                                                      L.u + b * pk.nb);
+          acc[r] = caxpy(wgt, kv, acc[r]);
+          yn[r] = caxpy(cnext, kv, rho[r]);
+        }
+        if (r & 1) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) rho[r] = caxpy(h / 6.0, acc[r], rho[r]);
+  }
+
+  if (a.rho_out) {
+#pragma unroll
+    for (int r = 0; r < EPT; ++r)
+      if (owns(g, r))
+        reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + row_of(g, r) * n + j] = rho[r];
+  }
+  if (a.counts)
+    for (int bb = tid; bb < pk.m; bb += T) {
+      a.counts[2 * (int64_t)L.ids[bb]] = a.nsteps;
+      a.counts[2 * (int64_t)L.ids[bb] + 1] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One application of L (or L^+) to every instance, stage input in LDS.
 // ---------------------------------------------------------------------------
 template <int T>
@@ -407,6 +633,40 @@ extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args
   LME_RK4_CASE(1024, 1) LME_RK4_CASE(1024, 2) LME_RK4_CASE(1024, 4) LME_RK4_CASE(1024, 6)
 #undef LME_RK4_CASE
   return hipErrorInvalidValue;
+}
+
+template <int T, int EPT, int WO, int NC, int NB>
+static hipError_t launch_colown_t(const lme::Rk4Args &a, int n_packs, int lds, hipStream_t s) {
+  auto k = lme::rk4_colown_kernel<T, EPT, WO, NC, NB>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(T), lds, s, a);
+  return hipGetLastError();
+}
+
+// Column-owner kernels: (T, EPT) configuration index cfg into kColCfg and the
+// operator shape (wo, nc, nb); returns hipErrorInvalidValue for shapes that
+// have no instantiation.
+extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb,
+                                                     const lme::Rk4Args *a, int n_packs,
+                                                     int lds, hipStream_t s) {
+#define LME_COL_CASE(CFG, TT, EE, W, K, B)                       \
+  if (cfg == CFG && wo == W && nc == K && nb == B)               \
+    return launch_colown_t<TT, EE, W, K, B>(*a, n_packs, lds, s);
+#define LME_COL_SHAPES(CFG, TT, EE)                                                        \
+  LME_COL_CASE(CFG, TT, EE, 1, 2, 0) LME_COL_CASE(CFG, TT, EE, 1, 3, 0)                    \
+  LME_COL_CASE(CFG, TT, EE, 2, 2, 0) LME_COL_CASE(CFG, TT, EE, 1, 2, 1)                    \
+  LME_COL_CASE(CFG, TT, EE, 1, 3, 1)
+  LME_COL_SHAPES(0, 512, 14)
+  LME_COL_SHAPES(1, 768, 9)
+#undef LME_COL_SHAPES
+#undef LME_COL_CASE
+  return hipErrorInvalidValue;
+}
+
+extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb) {
+  return (wo == 1 && nc == 2) || (wo == 1 && nc == 3) || (wo == 2 && nc == 2 && nb == 0);
 }
 
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,

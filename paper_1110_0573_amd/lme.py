@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "LME_OK", 1: "LME_EINVAL", 2: "LME_EGRID", 3: "LME_EMAXSTEPS"
 LME_RK4, LME_DOPRI5 = 0, 1
 LME_PATH_AUTO, LME_PATH_RESIDENT, LME_PATH_STREAMED = 0, 1, 2
 LME_FORM_OPERATOR, LME_FORM_SUPEROP = 0, 1
+LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
@@ -53,7 +54,7 @@ class Segments(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("path", C.c_int32), ("nsteps", C.c_int32),
-                ("block", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
+                ("block", C.c_int32), ("layout", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
                 ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int64)]
 
 
@@ -222,7 +223,7 @@ class Handle:
 
     # -- entry points ----------------------------------------------------------
     def evolve(self, rho0, tlist, method="rk4", nsteps=0, rtol=1e-6, atol=1e-9, h0=0.0,
-               h_min=0.0, max_steps=10**7, path=LME_PATH_AUTO, block=0, u=None,
+               h_min=0.0, max_steps=10**7, path=LME_PATH_AUTO, block=0, layout=0, u=None,
                want_expect=True, want_states=False, want_rho=True, stream=None):
         """Runs lme_evolve.  rho0: complex128 device tensor [state_elems].
         Returns a dict of device tensors (expect, states, rho, counts, status)."""
@@ -231,7 +232,8 @@ class Handle:
         tl = np.ascontiguousarray(tlist, np.float64)
         n_t = len(tl)
         opt = default_options(method=LME_RK4 if method == "rk4" else LME_DOPRI5,
-                              path=path, nsteps=int(nsteps), block=int(block), rtol=rtol,
+                              path=path, nsteps=int(nsteps), block=int(block),
+                              layout=int(layout), rtol=rtol,
                               atol=atol, h0=h0, h_min=h_min, max_steps=int(max_steps))
         out = {}
         out["expect"] = (torch.zeros((self.n_inst, self.n_e, n_t), dtype=torch.complex128,

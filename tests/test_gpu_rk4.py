@@ -155,21 +155,48 @@ def test_rk4_single_output_time_no_steps():
         np.testing.assert_array_equal(rho[b], s.rho0)
 
 
-def test_rk4_batched_equals_single_and_block_sizes_bitwise():
+def test_rk4_batched_equals_single_and_layouts_bitwise():
+    """Row layout (block 256/512/1024), column layout (block 512/768) and
+    single-instance runs give identical bits."""
     w = S.jc_sweep(n_inst=24, seed=51, nsteps=60, t_end=1.5, n_out=7)
-    _, ref = run(w.systems, w.tlist, w.nsteps, block=512)
+    _, ref = run(w.systems, w.tlist, w.nsteps, block=512, layout=lme.LME_LAYOUT_ROW)
     ref_ex = ref["expect"].cpu().numpy()
     ref_rho = ref["rho"].cpu().numpy()
-    for block in (256, 1024):
-        _, o = run(w.systems, w.tlist, w.nsteps, block=block)
-        assert np.array_equal(o["expect"].cpu().numpy(), ref_ex)
-        assert np.array_equal(o["rho"].cpu().numpy(), ref_rho)
+    variants = [(256, lme.LME_LAYOUT_ROW), (1024, lme.LME_LAYOUT_ROW),
+                (512, lme.LME_LAYOUT_COLUMN), (768, lme.LME_LAYOUT_COLUMN), (0, 0)]
+    for block, layout in variants:
+        _, o = run(w.systems, w.tlist, w.nsteps, block=block, layout=layout)
+        assert np.array_equal(o["expect"].cpu().numpy(), ref_ex), (block, layout)
+        assert np.array_equal(o["rho"].cpu().numpy(), ref_rho), (block, layout)
     h_all = lme.Handle(w.systems)
     rho_all = h_all.unpack(torch.from_numpy(ref_rho))
     for b in (0, 5, 23):
         hs, o = run([w.systems[b]], w.tlist, w.nsteps)
         assert np.array_equal(o["expect"].cpu().numpy()[0], ref_ex[b])
         assert np.array_equal(hs.unpack(o["rho"])[0], rho_all[b])
+
+
+def test_rk4_column_layout_with_controls_and_thermal_jumps():
+    """Column layout with one control term and three collapse operators."""
+    w = S.jc_drive(n_inst=5, N=6, n_seg=5, t_end=1.0, steps_per_seg=4, sigma_u=0.7)
+    for s in w.systems:
+        s.C.append(S.tidy(np.sqrt(0.02) * S.dag(S.jc_ops(6)[0])))
+    tl = np.linspace(0.0, 1.0, 6)
+    h, out = run(w.systems, tl, w.nsteps, layout=lme.LME_LAYOUT_COLUMN)
+    _, ref = run(w.systems, tl, w.nsteps, layout=lme.LME_LAYOUT_ROW)
+    assert np.array_equal(out["rho"].cpu().numpy(), ref["rho"].cpu().numpy())
+    rho = h.unpack(out["rho"])
+    for b, s in enumerate(w.systems):
+        _, ost = oracle.rk4(s, s.rho0, tl, w.nsteps, store_states=True)
+        assert td(rho[b], ost[-1]) <= TD_BAR
+
+
+def test_rk4_column_layout_rejects_general_jumps():
+    s = S.random_system(4, n_c=2, seed=5)
+    h = lme.Handle([s])
+    with pytest.raises(lme.LmeError) as e:
+        h.evolve(h.pack([s.rho0]), np.array([0.0, 1.0]), nsteps=4, layout=lme.LME_LAYOUT_COLUMN)
+    assert e.value.code == lme.LME_ENOTSUP
 
 
 def test_rk4_deterministic_repeat():
