@@ -34,7 +34,7 @@ extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap);
 extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb);
 extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
                                               int n_packs, int lds, hipStream_t s);
-extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb,
+extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb, int re,
                                                      const lme::Rk4Args *a, int n_packs,
                                                      int lds, hipStream_t s);
 extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
@@ -385,6 +385,22 @@ static int create_impl(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
         return fail(LME_ENOTSUP, "instance %d: control operator row wider than %d", b, lme::kMaxWidth);
 
     InstDesc &d = h->inst[b];
+    d.flags = 0;
+    {
+      bool jr = true, oi = true;
+      for (auto &c : C)
+        for (auto &row : c.rows)
+          for (auto &e : row) jr = jr && e.second.imag() == 0.0;
+      auto offdiag_imag = [](const Sparse &S) {
+        for (int i = 0; i < S.n; ++i)
+          for (auto &e : S.rows[i])
+            if (e.first != i && e.second.real() != 0.0) return false;
+        return true;
+      };
+      oi = offdiag_imag(A);
+      for (auto &x : B) oi = oi && offdiag_imag(x);
+      d.flags = (jr ? lme::kJumpsReal : 0) | (oi ? lme::kOffdiagImag : 0);
+    }
     std::vector<uint8_t> fb = make_blob(A, B, C, &d.fwd);
     std::vector<uint8_t> ab = make_blob(At, Bt, Ct, &d.adj);
     d.n = n;
@@ -732,7 +748,10 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
     return fail(LME_EINVAL, "unknown layout %d", opt->layout);
   // column layout: T in {512, 768}; row layout: T in {256, 512, 1024}
-  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0;
+  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0, re = 1;
+  for (auto &d : h->inst)
+    if ((d.flags & (lme::kJumpsReal | lme::kOffdiagImag)) != (lme::kJumpsReal | lme::kOffdiagImag))
+      re = 0;
   if (opt->layout != LME_LAYOUT_ROW && column_eligible(h, &wo, &nc, &nb)) {
     for (int c = 1; c >= 0; --c) {   // prefer the 768-thread configuration
       const int cT = lme::kColCfg[c][0], cE = lme::kColCfg[c][1];
@@ -785,7 +804,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   a.counts = counts_dev;
   a.status = status_dev;
   if (column)
-    e = lme_internal_launch_rk4_colown(col_cfg, wo, nc, nb, &a, (int)plan->packs.size(),
+    e = lme_internal_launch_rk4_colown(col_cfg, wo, nc, nb, re, &a, (int)plan->packs.size(),
                                        plan->max_lds, s);
   else
     e = lme_internal_launch_rk4(T, EPT, &a, (int)plan->packs.size(), plan->max_lds, s);

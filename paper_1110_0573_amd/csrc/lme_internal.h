@@ -74,6 +74,12 @@ struct Signature {
   int32_t n, wo, nb, wb, nc, wc;
 };
 
+// Value-structure flags of an instance's forward operators.
+enum : int32_t {
+  kJumpsReal = 1,         // every collapse-operator entry is real
+  kOffdiagImag = 2,       // off-diagonal entries of A and of every -iH_j are imaginary
+};
+
 struct InstDesc {
   int64_t rho_off;    // complex elements into the packed state
   int64_t ops_off;    // bytes into the forward op pool
@@ -82,6 +88,7 @@ struct InstDesc {
   int32_t n, we;      // dimension, expectation-op ELL width
   Signature fwd, adj;
   int32_t fwd_bytes, adj_bytes;
+  int32_t flags;      // kJumpsReal | kOffdiagImag
 };
 
 // A pack: m instances with one signature, integrated by one workgroup.

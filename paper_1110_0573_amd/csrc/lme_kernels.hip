@@ -398,20 +398,41 @@ __device__ __forceinline__ uint32_t row_indices(const OpView &op, int i) {
 }
 
 __device__ __forceinline__ int field8(uint32_t v, int f) { return (int)((v >> (8 * f)) & 255u); }
+// 24-bit multiply: full rate on CDNA (a 32-bit multiply is quarter rate);
+// every product here is below 2^24.
+__device__ __forceinline__ int mul24(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
 
 // (L y)_ij with the column-j data in registers; same operation order as
-// lindblad_elem().
-template <int WO, int NC, int NB>
+// lindblad_elem().  RE: the off-diagonal entries of A (and of the control
+// terms) are purely imaginary and the jump coefficients real, which holds for
+// a real Hamiltonian with collapse operators whose C^+C are diagonal; the
+// vanishing parts are skipped, which changes no bit of the result (they only
+// ever add exact zeros).
+template <int WO, int NC, int NB, bool RE>
 __device__ __forceinline__ double2 lindblad_col(const OpView &op, const ColData<WO, NC, NB> &cd,
                                                 const double2 *Y, int i, uint32_t ri, int j,
                                                 double2 yij, const double *uq) {
   const int n = op.n;
-  const double2 *Yrow = Y + i * n;
+  const double2 *Yrow = Y + mul24(i, n);
   double2 acc = cmul(cadd(op.D[i], cd.dj), yij);
 #pragma unroll
-  for (int w = 0; w < WO; ++w) acc = cfma(op.Oval[w * n + i], Y[field8(ri, w) * n + j], acc);
+  for (int w = 0; w < WO; ++w) {
+    const double2 yv = Y[mul24(field8(ri, w), n) + j];
+    if (RE) {
+      const double o = reinterpret_cast<const double *>(op.Oval + w * n + i)[1];
+      acc = make_double2(fma(-o, yv.y, acc.x), fma(o, yv.x, acc.y));
+    } else {
+      acc = cfma(op.Oval[w * n + i], yv, acc);
+    }
+  }
 #pragma unroll
-  for (int w = 0; w < WO; ++w) acc = cfma(cd.oval[w], Yrow[cd.ocol[w]], acc);
+  for (int w = 0; w < WO; ++w) {
+    const double2 yv = Yrow[cd.ocol[w]];
+    if (RE)
+      acc = make_double2(fma(-cd.oval[w].y, yv.y, acc.x), fma(cd.oval[w].y, yv.x, acc.y));
+    else
+      acc = cfma(cd.oval[w], yv, acc);
+  }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const double u = uq[q];
@@ -422,22 +443,42 @@ __device__ __forceinline__ double2 lindblad_col(const OpView &op, const ColData<
       double2 t = cmul(cadd(op.DB[q * n + i], cd.dbj[q]), yij);
 #pragma unroll
       for (int w = 0; w < kColWB; ++w)
-        if (w < wb) t = cfma(OB[w * n + i], Y[OC[w * n + i] * n + j], t);
+        if (w < wb) {
+          const double2 yv = Y[mul24(OC[w * n + i], n) + j];
+          if (RE) {
+            const double o = reinterpret_cast<const double *>(OB + w * n + i)[1];
+            t = make_double2(fma(-o, yv.y, t.x), fma(o, yv.x, t.y));
+          } else {
+            t = cfma(OB[w * n + i], yv, t);
+          }
+        }
 #pragma unroll
       for (int w = 0; w < kColWB; ++w)
-        if (w < wb) t = cfma(cd.obval[q][w], Yrow[cd.obcol[q][w]], t);
+        if (w < wb) {
+          const double2 yv = Yrow[cd.obcol[q][w]];
+          if (RE)
+            t = make_double2(fma(-cd.obval[q][w].y, yv.y, t.x), fma(cd.obval[q][w].y, yv.x, t.y));
+          else
+            t = cfma(cd.obval[q][w], yv, t);
+        }
       acc = caxpy(u, t, acc);
     }
   }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    const double2 p = cmul(op.Jval[k * n + i], cd.jval[k]);
-    acc = cfma(p, Y[field8(ri, WO + k) * n + cd.jcol[k]], acc);
+    const double2 yv = Y[mul24(field8(ri, WO + k), n) + cd.jcol[k]];
+    if (RE) {
+      const double p = reinterpret_cast<const double *>(op.Jval + k * n + i)[0] * cd.jval[k].x;
+      acc = make_double2(fma(p, yv.x, acc.x), fma(p, yv.y, acc.y));
+    } else {
+      const double2 p = cmul(op.Jval[k * n + i], cd.jval[k]);
+      acc = cfma(p, yv, acc);
+    }
   }
   return acc;
 }
 
-template <int T, int EPT, int WO, int NC, int NB>
+template <int T, int EPT, int WO, int NC, int NB, bool RE>
 __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const PackDesc pk = a.packs[blockIdx.x];
@@ -491,7 +532,7 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       for (int r = 0; r < EPT; ++r)
         if (owns(gg, r)) {
           const int i = row_of(gg, r);
-          Yb[i * n + j] = rho[r];
+          Yb[mul24(i, n) + j] = rho[r];
           if (a.states)
             reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems + L.off[b] +
                                                   i * n + j] = rho[r];
@@ -522,7 +563,7 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       asm volatile("" : "+v"(gg));
 #pragma unroll
       for (int r = 0; r < EPT; ++r)
-        if (owns(gg, r)) Yb[row_of(gg, r) * n + j] = yn[r];
+        if (owns(gg, r)) Yb[mul24(row_of(gg, r), n) + j] = yn[r];
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
@@ -530,7 +571,7 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
           uint32_t ri = ridx[r];
           int i = row_of(gg, r);
           asm volatile("" : "+v"(i), "+v"(ri));
-          const double2 kv = lindblad_col<WO, NC, NB>(op, cd, Yb, i, ri, j, yn[r],
+          const double2 kv = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, yn[r],
                                                       L.u + b * pk.nb);
           acc[r] = caxpy(wgt, kv, acc[r]);
           yn[r] = caxpy(cnext, kv, rho[r]);
@@ -635,9 +676,9 @@ extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args
   return hipErrorInvalidValue;
 }
 
-template <int T, int EPT, int WO, int NC, int NB>
+template <int T, int EPT, int WO, int NC, int NB, bool RE>
 static hipError_t launch_colown_t(const lme::Rk4Args &a, int n_packs, int lds, hipStream_t s) {
-  auto k = lme::rk4_colown_kernel<T, EPT, WO, NC, NB>;
+  auto k = lme::rk4_colown_kernel<T, EPT, WO, NC, NB, RE>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -645,21 +686,21 @@ static hipError_t launch_colown_t(const lme::Rk4Args &a, int n_packs, int lds, h
   return hipGetLastError();
 }
 
-// Column-owner kernels: (T, EPT) configuration index cfg into kColCfg and the
-// operator shape (wo, nc, nb); returns hipErrorInvalidValue for shapes that
-// have no instantiation.
-extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb,
+// Column-owner kernels: (T, EPT) configuration index cfg into kColCfg, the
+// operator shape (wo, nc, nb) and the real/imaginary specialisation re;
+// returns hipErrorInvalidValue for shapes that have no instantiation.
+extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb, int re,
                                                      const lme::Rk4Args *a, int n_packs,
                                                      int lds, hipStream_t s) {
-#define LME_COL_CASE(CFG, TT, EE, W, K, B)                       \
-  if (cfg == CFG && wo == W && nc == K && nb == B)               \
-    return launch_colown_t<TT, EE, W, K, B>(*a, n_packs, lds, s);
-#define LME_COL_SHAPES(CFG, TT, EE)                                                        \
-  LME_COL_CASE(CFG, TT, EE, 1, 2, 0) LME_COL_CASE(CFG, TT, EE, 1, 3, 0)                    \
-  LME_COL_CASE(CFG, TT, EE, 2, 2, 0) LME_COL_CASE(CFG, TT, EE, 1, 2, 1)                    \
-  LME_COL_CASE(CFG, TT, EE, 1, 3, 1)
-  LME_COL_SHAPES(0, 512, 14)
-  LME_COL_SHAPES(1, 768, 9)
+#define LME_COL_CASE(CFG, TT, EE, W, K, B, R)                          \
+  if (cfg == CFG && wo == W && nc == K && nb == B && re == R)          \
+    return launch_colown_t<TT, EE, W, K, B, (R != 0)>(*a, n_packs, lds, s);
+#define LME_COL_SHAPES(CFG, TT, EE, R)                                                        \
+  LME_COL_CASE(CFG, TT, EE, 1, 2, 0, R) LME_COL_CASE(CFG, TT, EE, 1, 3, 0, R)                 \
+  LME_COL_CASE(CFG, TT, EE, 2, 2, 0, R) LME_COL_CASE(CFG, TT, EE, 1, 2, 1, R)                 \
+  LME_COL_CASE(CFG, TT, EE, 1, 3, 1, R)
+  LME_COL_SHAPES(0, 512, 14, 0) LME_COL_SHAPES(0, 512, 14, 1)
+  LME_COL_SHAPES(1, 768, 9, 0) LME_COL_SHAPES(1, 768, 9, 1)
 #undef LME_COL_SHAPES
 #undef LME_COL_CASE
   return hipErrorInvalidValue;

@@ -142,13 +142,14 @@ def jc_ops(N):
 
 
 def jc_system(N, wc=1.0, wa=1.0, g=0.05 * TWO_PI, kappa=0.005, gamma=0.05,
-              n_th=0.0, psi0=(1, 0)):
-    """H = wc a^+a + wa sigma+sigma- + g (a^+ sigma- + a sigma+);
+              n_th=0.0, psi0=(1, 0), phase=0.0):
+    """H = wc a^+a + wa sigma+sigma- + g (e^{i phase} a^+ sigma- + h.c.);
     C = sqrt(kappa(1+n_th)) a, [sqrt(kappa n_th) a^+], sqrt(gamma) sigma-;
     E = a^+a, sigma_z; rho0 = |n_photon, q><..| with psi0 = (n_photon, q)."""
     a, sm, sz = jc_ops(N)
     ad, sp_ = dag(a), dag(sm)
-    H = tidy(wc * (ad @ a) + wa * (sp_ @ sm) + g * (ad @ sm + a @ sp_))
+    cp = np.exp(1j * phase)
+    H = tidy(wc * (ad @ a) + wa * (sp_ @ sm) + g * (cp * (ad @ sm) + np.conj(cp) * (a @ sp_)))
     C = [tidy(np.sqrt(kappa * (1.0 + n_th)) * a)]
     if n_th > 0:
         C.append(tidy(np.sqrt(kappa * n_th) * ad))

@@ -191,6 +191,21 @@ def test_rk4_column_layout_with_controls_and_thermal_jumps():
         assert td(rho[b], ost[-1]) <= TD_BAR
 
 
+def test_rk4_column_layout_complex_coupling():
+    """A complex coupling phase makes the off-diagonal of A non-imaginary: the
+    column layout takes its general-complex specialisation."""
+    systems = [S.jc_system(N, g=0.3, kappa=0.02, gamma=0.04, phase=0.7 + 0.1 * N,
+                           n_th=0.1) for N in (3, 7, 12, 20)]
+    tl = np.linspace(0.0, 2.0, 5)
+    h, out = run(systems, tl, 80, layout=lme.LME_LAYOUT_COLUMN)
+    _, ref = run(systems, tl, 80, layout=lme.LME_LAYOUT_ROW)
+    assert np.array_equal(out["rho"].cpu().numpy(), ref["rho"].cpu().numpy())
+    rho = h.unpack(out["rho"])
+    for b, s in enumerate(systems):
+        _, ost = oracle.rk4(s, s.rho0, tl, 80, store_states=True)
+        assert td(rho[b], ost[-1]) <= TD_BAR
+
+
 def test_rk4_column_layout_rejects_general_jumps():
     s = S.random_system(4, n_c=2, seed=5)
     h = lme.Handle([s])
