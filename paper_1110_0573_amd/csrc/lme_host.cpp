@@ -38,6 +38,10 @@ extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, in
                                                      const lme::Rk4Args *a, int n_packs,
                                                      int lds, hipStream_t s);
 extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
+extern "C" int lme_internal_dp5_epts(int *ept, int cap);
+extern "C" int lme_internal_dp5_extra_lds(int m);
+extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,
+                                              int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s);
 
@@ -185,7 +189,7 @@ struct DevBuf {
 // the handle
 // ---------------------------------------------------------------------------
 struct Plan {
-  int T = 0, EPT = 0, adjoint = 0, cap = 0, column = 0;
+  int T = 0, EPT = 0, adjoint = 0, cap = 0, column = 0, dp = 0;
   std::vector<PackDesc> packs;
   std::vector<int32_t> order;
   int max_lds = 0;
@@ -210,6 +214,10 @@ struct lme_ctx {
   // step tables of the last evolve call (content-cached)
   std::vector<int32_t> steps_key;
   DevBuf d_steps;
+  // adaptive stepping: stop tables (content-cached) and stage derivatives
+  std::vector<double> stops_key;
+  DevBuf d_stops;
+  DevBuf d_kbuf;
   ~lme_ctx() {
     for (Plan *p : plans) delete p;
   }
@@ -514,10 +522,11 @@ static int ensure_device(lme_ctx *h) {
 // Column layout (column == 1): per signature group choose G (threads per
 // column) and m (instances per pack) with m*n*G <= T and ceil(n/G) <= EPT,
 // maximising the fraction of the workgroup's T*ept element slots in use.
-static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, Plan **out) {
+static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, int dp,
+                      Plan **out) {
   for (Plan *p : h->plans)
     if (p->T == T && p->EPT == EPT && p->adjoint == adjoint && p->cap == cap &&
-        p->column == column) {
+        p->column == column && p->dp == dp) {
       *out = p;
       return LME_OK;
     }
@@ -534,6 +543,11 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
   p->adjoint = adjoint;
   p->cap = cap;
   p->column = column;
+  p->dp = dp;
+  // LDS of a pack of m instances (the adaptive kernel adds its step control)
+  auto pack_lds = [&](int n, int m, int blob, int nb) {
+    return lme_internal_pack_lds_bytes(n, m, blob, nb) + (dp ? lme_internal_dp5_extra_lds(m) : 0);
+  };
   for (auto &g : groups) {
     const InstDesc &d0 = h->inst[g.second[0]];
     const lme::Signature &s = adjoint ? d0.adj : d0.fwd;
@@ -544,9 +558,9 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
     auto lds_fit = [&](int64_t m) {
       // at most kMaxPack instances (the kernels encode the pack slot in 10 bits)
       m = std::min<int64_t>(m, lme::kMaxPack);
-      const int64_t per_inst = 16 * n2 + blob + 8LL * s.nb + 12;
+      const int64_t per_inst = 16 * n2 + blob + 8LL * s.nb + 12 + (dp ? 128 : 0);
       m = std::min<int64_t>(m, std::max<int64_t>(0, (h->lds_limit - 48) / per_inst));
-      while (m > 0 && lme_internal_pack_lds_bytes(n, (int)m, blob, s.nb) > h->lds_limit) --m;
+      while (m > 0 && pack_lds(n, (int)m, blob, s.nb) > h->lds_limit) --m;
       return (int)m;
     };
     int m_max = 0, G = 0;
@@ -584,7 +598,7 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       pk.nc = s.nc;
       pk.wc = s.wc;
       pk.blob_bytes = blob;
-      pk.lds_bytes = lme_internal_pack_lds_bytes(n, m, blob, s.nb);
+      pk.lds_bytes = pack_lds(n, m, blob, s.nb);
       pk.G = G;
       pk.ept = G > 0 ? (n + G - 1) / G : 0;
       for (int r = 0; r < m; ++r) p->order.push_back(g.second[done + r]);
@@ -721,6 +735,128 @@ static bool column_fits(const lme_ctx *h, int T, int EPT) {
   return true;
 }
 
+// Stop points of the adaptive stepper: every output time after tlist[0] and
+// every control edge inside (tlist[0], tlist[n_t-1]), sorted, duplicates
+// removed.  Packed as [stops (double) | out index | segment] into 8-byte
+// slots: stops[n], then 2n int32.
+static int dp5_tables(const lme_ctx *h, int32_t n_t, const double *tlist,
+                      std::vector<double> *stops, std::vector<int32_t> *out_idx,
+                      std::vector<int32_t> *seg) {
+  const double t0 = tlist[0], t1 = tlist[n_t - 1];
+  std::vector<double> st(tlist + 1, tlist + n_t);
+  for (int q = 0; q <= h->n_seg && h->n_seg > 0; ++q)
+    if (h->edges[q] > t0 && h->edges[q] < t1) st.push_back(h->edges[q]);
+  std::sort(st.begin(), st.end());
+  st.erase(std::unique(st.begin(), st.end()), st.end());
+  out_idx->assign(st.size(), -1);
+  seg->assign(st.size(), -1);
+  int k = 1;
+  double prev = t0;
+  for (size_t i = 0; i < st.size(); ++i) {
+    while (k < n_t && tlist[k] < st[i]) ++k;
+    if (k < n_t && tlist[k] == st[i]) (*out_idx)[i] = k;
+    (*seg)[i] = segment_at(h, 0.5 * (prev + st[i]));
+    prev = st[i];
+  }
+  stops->swap(st);
+  return LME_OK;
+}
+
+static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
+                      const void *rho0_dev, const double *u_dev, void *expect_dev,
+                      void *states_dev, void *rho_out_dev, int64_t *counts_dev,
+                      int32_t *status_dev, void *stream) {
+  if (!(opt->rtol > 0.0) || !std::isfinite(opt->rtol) || !(opt->atol >= 0.0) ||
+      !std::isfinite(opt->atol))
+    return fail(LME_EINVAL, "DOPRI5 needs rtol > 0 and atol >= 0, finite");
+  if (!std::isfinite(opt->h0) || !(opt->h_min >= 0.0) || !std::isfinite(opt->h_min))
+    return fail(LME_EINVAL, "DOPRI5 needs a finite h0 and h_min >= 0");
+  if (opt->max_steps < 1) return fail(LME_EINVAL, "DOPRI5 needs max_steps >= 1");
+  if (opt->path == LME_PATH_STREAMED)
+    return fail(LME_ENOTSUP, "the streamed DOPRI5 path is not available in this build");
+  if (opt->layout == LME_LAYOUT_COLUMN)
+    return fail(LME_ENOTSUP, "the column layout has no adaptive stepper");
+  if (opt->block != 0 && opt->block != 512)
+    return fail(LME_EINVAL, "the adaptive stepper runs 512-thread workgroups");
+  std::vector<double> stops;
+  std::vector<int32_t> out_idx, seg;
+  int rc = dp5_tables(h, n_t, tlist, &stops, &out_idx, &seg);
+  if (rc) return rc;
+  int max_n2 = 0;
+  for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
+  int epts[16];
+  const int ne = lme_internal_dp5_epts(epts, 16);
+  int EPT = 0;
+  for (int i = 0; i < ne && !EPT; ++i)
+    if (512 * epts[i] >= max_n2) EPT = epts[i];
+  if (!EPT)
+    return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the resident adaptive "
+                "workgroup", max_n2);
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = ensure_device(h))) return rc;
+  // tables: [stops | out_idx | seg], content-cached
+  std::vector<double> key(stops);
+  key.push_back((double)n_t);
+  for (int k = 0; k < n_t; ++k) key.push_back(tlist[k]);
+  const size_t ns = stops.size();
+  if (key != h->stops_key || !h->d_stops.p) {
+    std::vector<uint8_t> buf(ns * 8 + 2 * ns * 4 + 16, 0);
+    std::memcpy(buf.data(), stops.data(), ns * 8);
+    std::memcpy(buf.data() + ns * 8, out_idx.data(), ns * 4);
+    std::memcpy(buf.data() + ns * 12, seg.data(), ns * 4);
+    if ((rc = h->d_stops.upload(buf.data(), buf.size(), "stop tables"))) return rc;
+    h->stops_key.swap(key);
+  }
+  const size_t kbytes = (size_t)7 * h->state_elems * 16;
+  if (h->d_kbuf.bytes < kbytes) {
+    h->d_kbuf.release();
+    hipError_t e = hipMalloc(&h->d_kbuf.p, kbytes);
+    if (e != hipSuccess) {
+      h->d_kbuf.p = nullptr;
+      return fail(LME_ENOMEM, "hipMalloc(stage derivatives, %zu B) failed", kbytes);
+    }
+    h->d_kbuf.bytes = kbytes;
+  }
+  Plan *plan;
+  if ((rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan))) return rc;
+
+  lme::Dp5Args a;
+  std::memset(&a, 0, sizeof a);
+  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
+  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+  a.ops = static_cast<const uint8_t *>(h->d_ops.p);
+  a.eops = static_cast<const uint8_t *>(h->d_eops.p);
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_ctrl = h->n_ctrl;
+  a.n_seg = h->n_seg;
+  a.n_e = h->n_e;
+  a.n_t = n_t;
+  const uint8_t *tb = static_cast<const uint8_t *>(h->d_stops.p);
+  a.stops = reinterpret_cast<const double *>(tb);
+  a.stop_out = reinterpret_cast<const int32_t *>(tb + ns * 8);
+  a.stop_seg = reinterpret_cast<const int32_t *>(tb + ns * 12);
+  a.n_stops = (int32_t)ns;
+  a.t0 = tlist[0];
+  a.rtol = opt->rtol;
+  a.atol = opt->atol;
+  a.h0 = opt->h0;
+  a.h_min = opt->h_min;
+  a.max_steps = opt->max_steps;
+  a.state_elems = h->state_elems;
+  a.kbuf = static_cast<double *>(h->d_kbuf.p);
+  a.rho0 = static_cast<const double *>(rho0_dev);
+  a.rho_out = static_cast<double *>(rho_out_dev);
+  a.states = static_cast<double *>(states_dev);
+  a.expect = static_cast<double *>(expect_dev);
+  a.counts = counts_dev;
+  a.status = status_dev;
+  hipError_t e = lme_internal_launch_dp5(EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
+  if (e != hipSuccess) return hip_fail(e, "launch resident DOPRI5");
+  return LME_OK;
+}
+
 static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
                        const void *rho0_dev, const double *u_dev, void *expect_dev,
                        void *states_dev, void *rho_out_dev, int64_t *counts_dev,
@@ -736,7 +872,8 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
       opt->block != 1024)
     return fail(LME_EINVAL, "block must be 0, 256, 512, 768 or 1024");
   if (opt->method == LME_DOPRI5)
-    return fail(LME_ENOTSUP, "adaptive stepping is not available in this build");
+    return evolve_dp5(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
+                      counts_dev, status_dev, stream);
   if (opt->method != LME_RK4) return fail(LME_EINVAL, "unknown method %d", opt->method);
   if (n_t > 1 && opt->nsteps < 1) return fail(LME_EINVAL, "RK4 needs nsteps >= 1");
   if (opt->path == LME_PATH_STREAMED)
@@ -777,7 +914,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if ((rc = upload_tables(h, tab, s))) return rc;
   hipError_t e;
   Plan *plan;
-  if ((rc = plan_packs(h, T, EPT, 0, T * EPT, column, &plan))) return rc;
+  if ((rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan))) return rc;
 
   lme::Rk4Args a;
   std::memset(&a, 0, sizeof a);
@@ -844,7 +981,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   if (rc) return rc;
   hipError_t e;
   Plan *plan;
-  rc = plan_packs(h, 256, 0, adjoint ? 1 : 0, 1 << 30, 0, &plan);
+  rc = plan_packs(h, 256, 0, adjoint ? 1 : 0, 1 << 30, 0, 0, &plan);
   if (rc) return rc;
   lme::ApplyArgs a;
   std::memset(&a, 0, sizeof a);

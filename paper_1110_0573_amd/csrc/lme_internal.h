@@ -133,6 +133,31 @@ struct Rk4Args {
   int32_t *status;          // [n_inst]
 };
 
+// Per-call arguments of the resident Dormand-Prince kernel.
+struct Dp5Args {
+  const PackDesc *packs;
+  const int32_t *order;
+  const InstDesc *inst;
+  const uint8_t *ops;
+  const uint8_t *eops;
+  const double *u;          // [n_inst][n_ctrl][n_seg] or null
+  int32_t n_ctrl, n_seg, n_e, n_t;
+  const double *stops;      // [n_stops] stop times after t0 (outputs, edges)
+  const int32_t *stop_out;  // [n_stops] output index landed on, or -1
+  const int32_t *stop_seg;  // [n_stops] control segment of the interval ending there
+  int32_t n_stops;
+  double t0, rtol, atol, h0, h_min;
+  int64_t max_steps;
+  int64_t state_elems;
+  double *kbuf;             // [7][state_elems] complex: stage derivatives
+  const double *rho0;
+  double *rho_out;
+  double *states;           // [n_t][state_elems]
+  double *expect;           // [n_inst][n_e][n_t]
+  int64_t *counts;          // [n_inst][2]
+  int32_t *status;          // [n_inst]
+};
+
 // Per-call arguments of the one-shot Liouvillian application.
 struct ApplyArgs {
   const PackDesc *packs;

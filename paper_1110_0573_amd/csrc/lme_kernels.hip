@@ -597,6 +597,411 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Resident Dormand-Prince 5(4) with per-instance step control.
+// One workgroup integrates one pack; each instance has its own t, h,
+// accept/reject history and position in the list of stop points (output
+// times and control edges, which every step lands on exactly).  The stage
+// input is shared through LDS; each thread keeps rho, the stage input and the
+// fifth-order solution of its elements in VGPRs and the seven stage
+// derivatives in a global scratch it alone reads and writes.  Per-instance
+// norms are reduced in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+
+// Dormand & Prince (1980): stage matrix, fifth-order weights (= last row,
+// first-same-as-last) and the embedded fourth-order weights.
+__constant__ double kDpA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+// error weights b_i - bhat_i
+__constant__ double kDpE[7] = {35.0 / 384 - 5179.0 / 57600,
+                               0.0,
+                               500.0 / 1113 - 7571.0 / 16695,
+                               125.0 / 192 - 393.0 / 640,
+                               -2187.0 / 6784 - (-92097.0 / 339200),
+                               11.0 / 84 - 187.0 / 2100,
+                               0.0 - 1.0 / 40};
+
+// Per-instance step control, in LDS.
+struct DpCtl {
+  double t, h, h_try, hs;
+  int64_t n_acc, n_rej;
+  int32_t stop, status, active, accept, landing, seg, k1_seg, prev_rej, out_due, need_k1;
+};
+
+__host__ __device__ inline int32_t dp_ctl_bytes(int32_t m) {
+  return align16(m * (int32_t)sizeof(DpCtl));
+}
+
+// Sum over each instance's n2 entries of buf (LDS doubles) -> out[b];
+// waves take instances round-robin, lanes stride the entries, then a
+// butterfly: a fixed order.
+template <int T>
+__device__ void per_instance_sum(const double *buf, int m, int n2, double *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int b = wave; b < m; b += T / 64) {
+    double v = 0.0;
+    for (int e = lane; e < n2; e += 64) v += buf[b * n2 + e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) out[b] = v;
+  }
+}
+
+// Expectation values of the instances whose out_due >= 0 (their rho is in Y).
+template <int T>
+__device__ void dp_outputs(const Dp5Args &a, const PackDesc &pk, const PackLds &L,
+                           const DpCtl *ctl) {
+  const int n = pk.n, n2 = n * n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int task = wave; task < pk.m * a.n_e; task += T / 64) {
+    const int b = task / a.n_e, e = task - b * a.n_e;
+    const int k = ctl[b].out_due;
+    if (k < 0) continue;
+    const int id = L.ids[b];
+    const InstDesc &d = a.inst[id];
+    const int we = d.we;
+    const int32_t *Ec = reinterpret_cast<const int32_t *>(a.eops + d.eops_off);
+    const double2 *Ev = reinterpret_cast<const double2 *>(
+        a.eops + d.eops_off + eops_val_offset(n, we, a.n_e));
+    const double2 *Y = L.Y + b * n2;
+    double2 part = make_double2(0.0, 0.0);
+    for (int i = lane; i < n; i += 64)
+      for (int w = 0; w < we; ++w) {
+        const int idx = (e * we + w) * n + i;
+        part = cfma(Ev[idx], Y[Ec[idx] * n + i], part);
+      }
+    part = wave_sum(part);
+    if (lane == 0) {
+      double *dst = a.expect + 2 * (((int64_t)id * a.n_e + e) * a.n_t + k);
+      dst[0] = part.x;
+      dst[1] = part.y;
+    }
+  }
+}
+
+template <int T, int EPT>
+__global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, E = pk.m * n2, m = pk.m;
+  const PackLds L = carve(smem, pk);
+  DpCtl *ctl = reinterpret_cast<DpCtl *>(smem + pack_lds_bytes(n, m, pk.blob_bytes, pk.nb));
+  double *red = reinterpret_cast<double *>(L.Y);   // reduction scratch aliases Y
+  double *sums = reinterpret_cast<double *>(L.u);  // (reused only when nb == 0: see below)
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  const int tid = threadIdx.x;
+  double2 *K = reinterpret_cast<double2 *>(a.kbuf);
+  const int64_t SE = a.state_elems;
+  (void)sums;
+
+  for (int b = tid; b < m; b += T) {
+    const int id = a.order[pk.first + b];
+    L.ids[b] = id;
+    L.off[b] = a.inst[id].rho_off;
+    if (a.status) a.status[id] = 0;
+    DpCtl c;
+    c.t = a.t0;
+    c.h = a.h0;
+    c.h_try = 0.0;
+    c.hs = 0.0;
+    c.n_acc = c.n_rej = 0;
+    c.stop = 0;
+    c.status = 0;
+    c.active = a.n_stops > 0;
+    c.accept = c.landing = 0;
+    c.seg = -1;
+    c.k1_seg = -2;
+    c.prev_rej = 0;
+    c.out_due = 0;   // the initial state is output 0
+    c.need_k1 = 1;
+    ctl[b] = c;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, 0);
+  __syncthreads();
+
+  double2 rho[EPT], yn[EPT], y5[EPT];
+  uint32_t bij[EPT];
+  const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int f = tid + s * T;
+    rho[s] = make_double2(0.0, 0.0);
+    bij[s] = 0;
+    if (f < E) {
+      const int b = f / n2, r = f - b * n2;
+      const int i = r / n;
+      bij[s] = pack_bij(b, i, r - i * n);
+      rho[s] = rho0[L.off[b] + r];
+    }
+  }
+  auto goff = [&](uint32_t v) { return L.off[slot_b(v)] + slot_i(v) * n + slot_j(v); };
+  auto set_controls = [&](int b, int seg) {
+    for (int q = 0; q < pk.nb; ++q)
+      L.u[b * pk.nb + q] =
+          seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+  };
+  // writes rho of every instance with a due output to Y, then the outputs
+  auto outputs = [&]() {
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      const int f = tid + s * T;
+      if (f < E) {
+        const int b = slot_b(bij[s]);
+        const int k = ctl[b].out_due;
+        if (k >= 0) {
+          L.Y[f] = rho[s];
+          if (a.states)
+            reinterpret_cast<double2 *>(a.states)[(int64_t)k * SE + goff(bij[s])] = rho[s];
+        }
+      }
+    }
+    __syncthreads();
+    if (a.expect && a.n_e > 0) dp_outputs<T>(a, pk, L, ctl);
+    __syncthreads();
+    for (int b = tid; b < m; b += T) ctl[b].out_due = -1;
+    __syncthreads();
+  };
+  auto elem = [&](int s, const double2 &y) {
+    uint32_t v = bij[s];
+    asm volatile("" : "+v"(v));  // no per-slot addresses hoisted across steps
+    const int b = slot_b(v);
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+    return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), y, L.u + b * pk.nb);
+  };
+
+  outputs();
+  if (a.n_stops == 0) goto finish;
+
+  // Starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4) in
+  // the scaled RMS norm, exponent 1/5, with the controls of the first interval.
+  if (a.h0 <= 0.0) {
+    for (int b = tid; b < m; b += T) set_controls(b, a.n_seg > 0 ? a.stop_seg[0] : -1);
+#pragma unroll
+    for (int s = 0; s < EPT; ++s)
+      if (tid + s * T < E) L.Y[tid + s * T] = rho[s];
+    __syncthreads();
+    double2 (&f0)[EPT] = y5;  // the stage arrays are idle until the first step
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      f0[s] = make_double2(0.0, 0.0);
+      if (tid + s * T < E) {
+        f0[s] = elem(s, rho[s]);
+        K[goff(bij[s])] = f0[s];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      const int f = tid + s * T;
+      if (f < E) {
+        const double sc = a.atol + a.rtol * hypot(rho[s].x, rho[s].y);
+        const double r0 = hypot(rho[s].x, rho[s].y) / sc, r1 = hypot(f0[s].x, f0[s].y) / sc;
+        red[f] = r0 * r0;
+        red[E + f] = r1 * r1;
+      }
+    }
+    __syncthreads();
+    double *d01 = reinterpret_cast<double *>(ctl + m);  // 2m doubles after ctl
+    per_instance_sum<T>(red, m, n2, d01);
+    per_instance_sum<T>(red + E, m, n2, d01 + m);
+    __syncthreads();
+    for (int b = tid; b < m; b += T) {
+      const double d0 = sqrt(d01[b] / n2), d1 = sqrt(d01[m + b] / n2);
+      ctl[b].hs = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+      ctl[b].t = d1;  // keep d1 until h is set
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EPT; ++s)
+      if (tid + s * T < E) {
+        const double hs = ctl[slot_b(bij[s])].hs;
+        L.Y[tid + s * T] = caxpy(hs, f0[s], rho[s]);
+      }
+    __syncthreads();
+    double2 (&f1)[EPT] = yn;
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      f1[s] = make_double2(0.0, 0.0);
+      if (tid + s * T < E) f1[s] = elem(s, L.Y[tid + s * T]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      const int f = tid + s * T;
+      if (f < E) {
+        const double sc = a.atol + a.rtol * hypot(rho[s].x, rho[s].y);
+        const double r2 = hypot(f1[s].x - f0[s].x, f1[s].y - f0[s].y) / sc;
+        red[f] = r2 * r2;
+      }
+    }
+    __syncthreads();
+    per_instance_sum<T>(red, m, n2, d01);
+    __syncthreads();
+    for (int b = tid; b < m; b += T) {
+      DpCtl &c = ctl[b];
+      const double hs = c.hs, d1 = c.t;
+      const double d2 = sqrt(d01[b] / n2) / hs;
+      const double dm = fmax(d1, d2);
+      const double h1 = (dm <= 1e-15) ? fmax(1e-6, hs * 1e-3) : pow(0.01 / dm, 0.2);
+      c.h = fmin(100.0 * hs, h1);
+      c.t = a.t0;
+      c.k1_seg = a.n_seg > 0 ? a.stop_seg[0] : -1;   // f0 is the first step's k1
+    }
+    __syncthreads();
+  }
+
+  for (;;) {
+    __syncthreads();  // the previous step's decision has been applied everywhere
+    // ---- step set-up, one thread per instance
+    int any = 0;
+    for (int b = tid; b < m; b += T) {
+      DpCtl &c = ctl[b];
+      if (c.active) {
+        if (c.n_acc + c.n_rej >= a.max_steps) {
+          c.status = 3;  // LME_EMAXSTEPS
+          c.active = 0;
+        } else if (c.h < a.h_min) {
+          c.status = 4;  // LME_ESTEPUNDERFLOW
+          c.active = 0;
+        } else {
+          const double ts = a.stops[c.stop];
+          c.landing = c.h >= ts - c.t;
+          c.h_try = c.landing ? ts - c.t : c.h;
+          c.seg = a.n_seg > 0 ? a.stop_seg[c.stop] : -1;
+          c.need_k1 = c.k1_seg != c.seg;
+          set_controls(b, c.seg);
+        }
+      }
+      any |= c.active;
+    }
+    if (!__syncthreads_or(any)) break;
+
+    // ---- seven stages
+    for (int st = 0; st < 7; ++st) {
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        const int f = tid + s * T;
+        if (f < E) {
+          const DpCtl &c = ctl[slot_b(bij[s])];
+          if (c.active) {
+            double2 y = rho[s];
+            if (st > 0) {
+              const int64_t g = goff(bij[s]);
+              double2 acc = make_double2(0.0, 0.0);
+              for (int jj = 0; jj < st; ++jj) acc = caxpy(kDpA[st][jj], K[jj * SE + g], acc);
+              y = caxpy(c.h_try, acc, y);
+            }
+            if (st == 6) y5[s] = y;
+            yn[s] = y;
+            L.Y[f] = y;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        const int f = tid + s * T;
+        if (f < E) {
+          const DpCtl &c = ctl[slot_b(bij[s])];
+          if (c.active && (st > 0 || c.need_k1)) K[st * SE + goff(bij[s])] = elem(s, yn[s]);
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- error norm: RMS over the n^2 moduli of e / (atol + rtol max(|rho|, |y5|))
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      const int f = tid + s * T;
+      if (f < E) {
+        const DpCtl &c = ctl[slot_b(bij[s])];
+        double v = 0.0;
+        if (c.active) {
+          const int64_t g = goff(bij[s]);
+          double2 e = make_double2(0.0, 0.0);
+          for (int jj = 0; jj < 7; ++jj) e = caxpy(kDpE[jj], K[jj * SE + g], e);
+          e = make_double2(c.h_try * e.x, c.h_try * e.y);
+          const double sc =
+              a.atol + a.rtol * fmax(hypot(rho[s].x, rho[s].y), hypot(y5[s].x, y5[s].y));
+          const double r = hypot(e.x, e.y) / sc;
+          v = r * r;
+        }
+        red[f] = v;
+      }
+    }
+    __syncthreads();
+    double *errs = reinterpret_cast<double *>(ctl + m);
+    per_instance_sum<T>(red, m, n2, errs);
+    __syncthreads();
+    int due = 0;
+    for (int b = tid; b < m; b += T) {
+      DpCtl &c = ctl[b];
+      c.accept = 0;
+      if (!c.active) continue;
+      const double err = sqrt(errs[b] / n2);
+      c.k1_seg = c.seg;  // k1 now holds f(rho) for this segment
+      if (!isfinite(err)) {
+        c.status = 5;  // LME_ENONFINITE
+        c.active = 0;
+      } else if (err <= 1.0) {
+        c.accept = 1;
+        ++c.n_acc;
+        double fac = (err == 0.0) ? 10.0 : 0.9 * pow(err, -0.2);
+        fac = fmin(10.0, fmax(0.2, fac));
+        if (c.prev_rej && fac > 1.0) fac = 1.0;
+        c.prev_rej = 0;
+        c.h = c.h_try * fac;
+        if (c.landing) {
+          c.t = a.stops[c.stop];
+          c.out_due = a.stop_out[c.stop];
+          due |= c.out_due >= 0;
+          if (++c.stop == a.n_stops) c.active = 0;
+        } else {
+          c.t += c.h_try;
+        }
+      } else {
+        ++c.n_rej;
+        c.prev_rej = 1;
+        c.h = c.h_try * fmax(0.2, 0.9 * pow(err, -0.2));
+      }
+    }
+    due = __syncthreads_or(due);
+    // ---- accepted instances move to the fifth-order solution; k7 -> k1
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      const int f = tid + s * T;
+      if (f < E && ctl[slot_b(bij[s])].accept) {
+        rho[s] = y5[s];
+        const int64_t g = goff(bij[s]);
+        K[g] = K[6 * SE + g];
+      }
+    }
+    if (due) outputs();
+  }
+
+finish:
+  __syncthreads();
+  if (a.rho_out) {
+#pragma unroll
+    for (int s = 0; s < EPT; ++s)
+      if (tid + s * T < E) reinterpret_cast<double2 *>(a.rho_out)[goff(bij[s])] = rho[s];
+  }
+  for (int b = tid; b < m; b += T) {
+    const int id = L.ids[b];
+    if (a.counts) {
+      a.counts[2 * (int64_t)id] = ctl[b].n_acc;
+      a.counts[2 * (int64_t)id + 1] = ctl[b].n_rej;
+    }
+    if (a.status) a.status[id] = ctl[b].status;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One application of L (or L^+) to every instance, stage input in LDS.
 // ---------------------------------------------------------------------------
 template <int T>
@@ -708,6 +1113,40 @@ extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, in
 
 extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb) {
   return (wo == 1 && nc == 2) || (wo == 1 && nc == 3) || (wo == 2 && nc == 2 && nb == 0);
+}
+
+template <int T, int EPT>
+static hipError_t launch_dp5_t(const lme::Dp5Args &a, int n_packs, int lds, hipStream_t s) {
+  auto k = lme::dp5_resident_kernel<T, EPT>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(T), lds, s, a);
+  return hipGetLastError();
+}
+
+// Resident Dormand-Prince: 512 threads, EPT elements per thread.
+extern "C" int lme_internal_dp5_epts(int *ept, int cap) {
+  static const int e[] = {1, 2, 4, 8, 16};
+  for (int i = 0; i < 5 && i < cap; ++i) ept[i] = e[i];
+  return 5;
+}
+
+// LDS beyond the pack proper: per-instance step control and 2 m doubles.
+extern "C" int lme_internal_dp5_extra_lds(int m) {
+  return lme::dp_ctl_bytes(m) + lme::align16(16 * m);
+}
+
+extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,
+                                              int lds, hipStream_t s) {
+  switch (EPT) {
+    case 1: return launch_dp5_t<512, 1>(*a, n_packs, lds, s);
+    case 2: return launch_dp5_t<512, 2>(*a, n_packs, lds, s);
+    case 4: return launch_dp5_t<512, 4>(*a, n_packs, lds, s);
+    case 8: return launch_dp5_t<512, 8>(*a, n_packs, lds, s);
+    case 16: return launch_dp5_t<512, 16>(*a, n_packs, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,

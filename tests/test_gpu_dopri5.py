@@ -1,0 +1,116 @@
+"""GPU parity of the adaptive Dormand-Prince path against the oracle.
+
+Both sides run the same controller on the same stop points; their step
+sequences agree up to rounding of the error norm, so the bar is the adaptive
+one: every expectation trace within 1e-6 of the oracle's, relative to the
+trace's largest magnitude.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1110_0573_amd import systems as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1110_0573_amd import lme  # noqa: E402
+
+REL = 1e-6
+
+
+def run(systems, tlist, rtol, atol, **kw):
+    h = lme.Handle(systems)
+    out = h.evolve(h.pack([s.rho0 for s in systems]), tlist, method="dopri5", rtol=rtol,
+                   atol=atol, **kw)
+    torch.cuda.synchronize()
+    return h, out
+
+
+def close(gpu, ora):
+    for m in range(ora.shape[0]):
+        scale = max(np.max(np.abs(ora[m])), 1e-300)
+        assert np.max(np.abs(gpu[m] - ora[m])) <= REL * scale, (m, np.max(np.abs(gpu[m] - ora[m])))
+
+
+def test_dp5_kerr_small():
+    s = S.kerr_system(15, delta=0.5, K=0.3, E=0.4, kappa=0.6)
+    tl = np.linspace(0.0, 5.0, 21)
+    h, out = run([s], tl, 1e-8, 1e-11)
+    r = oracle.dopri5(s, s.rho0, tl, 1e-8, 1e-11)
+    close(out["expect"].cpu().numpy()[0], r["expect"])
+    assert out["status"].cpu().numpy()[0] == 0
+    acc, rej = out["counts"].cpu().numpy()[0]
+    assert abs(acc - r["counts"][0]) <= 0.02 * r["counts"][0] + 2
+
+
+def test_dp5_kerr_full_cutoff_short_horizon():
+    """The headline Kerr cavity (N=60, seeded parameters, rtol 1e-8) on t in [0, 5]."""
+    w = S.kerr_single()
+    s = w.systems[0]
+    tl = np.linspace(0.0, 5.0, 11)
+    h, out = run([s], tl, w.rtol, w.atol)
+    r = oracle.dopri5(s, s.rho0, tl, w.rtol, w.atol)
+    close(out["expect"].cpu().numpy()[0], r["expect"])
+
+
+def test_dp5_batched_ragged_jc_per_instance_control():
+    w = S.jc_sweep(n_inst=20, seed=81, t_end=3.0, n_out=7, coherent=True)
+    h, out = run(w.systems, w.tlist, 1e-7, 1e-10, want_states=True)
+    ex = out["expect"].cpu().numpy()
+    st = h.unpack(out["states"])
+    counts = out["counts"].cpu().numpy()
+    for b, s in enumerate(w.systems):
+        r = oracle.dopri5(s, s.rho0, w.tlist, 1e-7, 1e-10, store_states=True)
+        close(ex[b], r["expect"])
+        assert np.max(np.abs(st[b][-1] - r["states"][-1])) <= 1e-6
+        assert abs(counts[b, 0] - r["counts"][0]) <= 0.05 * r["counts"][0] + 2
+    # instances with different dynamics took different numbers of steps
+    assert len(set(counts[:, 0])) > 1
+
+
+def test_dp5_controls_stop_on_edges():
+    w = S.jc_drive(n_inst=4, N=4, n_seg=6, t_end=1.2, steps_per_seg=1, sigma_u=0.8)
+    tl = np.array([0.0, 0.5, 1.2])
+    h, out = run(w.systems, tl, 1e-9, 1e-12)
+    ex = out["expect"].cpu().numpy()
+    for b, s in enumerate(w.systems):
+        r = oracle.dopri5(s, s.rho0, tl, 1e-9, 1e-12)
+        close(ex[b], r["expect"])
+
+
+def test_dp5_given_first_step_and_general_operators():
+    systems = [S.random_system(n, n_c=2, seed=300 + n) for n in (2, 5, 8)]
+    tl = np.linspace(0.0, 1.0, 5)
+    h, out = run(systems, tl, 1e-8, 1e-11, h0=1e-3)
+    ex = out["expect"].cpu().numpy()
+    for b, s in enumerate(systems):
+        r = oracle.dopri5(s, s.rho0, tl, 1e-8, 1e-11, h0=1e-3)
+        close(ex[b], r["expect"])
+
+
+def test_dp5_device_status_codes():
+    s = S.jc_system(3, g=0.4, kappa=0.3, gamma=0.2)
+    tl = np.array([0.0, 3.0])
+    _, o = run([s], tl, 1e-8, 1e-11, max_steps=1)
+    assert o["status"].cpu().numpy()[0] == lme.LME_EMAXSTEPS
+    _, o = run([s], tl, 1e-8, 1e-11, h_min=1.0)
+    assert o["status"].cpu().numpy()[0] == lme.LME_ESTEPUNDERFLOW
+    bad = s.rho0.copy()
+    bad[0, 0] = np.nan
+    h = lme.Handle([s, s])
+    o = h.evolve(h.pack([bad, s.rho0]), tl, method="dopri5", rtol=1e-8, atol=1e-11)
+    torch.cuda.synchronize()
+    st = o["status"].cpu().numpy()
+    assert st[0] == lme.LME_ENONFINITE and st[1] == 0
+
+
+def test_dp5_rejects_bad_options():
+    s = S.jc_system(3)
+    h = lme.Handle([s])
+    with pytest.raises(lme.LmeError) as e:
+        h.evolve(h.pack([s.rho0]), np.array([0.0, 1.0]), method="dopri5", rtol=0.0)
+    assert e.value.code == lme.LME_EINVAL
