@@ -221,6 +221,28 @@ int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
               const double *u_dev, const void *y_dev, void *out_dev,
               void *stream);
 
+/* Cost and gradient for optimal control of piecewise-constant drives.
+ * Integrates every instance with fixed-step RK4 (nsteps equal steps on
+ * [t0, t1]; every control edge inside must be on that grid, else LME_EGRID)
+ * and returns J_b = Re Tr(O_b rho_b(t1)) and dJ_b/du_b[j][s] for every control
+ * term j and segment s: the exact derivative of the discrete RK4 map,
+ * obtained by its adjoint (backward recurrence with L^+, the Hilbert-Schmidt
+ * adjoint of the Liouvillian of Eq. (master_equation)).  A checkpoint of rho
+ * is kept every ckpt_every steps; the stage inputs of one checkpoint interval
+ * are recomputed during the backward pass.
+ *   rho0_dev, O_dev: packed complex128 (lme_layout); O_b is any n x n matrix
+ *                    (a projector |target><target| gives the fidelity);
+ *   u_dev: device [n_inst][n_ctrl][n_seg], or NULL for the create-time values;
+ *   cost_dev: device double [n_inst]; grad_dev: device double
+ *             [n_inst][n_ctrl][n_seg] (overwritten).
+ * Needs 1 <= n_ctrl <= 2 control terms and n_seg >= 1 (LME_ENOTSUP /
+ * LME_EINVAL otherwise).  Device scratch: (ceil(nsteps/ckpt_every) +
+ * 4 ckpt_every) x 16 x state_elems bytes, owned by the handle.
+ * Asynchronous on `stream`. */
+int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, double t1,
+                  const void *rho0_dev, const void *O_dev, const double *u_dev,
+                  double *cost_dev, double *grad_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,8 @@ extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, in
                                                      int lds, hipStream_t s);
 extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
 extern "C" int lme_internal_dp5_epts(int *ept, int cap);
+extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradArgs *a,
+                                               int n_packs, int lds, hipStream_t s);
 extern "C" int lme_internal_dp5_extra_lds(int m);
 extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,
                                               int lds, hipStream_t s);
@@ -218,6 +220,8 @@ struct lme_ctx {
   std::vector<double> stops_key;
   DevBuf d_stops;
   DevBuf d_kbuf;
+  // gradient: checkpoints and one interval of stage inputs
+  DevBuf d_ckpt;
   ~lme_ctx() {
     for (Plan *p : plans) delete p;
   }
@@ -530,11 +534,15 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       *out = p;
       return LME_OK;
     }
+  // adjoint: 0 forward blobs, 1 adjoint blobs, 2 both (gradient kernel)
   auto key = [&](const InstDesc &d) {
-    const lme::Signature &s = adjoint ? d.adj : d.fwd;
-    return std::make_tuple(s.n, s.wo, s.nb, s.wb, s.nc, s.wc);
+    const lme::Signature &s = adjoint == 1 ? d.adj : d.fwd;
+    const lme::Signature &t = d.adj;
+    return std::make_tuple(s.n, s.wo, s.nb, s.wb, s.nc, s.wc,
+                           adjoint == 2 ? t.wo : 0, adjoint == 2 ? t.wb : 0,
+                           adjoint == 2 ? t.wc : 0);
   };
-  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int32_t>> groups;
+  std::map<std::tuple<int, int, int, int, int, int, int, int, int>, std::vector<int32_t>> groups;
   for (int b = 0; b < h->n_inst; ++b) groups[key(h->inst[b])].push_back(b);
 
   std::unique_ptr<Plan> p(new Plan);
@@ -546,19 +554,21 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
   p->dp = dp;
   // LDS of a pack of m instances (the adaptive kernel adds its step control)
   auto pack_lds = [&](int n, int m, int blob, int nb) {
-    return lme_internal_pack_lds_bytes(n, m, blob, nb) + (dp ? lme_internal_dp5_extra_lds(m) : 0);
+    return lme_internal_pack_lds_bytes(n, m, blob, nb) +
+           (dp == 1 ? lme_internal_dp5_extra_lds(m) : dp == 2 ? lme::align16(8 * m) : 0);
   };
   for (auto &g : groups) {
     const InstDesc &d0 = h->inst[g.second[0]];
-    const lme::Signature &s = adjoint ? d0.adj : d0.fwd;
-    const int blob = adjoint ? d0.adj_bytes : d0.fwd_bytes;
+    const lme::Signature &s = adjoint == 1 ? d0.adj : d0.fwd;
+    const int blob = adjoint == 1 ? d0.adj_bytes
+                     : adjoint == 2 ? d0.fwd_bytes + d0.adj_bytes : d0.fwd_bytes;
     const int n = s.n;
     const int64_t n2 = (int64_t)n * n;
     const int cnt = (int)g.second.size();
     auto lds_fit = [&](int64_t m) {
       // at most kMaxPack instances (the kernels encode the pack slot in 10 bits)
       m = std::min<int64_t>(m, lme::kMaxPack);
-      const int64_t per_inst = 16 * n2 + blob + 8LL * s.nb + 12 + (dp ? 128 : 0);
+      const int64_t per_inst = 16 * n2 + blob + 8LL * s.nb + 12 + (dp ? 128 : 0);  // upper bound
       m = std::min<int64_t>(m, std::max<int64_t>(0, (h->lds_limit - 48) / per_inst));
       while (m > 0 && pack_lds(n, (int)m, blob, s.nb) > h->lds_limit) --m;
       return (int)m;
@@ -601,6 +611,10 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       pk.lds_bytes = pack_lds(n, m, blob, s.nb);
       pk.G = G;
       pk.ept = G > 0 ? (n + G - 1) / G : 0;
+      pk.awo = d0.adj.wo;
+      pk.awb = d0.adj.wb;
+      pk.awc = d0.adj.wc;
+      pk.fwd_bytes = d0.fwd_bytes;
       for (int r = 0; r < m; ++r) p->order.push_back(g.second[done + r]);
       done += m;
       p->packs.push_back(pk);
@@ -1005,6 +1019,93 @@ extern "C" int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
                          const double *u_dev, const void *y_dev, void *out_dev, void *stream) {
   try {
     return apply_impl(h, form, adjoint, t, u_dev, y_dev, out_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cost and gradient (discrete adjoint of RK4)
+// ---------------------------------------------------------------------------
+static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, double t1,
+                          const void *rho0_dev, const void *O_dev, const double *u_dev,
+                          double *cost_dev, double *grad_dev, void *stream) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (!rho0_dev || !O_dev || !cost_dev || !grad_dev)
+    return fail(LME_EINVAL, "rho0, O, cost and grad must be device pointers");
+  if (nsteps < 1 || ckpt_every < 1) return fail(LME_EINVAL, "need nsteps >= 1 and ckpt_every >= 1");
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 > t0))
+    return fail(LME_EINVAL, "need finite t0 < t1");
+  if (h->n_ctrl < 1 || h->n_seg < 1)
+    return fail(LME_EINVAL, "the gradient needs control terms and segments");
+  if (h->n_ctrl > 2) return fail(LME_ENOTSUP, "the gradient kernel takes at most 2 control terms");
+  const double hstep = (t1 - t0) / nsteps;
+  const double tl[2] = {t0, t1};
+  std::vector<int32_t> tab;
+  int rc = rk4_tables(h, 2, tl, nsteps, hstep, &tab);
+  if (rc) return rc;
+  int max_n2 = 0;
+  for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
+  int EPT = 0;
+  for (int e : {1, 2, 4, 8})
+    if (!EPT && 512 * e >= max_n2) EPT = e;
+  if (!EPT)
+    return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the gradient workgroup",
+                max_n2);
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = ensure_device(h))) return rc;
+  if ((rc = upload_tables(h, tab, s))) return rc;
+  const int n_ck = (nsteps + ckpt_every - 1) / ckpt_every;
+  const size_t ck_bytes = (size_t)n_ck * h->state_elems * 16;
+  const size_t sb_bytes = (size_t)4 * ckpt_every * h->state_elems * 16;
+  if (h->d_ckpt.bytes < ck_bytes + sb_bytes) {
+    h->d_ckpt.release();
+    hipError_t e = hipMalloc(&h->d_ckpt.p, ck_bytes + sb_bytes);
+    if (e != hipSuccess) {
+      h->d_ckpt.p = nullptr;
+      return fail(LME_ENOMEM, "hipMalloc(checkpoints, %zu B) failed", ck_bytes + sb_bytes);
+    }
+    h->d_ckpt.bytes = ck_bytes + sb_bytes;
+  }
+  Plan *plan;
+  if ((rc = plan_packs(h, 512, EPT, 2, 512 * EPT, 0, 2, &plan))) return rc;
+  lme::GradArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
+  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+  a.ops = static_cast<const uint8_t *>(h->d_ops.p);
+  a.adj = static_cast<const uint8_t *>(h->d_adj.p);
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_ctrl = h->n_ctrl;
+  a.n_seg = h->n_seg;
+  a.seg_of_step = static_cast<const int32_t *>(h->d_steps.p);
+  a.nsteps = nsteps;
+  a.ckpt_every = ckpt_every;
+  a.h = hstep;
+  a.state_elems = h->state_elems;
+  a.rho0 = static_cast<const double *>(rho0_dev);
+  a.O = static_cast<const double *>(O_dev);
+  a.ckpt = static_cast<double *>(h->d_ckpt.p);
+  a.stages = reinterpret_cast<double *>(static_cast<uint8_t *>(h->d_ckpt.p) + ck_bytes);
+  a.cost = cost_dev;
+  a.grad = grad_dev;
+  hipError_t e = lme_internal_launch_grad(EPT, h->n_ctrl, &a, (int)plan->packs.size(),
+                                          plan->max_lds, s);
+  if (e != hipSuccess) return hip_fail(e, "launch gradient");
+  return LME_OK;
+}
+
+extern "C" int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0,
+                             double t1, const void *rho0_dev, const void *O_dev,
+                             const double *u_dev, double *cost_dev, double *grad_dev,
+                             void *stream) {
+  try {
+    return cost_grad_impl(h, nsteps, ckpt_every, t0, t1, rho0_dev, O_dev, u_dev, cost_dev,
+                          grad_dev, stream);
   } catch (const std::bad_alloc &) {
     return fail(LME_ENOMEM, "out of host memory");
   } catch (...) {

@@ -100,6 +100,8 @@ struct PackDesc {
   int32_t lds_bytes;  // total dynamic LDS this pack needs
   int32_t G;          // column-owner kernels: row groups (threads per column)
   int32_t ept;        // column-owner kernels: rows per thread, ceil(n / G)
+  int32_t awo, awb, awc;  // gradient kernel: widths of the adjoint blob
+  int32_t fwd_bytes;      // gradient kernel: forward part of blob_bytes
 };
 
 // Column-owner kernels hold one column's operator entries in registers; they
@@ -156,6 +158,28 @@ struct Dp5Args {
   double *expect;           // [n_inst][n_e][n_t]
   int64_t *counts;          // [n_inst][2]
   int32_t *status;          // [n_inst]
+};
+
+// Per-call arguments of the resident cost-gradient kernel.
+constexpr int kMaxGradCtrl = 4;
+struct GradArgs {
+  const PackDesc *packs;    // packs over the forward signature
+  const int32_t *order;
+  const InstDesc *inst;
+  const uint8_t *ops;       // forward op pool
+  const uint8_t *adj;       // adjoint op pool
+  const double *u;          // [n_inst][n_ctrl][n_seg]
+  int32_t n_ctrl, n_seg;
+  const int32_t *seg_of_step;  // [nsteps]
+  int32_t nsteps, ckpt_every;
+  double h;
+  int64_t state_elems;
+  const double *rho0;
+  const double *O;          // packed like the states
+  double *ckpt;             // [n_ckpt][state_elems] complex
+  double *stages;           // [ckpt_every][4][state_elems] complex
+  double *cost;             // [n_inst]
+  double *grad;             // [n_inst][n_ctrl][n_seg]
 };
 
 // Per-call arguments of the one-shot Liouvillian application.

@@ -1002,6 +1002,289 @@ finish:
 }
 
 // ---------------------------------------------------------------------------
+// Cost J = Re Tr(O rho(t1)) under fixed-step RK4 and its gradient with
+// respect to the piecewise-constant amplitudes, by the discrete adjoint of
+// the RK4 map.  One workgroup per pack: forward pass with a checkpoint every
+// ckpt_every steps; backward pass over the checkpoint intervals in reverse,
+// each first recomputing its stage inputs Y_1..Y_4 into global scratch, then
+// stepping back with
+//   kappa_4 = h/6 lambda,              w_4 = L^+ kappa_4,
+//   kappa_3 = h/3 lambda + h   w_4,    w_3 = L^+ kappa_3,
+//   kappa_2 = h/3 lambda + h/2 w_3,    w_2 = L^+ kappa_2,
+//   kappa_1 = h/6 lambda + h/2 w_2,    w_1 = L^+ kappa_1,
+//   lambda <- lambda + w_1 + w_2 + w_3 + w_4,
+//   dJ/du_q[seg] += sum_i Re <kappa_i, -i[H_q, Y_i]>,
+// starting from lambda = O^+ (the gradient of Re Tr(O rho) under the real
+// inner product Re Tr(X^+ Y)).  -i[H_q, Y] is the two-sided control term
+// B_q Y + Y B_q^+ of the forward operator blob.  The blobs of a pack hold the
+// forward operators followed by the adjoint ones.
+// ---------------------------------------------------------------------------
+template <int T, int EPT, int NQ>
+__global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, E = pk.m * n2, m = pk.m;
+  const PackLds L = carve(smem, pk);
+  double *sums = reinterpret_cast<double *>(smem + pack_lds_bytes(n, m, pk.blob_bytes, pk.nb));
+  double *red = reinterpret_cast<double *>(L.Y);
+  const BlobLayout BF = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  const BlobLayout BA = blob_layout(n, pk.awo, pk.nb, pk.awb, pk.nc, pk.awc);
+  const int tid = threadIdx.x;
+  const int64_t SE = a.state_elems;
+  const double h = a.h;
+
+  {  // forward blob then adjoint blob of every instance
+    const int nv = pk.blob_bytes / 16, nf = pk.fwd_bytes / 16;
+    for (int idx = tid; idx < m * nv; idx += T) {
+      const int b = idx / nv, r = idx - b * nv;
+      const InstDesc &d = a.inst[a.order[pk.first + b]];
+      const uint4 *src = r < nf ? reinterpret_cast<const uint4 *>(a.ops + d.ops_off) + r
+                                : reinterpret_cast<const uint4 *>(a.adj + d.adj_off) + (r - nf);
+      reinterpret_cast<uint4 *>(L.blobs + (size_t)b * pk.blob_bytes)[r] = *src;
+    }
+  }
+  for (int b = tid; b < m; b += T) {
+    const int id = a.order[pk.first + b];
+    L.ids[b] = id;
+    L.off[b] = a.inst[id].rho_off;
+    for (int q = 0; q < a.n_ctrl * a.n_seg; ++q) a.grad[(int64_t)id * a.n_ctrl * a.n_seg + q] = 0.0;
+  }
+  __syncthreads();
+
+  double2 rho[EPT], acc[EPT], yn[EPT];
+  uint32_t bij[EPT];
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    const int f = tid + s * T;
+    rho[s] = make_double2(0.0, 0.0);
+    bij[s] = 0;
+    if (f < E) {
+      const int b = f / n2, r = f - b * n2;
+      const int i = r / n;
+      bij[s] = pack_bij(b, i, r - i * n);
+      rho[s] = reinterpret_cast<const double2 *>(a.rho0)[L.off[b] + r];
+    }
+  }
+  auto valid = [&](int s) { return tid + s * T < E; };
+  auto goff = [&](uint32_t v) { return L.off[slot_b(v)] + slot_i(v) * n + slot_j(v); };
+  auto set_u = [&](int st) {  // between two barriers
+    const int seg = a.seg_of_step[st];
+    for (int idx = tid; idx < m * pk.nb; idx += T) {
+      const int b = idx / pk.nb, q = idx - b * pk.nb;
+      L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+    }
+  };
+  // element of L y (fwd) or L^+ y (adjoint) for slot s; Y holds the input
+  auto apply = [&](int s, const double2 &yij, bool adjoint) {
+    uint32_t v = bij[s];
+    asm volatile("" : "+v"(v));
+    const int b = slot_b(v);
+    const uint8_t *blob = L.blobs + (size_t)b * pk.blob_bytes;
+    const OpView op = adjoint ? make_view(blob + pk.fwd_bytes, BA) : make_view(blob, BF);
+    return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), yij, L.u + b * pk.nb);
+  };
+
+  // ---- forward pass with checkpoints
+  double2 *ck = reinterpret_cast<double2 *>(a.ckpt);
+  for (int st = 0; st < a.nsteps; ++st) {
+    if (st % a.ckpt_every == 0) {
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) ck[(int64_t)(st / a.ckpt_every) * SE + goff(bij[s])] = rho[s];
+    }
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) {
+      yn[s] = rho[s];
+      acc[s] = make_double2(0.0, 0.0);
+    }
+    for (int stage = 0; stage < 4; ++stage) {
+      const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
+      const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+      __syncthreads();
+      if (stage == 0) set_u(st);
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) L.Y[tid + s * T] = yn[s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) {
+          const double2 kv = apply(s, yn[s], false);
+          acc[s] = caxpy(wgt, kv, acc[s]);
+          yn[s] = caxpy(cnext, kv, rho[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < EPT; ++s) rho[s] = caxpy(h / 6.0, acc[s], rho[s]);
+  }
+
+  // ---- cost: J = Re sum_ij O_ij rho_ji ; lambda = O^+
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < EPT; ++s)
+    if (valid(s)) L.Y[tid + s * T] = rho[s];
+  __syncthreads();
+  const double2 *O = reinterpret_cast<const double2 *>(a.O);
+  double2 lam[EPT];
+  double part[EPT];
+#pragma unroll
+  for (int s = 0; s < EPT; ++s) {
+    lam[s] = make_double2(0.0, 0.0);
+    part[s] = 0.0;
+    if (valid(s)) {
+      const uint32_t v = bij[s];
+      const int b = slot_b(v), i = slot_i(v), j = slot_j(v);
+      const double2 oij = O[L.off[b] + i * n + j];
+      const double2 rji = L.Y[b * n2 + j * n + i];
+      part[s] = oij.x * rji.x - oij.y * rji.y;
+      lam[s] = cconj(O[L.off[b] + j * n + i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < EPT; ++s)
+    if (valid(s)) red[tid + s * T] = part[s];
+  __syncthreads();
+  per_instance_sum<T>(red, m, n2, sums);
+  __syncthreads();
+  for (int b = tid; b < m; b += T) a.cost[L.ids[b]] = sums[b];
+
+  // ---- backward pass
+  const double ck_kap_l[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0};
+  const double ck_kap_w[4] = {0.5 * h, 0.5 * h, h, 0.0};  // coefficient of w_{i+1}
+  double gacc[EPT][NQ];
+#pragma unroll
+  for (int s = 0; s < EPT; ++s)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) gacc[s][q] = 0.0;
+  int cur_seg = -1;
+  // adds every slot's accumulated gradient of segment cur_seg to grad
+  auto flush = [&]() {
+    for (int q = 0; q < NQ; ++q) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < EPT; ++s)
+        if (valid(s)) red[tid + s * T] = gacc[s][q];
+      __syncthreads();
+      per_instance_sum<T>(red, m, n2, sums);
+      __syncthreads();
+      if (cur_seg >= 0)
+        for (int b = tid; b < m; b += T)
+          a.grad[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + cur_seg] += sums[b];
+    }
+#pragma unroll
+    for (int s = 0; s < EPT; ++s)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) gacc[s][q] = 0.0;
+  };
+  double2 *SB = reinterpret_cast<double2 *>(a.stages);
+  const int n_ck = (a.nsteps + a.ckpt_every - 1) / a.ckpt_every;
+  for (int c = n_ck - 1; c >= 0; --c) {
+    const int s0 = c * a.ckpt_every, s1 = min(s0 + a.ckpt_every, a.nsteps);
+    // recompute the stage inputs of steps s0..s1-1
+#pragma unroll
+    for (int s = 0; s < EPT; ++s)
+      if (valid(s)) rho[s] = ck[(int64_t)c * SE + goff(bij[s])];
+    for (int st = s0; st < s1; ++st) {
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        yn[s] = rho[s];
+        acc[s] = make_double2(0.0, 0.0);
+      }
+      for (int stage = 0; stage < 4; ++stage) {
+        const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
+        const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+        __syncthreads();
+        if (stage == 0) set_u(st);
+#pragma unroll
+        for (int s = 0; s < EPT; ++s)
+          if (valid(s)) {
+            L.Y[tid + s * T] = yn[s];
+            SB[((int64_t)(st - s0) * 4 + stage) * SE + goff(bij[s])] = yn[s];
+          }
+        __syncthreads();
+        if (stage < 3) {
+#pragma unroll
+          for (int s = 0; s < EPT; ++s)
+            if (valid(s)) {
+              const double2 kv = apply(s, yn[s], false);
+              acc[s] = caxpy(wgt, kv, acc[s]);
+              yn[s] = caxpy(cnext, kv, rho[s]);
+            }
+        } else {
+#pragma unroll
+          for (int s = 0; s < EPT; ++s)
+            if (valid(s)) acc[s] = caxpy(wgt, apply(s, yn[s], false), acc[s]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) rho[s] = caxpy(h / 6.0, acc[s], rho[s]);
+    }
+    // step back through the interval
+    for (int st = s1 - 1; st >= s0; --st) {
+      const int seg = a.seg_of_step[st];
+      if (seg != cur_seg) {
+        flush();
+        cur_seg = seg;
+      }
+      // acc: w_{i+1} of the previous stage; yn: sum of the w_i
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) {
+        acc[s] = make_double2(0.0, 0.0);
+        yn[s] = make_double2(0.0, 0.0);
+      }
+      for (int stage = 3; stage >= 0; --stage) {
+        double2 kap[EPT];
+#pragma unroll
+        for (int s = 0; s < EPT; ++s)
+          kap[s] = caxpy(ck_kap_w[stage], acc[s],
+                         make_double2(ck_kap_l[stage] * lam[s].x, ck_kap_l[stage] * lam[s].y));
+        // gradient: Re <kappa_i, B_q Y_i>
+        __syncthreads();
+        if (stage == 3) set_u(st);
+#pragma unroll
+        for (int s = 0; s < EPT; ++s)
+          if (valid(s))
+            L.Y[tid + s * T] = SB[((int64_t)(st - s0) * 4 + stage) * SE + goff(bij[s])];
+        __syncthreads();
+        if (seg >= 0) {
+#pragma unroll
+          for (int s = 0; s < EPT; ++s)
+            if (valid(s)) {
+              const uint32_t v = bij[s];
+              const int b = slot_b(v), i = slot_i(v), j = slot_j(v);
+              const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BF);
+              const double2 *Yb = L.Y + b * n2;
+              const double2 yij = Yb[i * n + j];
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) {
+                const double2 bq = two_sided(op.DB + q * n, op.OBval + q * op.wb * n,
+                                             op.OBcol + q * op.wb * n, op.wb, n, Yb, i, j, yij);
+                gacc[s][q] += kap[s].x * bq.x + kap[s].y * bq.y;
+              }
+            }
+        }
+        // w_i = L^+ kappa_i
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < EPT; ++s)
+          if (valid(s)) L.Y[tid + s * T] = kap[s];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < EPT; ++s)
+          if (valid(s)) {
+            acc[s] = apply(s, kap[s], true);
+            yn[s] = cadd(yn[s], acc[s]);
+          }
+      }
+#pragma unroll
+      for (int s = 0; s < EPT; ++s) lam[s] = cadd(lam[s], yn[s]);
+    }
+  }
+  flush();
+}
+
+// ---------------------------------------------------------------------------
 // One application of L (or L^+) to every instance, stage input in LDS.
 // ---------------------------------------------------------------------------
 template <int T>
@@ -1146,6 +1429,27 @@ extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, in
     case 8: return launch_dp5_t<512, 8>(*a, n_packs, lds, s);
     case 16: return launch_dp5_t<512, 16>(*a, n_packs, lds, s);
   }
+  return hipErrorInvalidValue;
+}
+
+template <int T, int EPT, int NQ>
+static hipError_t launch_grad_t(const lme::GradArgs &a, int n_packs, int lds, hipStream_t s) {
+  auto k = lme::grad_resident_kernel<T, EPT, NQ>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(T), lds, s, a);
+  return hipGetLastError();
+}
+
+// Gradient kernel: 512 threads, EPT in {1, 2, 4, 8}, 1 or 2 control terms.
+extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradArgs *a,
+                                               int n_packs, int lds, hipStream_t s) {
+#define LME_G(E, Q) \
+  if (EPT == E && nq == Q) return launch_grad_t<512, E, Q>(*a, n_packs, lds, s);
+  LME_G(1, 1) LME_G(2, 1) LME_G(4, 1) LME_G(8, 1)
+  LME_G(1, 2) LME_G(2, 2) LME_G(4, 2) LME_G(8, 2)
+#undef LME_G
   return hipErrorInvalidValue;
 }
 

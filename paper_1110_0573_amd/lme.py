@@ -28,7 +28,7 @@ LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
-           "lme_last_error", "lme_layout", "lme_evolve", "lme_apply"]
+           "lme_last_error", "lme_layout", "lme_evolve", "lme_apply", "lme_cost_grad"]
 
 
 class LmeError(RuntimeError):
@@ -89,6 +89,9 @@ def load():
                                    C.c_void_p, C.c_void_p, C.c_void_p]
         lib.lme_apply.argtypes = [H, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.lme_cost_grad.argtypes = [H, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]
         _LIB = lib
     return _LIB
 
@@ -259,6 +262,55 @@ class Handle:
                               _ptr(out), _stream_ptr(stream))
         _check(rc, "lme_apply")
         return out
+
+
+def _cost_grad(handle, rho0, O, u, t0, t1, nsteps, ckpt_every, stream=None):
+    import torch
+    dev = rho0.device
+    cost = torch.empty(handle.n_inst, dtype=torch.float64, device=dev)
+    grad = torch.empty((handle.n_inst, handle.n_ctrl, handle.n_seg), dtype=torch.float64,
+                       device=dev)
+    rc = load().lme_cost_grad(handle._h, int(nsteps), int(ckpt_every), float(t0), float(t1),
+                              _ptr(rho0), _ptr(O), _ptr(u), _ptr(cost), _ptr(grad),
+                              _stream_ptr(stream))
+    _check(rc, "lme_cost_grad")
+    return cost, grad
+
+
+class _CostFn:
+    """Holder for the torch.autograd.Function, built on first use."""
+    fn = None
+
+
+def _cost_function():
+    if _CostFn.fn is None:
+        import torch
+
+        class ExpectationCost(torch.autograd.Function):
+            """J(u) = Re Tr(O rho(t1)) per instance; backward multiplies the
+            gradient computed by lme_cost_grad (the discrete adjoint) with the
+            incoming gradient."""
+
+            @staticmethod
+            def forward(ctx, u, handle, rho0, O, t0, t1, nsteps, ckpt_every):
+                cost, grad = _cost_grad(handle, rho0, O, u.detach().contiguous(), t0, t1,
+                                        nsteps, ckpt_every)
+                ctx.save_for_backward(grad)
+                return cost
+
+            @staticmethod
+            def backward(ctx, g):
+                (grad,) = ctx.saved_tensors
+                return (g[:, None, None] * grad, None, None, None, None, None, None, None)
+
+        _CostFn.fn = ExpectationCost
+    return _CostFn.fn
+
+
+def expectation_cost(u, handle, rho0, O, t0, t1, nsteps, ckpt_every=10):
+    """Differentiable J_b(u) = Re Tr(O_b rho_b(t1)) (torch.autograd.Function).
+    u: float64 device tensor [n_inst, n_ctrl, n_seg]; returns [n_inst]."""
+    return _cost_function().apply(u, handle, rho0, O, t0, t1, nsteps, ckpt_every)
 
 
 def raw_create_batch(systems, n_ctrl=None, n_e=None):
