@@ -86,8 +86,10 @@ typedef enum lme_layout_kind {
 
 /* Form of the Liouvillian application used by lme_apply. */
 typedef enum lme_form {
-  LME_FORM_OPERATOR = 0,   /* sparse H, C_k applied to the dense n x n matrix */
-  LME_FORM_SUPEROP = 1     /* explicit n^2 x n^2 CSR superoperator SpMV       */
+  LME_FORM_OPERATOR = 0,   /* sparse H, C_k applied to the dense n x n matrix;
+                              stage input staged in LDS when it fits          */
+  LME_FORM_SUPEROP = 1,    /* explicit n^2 x n^2 CSR superoperator SpMV       */
+  LME_FORM_OPERATOR_STREAMED = 2  /* operator form read straight from HBM     */
 } lme_form;
 
 /* Square sparse matrix in CSR form, host memory.
@@ -214,8 +216,8 @@ int lme_evolve(lme_handle h, const lme_options *opt, int32_t n_t,
  * L^+ x = i[H, x] + sum_k (C_k^+ x C_k - 1/2 {C_k^+ C_k, x}),
  * to every instance of a packed batch at time t:
  *   out_dev = L(t) y_dev   (both complex128, packed; must not overlap).
- *   form: LME_FORM_OPERATOR or LME_FORM_SUPEROP (the latter assembles the
- *         n^2 x n^2 CSR superoperator on first use; forward only).
+ *   form: lme_form (LME_FORM_SUPEROP assembles the n^2 x n^2 CSR
+ *         superoperator on first use; forward only).
  *   u_dev: as in lme_evolve (NULL = amplitudes given at create). */
 int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
               const double *u_dev, const void *y_dev, void *out_dev,
@@ -242,6 +244,33 @@ int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
 int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, double t1,
                   const void *rho0_dev, const void *O_dev, const double *u_dev,
                   double *cost_dev, double *grad_dev, void *stream);
+
+/* Tuning knobs of a handle (schedules only: every setting gives identical
+ * results).  0 in a field means "library default".
+ *   rk4_layout, rk4_block: used by lme_evolve (RK4) when the options leave
+ *                          layout = LME_LAYOUT_AUTO and block = 0;
+ *   apply_cap: elements per workgroup of the LDS-staged application
+ *              (lme_apply, LME_FORM_OPERATOR), 256 .. 65536. */
+typedef struct lme_tuning {
+  int32_t rk4_layout;
+  int32_t rk4_block;
+  int32_t apply_cap;
+  int32_t reserved;
+  double rk4_ms_per_step;   /* lme_autotune: best trial time per RK4 step      */
+  double apply_us;          /* lme_autotune: best trial time per application  */
+} lme_tuning;
+
+int lme_get_tuning(lme_handle h, lme_tuning *t);
+int lme_set_tuning(lme_handle h, const lme_tuning *t);
+
+/* Autotuner.  Times every eligible RK4 configuration (layout x workgroup
+ * size) on a trial of min(opt->nsteps, 40) steps of this batch from rho0_dev,
+ * and every pack size of the LDS-staged application, with HIP events on
+ * `stream`; stores the fastest in the handle and in *result (may be NULL).
+ * Synchronises the stream.  Uses a device scratch of two states.
+ * Errors as lme_evolve. */
+int lme_autotune(lme_handle h, const lme_options *opt, const void *rho0_dev, void *stream,
+                 lme_tuning *result);
 
 #ifdef __cplusplus
 }

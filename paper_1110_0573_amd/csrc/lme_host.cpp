@@ -44,6 +44,11 @@ extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradA
 extern "C" int lme_internal_dp5_extra_lds(int m);
 extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,
                                               int lds, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, int re,
+                                                      const lme::ApplyArgs *a, int n_packs,
+                                                      int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s);
 
@@ -222,6 +227,15 @@ struct lme_ctx {
   DevBuf d_kbuf;
   // gradient: checkpoints and one interval of stage inputs
   DevBuf d_ckpt;
+  // streamed kernels: element tiles
+  std::vector<lme::Tile> tiles;
+  DevBuf d_tiles;
+  // superoperator form (assembled on first use from the folded operators)
+  std::vector<Sparse> A_host;
+  std::vector<std::vector<Sparse>> C_host;
+  DevBuf d_sd, d_scol, d_sval;
+  int apply_cap = 4096;   // elements per pack of the LDS-staged application
+  lme_tuning tuning = {0, 0, 0, 0, 0.0, 0.0};
   ~lme_ctx() {
     for (Plan *p : plans) delete p;
   }
@@ -322,6 +336,7 @@ static int create_impl(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
   *out = nullptr;
   if (n_inst < 1 || !inst) return fail(LME_EINVAL, "n_inst must be >= 1 with a valid array");
   if (n_ctrl < 0 || n_e < 0) return fail(LME_EINVAL, "n_ctrl and n_e must be >= 0");
+  if (n_ctrl > lme::kMaxWidth) return fail(LME_ENOTSUP, "at most %d control terms", lme::kMaxWidth);
   int32_t n_seg = 0;
   std::vector<double> edges;
   if (seg && seg->n_seg > 0) {
@@ -396,6 +411,8 @@ static int create_impl(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
       if (x.width_offdiag() > lme::kMaxWidth || x.dagger().width_offdiag() > lme::kMaxWidth)
         return fail(LME_ENOTSUP, "instance %d: control operator row wider than %d", b, lme::kMaxWidth);
 
+    h->A_host.push_back(A);
+    h->C_host.push_back(C);
     InstDesc &d = h->inst[b];
     d.flags = 0;
     {
@@ -741,6 +758,15 @@ static bool column_eligible(const lme_ctx *h, int *wo, int *nc, int *nb) {
   return true;
 }
 
+// 1 when every instance has real jump coefficients and purely imaginary
+// off-diagonal entries of A and of the control terms.
+static int real_structure(const lme_ctx *h) {
+  for (auto &d : h->inst)
+    if ((d.flags & (lme::kJumpsReal | lme::kOffdiagImag)) != (lme::kJumpsReal | lme::kOffdiagImag))
+      return 0;
+  return 1;
+}
+
 static bool column_fits(const lme_ctx *h, int T, int EPT) {
   for (auto &d : h->inst) {
     const int n = d.n;
@@ -898,11 +924,15 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if ((rc = rk4_tables(h, n_t, tlist, nsteps, hstep, &tab))) return rc;
   if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
     return fail(LME_EINVAL, "unknown layout %d", opt->layout);
+  lme_options tuned = *opt;  // tuned defaults fill the fields left open
+  if (tuned.layout == LME_LAYOUT_AUTO && tuned.block == 0 && h->tuning.rk4_block > 0) {
+    tuned.layout = h->tuning.rk4_layout;
+    tuned.block = h->tuning.rk4_block;
+  }
+  opt = &tuned;
   // column layout: T in {512, 768}; row layout: T in {256, 512, 1024}
-  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0, re = 1;
-  for (auto &d : h->inst)
-    if ((d.flags & (lme::kJumpsReal | lme::kOffdiagImag)) != (lme::kJumpsReal | lme::kOffdiagImag))
-      re = 0;
+  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0;
+  const int re = real_structure(h);
   if (opt->layout != LME_LAYOUT_ROW && column_eligible(h, &wo, &nc, &nb)) {
     for (int c = 1; c >= 0; --c) {   // prefer the 768-thread configuration
       const int cT = lme::kColCfg[c][0], cE = lme::kColCfg[c][1];
@@ -980,29 +1010,43 @@ extern "C" int lme_evolve(lme_handle h, const lme_options *opt, int32_t n_t, con
 // ---------------------------------------------------------------------------
 // single application
 // ---------------------------------------------------------------------------
-static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, const double *u_dev,
-                      const void *y_dev, void *out_dev, void *stream) {
-  if (!h) return fail(LME_EINVAL, "handle is NULL");
-  if (!y_dev || !out_dev) return fail(LME_EINVAL, "y and out must be device pointers");
-  if (y_dev == out_dev) return fail(LME_EINVAL, "y and out must not overlap");
-  if (!std::isfinite(t)) return fail(LME_EINVAL, "t is not finite");
-  if (form != LME_FORM_OPERATOR && form != LME_FORM_SUPEROP)
-    return fail(LME_EINVAL, "unknown form %d", form);
-  if (form == LME_FORM_SUPEROP)
-    return fail(LME_ENOTSUP, "the superoperator form is not available in this build");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  int rc = ensure_device(h);
+static bool column_eligible(const lme_ctx *h, int *wo, int *nc, int *nb);
+static int real_structure(const lme_ctx *h);
+
+// Element tiles of the streamed kernels: 2048 consecutive elements of one
+// instance each, in instance order.
+constexpr int kTileElems = 2048;
+
+static int ensure_tiles(lme_ctx *h) {
+  if (h->d_tiles.p) return LME_OK;
+  std::vector<lme::Tile> t;
+  for (int b = 0; b < h->n_inst; ++b) {
+    const int n2 = h->inst[b].n * h->inst[b].n;
+    for (int e0 = 0; e0 < n2; e0 += kTileElems) {
+      lme::Tile x;
+      x.inst = b;
+      x.e0 = e0;
+      x.e1 = std::min(n2, e0 + kTileElems);
+      x.pad = 0;
+      t.push_back(x);
+    }
+  }
+  int rc = h->d_tiles.upload(t.data(), t.size() * sizeof(lme::Tile), "tiles");
   if (rc) return rc;
-  hipError_t e;
-  Plan *plan;
-  rc = plan_packs(h, 256, 0, adjoint ? 1 : 0, 1 << 30, 0, 0, &plan);
+  h->tiles.swap(t);
+  return LME_OK;
+}
+
+static int apply_streamed(lme_ctx *h, int adjoint, double t, const double *u_dev,
+                          const void *y_dev, void *out_dev, hipStream_t s) {
+  int rc = ensure_tiles(h);
   if (rc) return rc;
-  lme::ApplyArgs a;
+  lme::ApplyGArgs a;
   std::memset(&a, 0, sizeof a);
-  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
-  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.tiles = static_cast<const lme::Tile *>(h->d_tiles.p);
+  a.n_tiles = (int32_t)h->tiles.size();
   a.inst = static_cast<const InstDesc *>(h->d_inst.p);
-  a.adjoint = adjoint ? 1 : 0;
+  a.adjoint = adjoint;
   a.ops = static_cast<const uint8_t *>(adjoint ? h->d_adj.p : h->d_ops.p);
   a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
   a.n_ctrl = h->n_ctrl;
@@ -1010,7 +1054,132 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   a.seg = segment_at(h, t);
   a.y = static_cast<const double *>(y_dev);
   a.out = static_cast<double *>(out_dev);
-  e = lme_internal_launch_apply_lds(&a, (int)plan->packs.size(), plan->max_lds, s);
+  hipError_t e = lme_internal_launch_apply_global(&a, s);
+  return e == hipSuccess ? LME_OK : hip_fail(e, "launch streamed apply");
+}
+
+// Superoperator of one instance in row-major vectorisation, vec(y)[i*n+j] =
+// y_ij:  S = A (x) I + I (x) conj(A) + sum_k C_k (x) conj(C_k), i.e. row (i, j)
+// holds A_il at column (l, j), conj(A_jl) at (i, l) and C_il conj(C_jm) at
+// (l, m) -- the operator form L y = A y + y A^+ + sum_k C_k y C_k^+ written
+// out element by element.
+static void superop_rows(const Sparse &A, const std::vector<Sparse> &C,
+                         std::vector<std::vector<std::pair<int, cd>>> *rows) {
+  const int n = A.n;
+  rows->assign((size_t)n * n, {});
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      std::vector<std::pair<int, cd>> r;
+      for (auto &x : A.rows[i]) r.emplace_back(x.first * n + j, x.second);
+      for (auto &x : A.rows[j]) r.emplace_back(i * n + x.first, std::conj(x.second));
+      for (auto &c : C)
+        for (auto &x : c.rows[i])
+          for (auto &z : c.rows[j]) r.emplace_back(x.first * n + z.first, x.second * std::conj(z.second));
+      std::sort(r.begin(), r.end(), [](const std::pair<int, cd> &a, const std::pair<int, cd> &b) {
+        return a.first < b.first;
+      });
+      std::vector<std::pair<int, cd>> m;
+      for (auto &e : r) {
+        if (!m.empty() && m.back().first == e.first)
+          m.back().second += e.second;
+        else
+          m.push_back(e);
+      }
+      (*rows)[(size_t)i * n + j].swap(m);
+    }
+}
+
+static int ensure_superop(lme_ctx *h) {
+  if (h->d_sd.p) return LME_OK;
+  std::vector<lme::SuperDesc> sd(h->n_inst);
+  std::vector<int32_t> col;
+  std::vector<cd> val;
+  for (int b = 0; b < h->n_inst; ++b) {
+    std::vector<std::vector<std::pair<int, cd>>> rows;
+    superop_rows(h->A_host[b], h->C_host[b], &rows);
+    int w = 0;
+    for (auto &r : rows) w = std::max(w, (int)r.size());
+    const size_t n2 = rows.size();
+    sd[b].col_off = (int64_t)col.size();
+    sd[b].val_off = (int64_t)val.size();
+    sd[b].w = w;
+    sd[b].pad = 0;
+    const size_t base_c = col.size(), base_v = val.size();
+    col.resize(base_c + (size_t)w * n2);
+    val.resize(base_v + (size_t)w * n2, cd(0.0, 0.0));
+    for (size_t e = 0; e < n2; ++e)
+      for (int sl = 0; sl < w; ++sl) {
+        const bool on = sl < (int)rows[e].size();
+        col[base_c + (size_t)sl * n2 + e] = on ? rows[e][sl].first : (int32_t)e;
+        if (on) val[base_v + (size_t)sl * n2 + e] = rows[e][sl].second;
+      }
+  }
+  int rc;
+  if ((rc = h->d_sd.upload(sd.data(), sd.size() * sizeof(lme::SuperDesc), "superop index"))) return rc;
+  if ((rc = h->d_scol.upload(col.data(), col.size() * 4, "superop columns"))) return rc;
+  if ((rc = h->d_sval.upload(val.data(), val.size() * 16, "superop values"))) return rc;
+  return LME_OK;
+}
+
+static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, const double *u_dev,
+                      const void *y_dev, void *out_dev, void *stream) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (!y_dev || !out_dev) return fail(LME_EINVAL, "y and out must be device pointers");
+  if (y_dev == out_dev) return fail(LME_EINVAL, "y and out must not overlap");
+  if (!std::isfinite(t)) return fail(LME_EINVAL, "t is not finite");
+  if (form != LME_FORM_OPERATOR && form != LME_FORM_SUPEROP && form != LME_FORM_OPERATOR_STREAMED)
+    return fail(LME_EINVAL, "unknown form %d", form);
+  if (form == LME_FORM_SUPEROP && (adjoint || h->n_ctrl > 0))
+    return fail(LME_ENOTSUP, "the superoperator form is forward-only and takes no controls");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  adjoint = adjoint ? 1 : 0;
+  if (form == LME_FORM_SUPEROP) {
+    if ((rc = ensure_superop(h)) || (rc = ensure_tiles(h))) return rc;
+    lme::SuperArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.tiles = static_cast<const lme::Tile *>(h->d_tiles.p);
+    a.n_tiles = (int32_t)h->tiles.size();
+    a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+    a.sd = static_cast<const lme::SuperDesc *>(h->d_sd.p);
+    a.col = static_cast<const int32_t *>(h->d_scol.p);
+    a.val = static_cast<const double *>(h->d_sval.p);
+    a.y = static_cast<const double *>(y_dev);
+    a.out = static_cast<double *>(out_dev);
+    hipError_t e = lme_internal_launch_superop(&a, s);
+    return e == hipSuccess ? LME_OK : hip_fail(e, "launch superoperator");
+  }
+  if (form == LME_FORM_OPERATOR_STREAMED)
+    return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
+  // packs of at most apply_cap elements: several workgroups per CU keep
+  // enough HBM reads in flight
+  int max_n2 = 0;
+  for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
+  Plan *plan;
+  rc = plan_packs(h, 256, 0, adjoint, std::max(h->apply_cap, max_n2), 0, 0, &plan);
+  if (rc == LME_ENOTSUP) return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
+  if (rc) return rc;
+  lme::ApplyArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
+  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+  a.adjoint = adjoint;
+  a.ops = static_cast<const uint8_t *>(adjoint ? h->d_adj.p : h->d_ops.p);
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_ctrl = h->n_ctrl;
+  a.n_seg = h->n_seg;
+  a.seg = segment_at(h, t);
+  a.y = static_cast<const double *>(y_dev);
+  a.out = static_cast<double *>(out_dev);
+  int wo, nc, nb;
+  hipError_t e;
+  if (!adjoint && column_eligible(h, &wo, &nc, &nb))
+    e = lme_internal_launch_apply_shape(wo, nc, nb, real_structure(h), &a,
+                                        (int)plan->packs.size(), plan->max_lds, s);
+  else
+    e = lme_internal_launch_apply_lds(&a, (int)plan->packs.size(), plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch apply");
   return LME_OK;
 }
@@ -1106,6 +1275,142 @@ extern "C" int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, d
   try {
     return cost_grad_impl(h, nsteps, ckpt_every, t0, t1, rho0_dev, O_dev, u_dev, cost_dev,
                           grad_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+extern "C" int lme_get_tuning(lme_handle h, lme_tuning *t) {
+  if (!h || !t) return fail(LME_EINVAL, "handle and tuning must not be NULL");
+  *t = h->tuning;
+  t->apply_cap = h->apply_cap;
+  return LME_OK;
+}
+
+extern "C" int lme_set_tuning(lme_handle h, const lme_tuning *t) {
+  if (!h || !t) return fail(LME_EINVAL, "handle and tuning must not be NULL");
+  if (t->rk4_layout < LME_LAYOUT_AUTO || t->rk4_layout > LME_LAYOUT_COLUMN)
+    return fail(LME_EINVAL, "unknown layout %d", t->rk4_layout);
+  if (t->rk4_block != 0 && t->rk4_block != 256 && t->rk4_block != 512 && t->rk4_block != 768 &&
+      t->rk4_block != 1024)
+    return fail(LME_EINVAL, "block must be 0, 256, 512, 768 or 1024");
+  if (t->apply_cap != 0 && (t->apply_cap < 256 || t->apply_cap > 65536))
+    return fail(LME_EINVAL, "apply_cap must be 0 or in [256, 65536]");
+  h->tuning = *t;
+  h->apply_cap = t->apply_cap ? t->apply_cap : 4096;
+  h->tuning.apply_cap = h->apply_cap;
+  return LME_OK;
+}
+
+namespace {
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+}  // namespace
+
+static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_dev, void *stream,
+                         lme_tuning *result) {
+  if (!h || !opt || !rho0_dev) return fail(LME_EINVAL, "handle, options and rho0 are required");
+  if (opt->method != LME_RK4 || opt->nsteps < 1)
+    return fail(LME_EINVAL, "the autotuner times RK4 runs: method RK4 and nsteps >= 1");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  DevBuf out;
+  hipError_t e = hipMalloc(&out.p, (size_t)h->state_elems * 16);
+  if (e != hipSuccess) {
+    out.p = nullptr;
+    return fail(LME_ENOMEM, "autotune scratch");
+  }
+  out.bytes = (size_t)h->state_elems * 16;
+  EventPair ev;
+  if ((e = hipEventCreate(&ev.a)) != hipSuccess || (e = hipEventCreate(&ev.b)) != hipSuccess)
+    return hip_fail(e, "hipEventCreate");
+  auto time_ms = [&](auto &&launch, int reps, float *ms) -> int {
+    int r = launch();  // warm-up (plans, uploads)
+    if (r) return r;
+    hipEventRecord(ev.a, s);
+    for (int i = 0; i < reps && !r; ++i) r = launch();
+    hipEventRecord(ev.b, s);
+    hipError_t x = hipEventSynchronize(ev.b);
+    if (r) return r;
+    if (x != hipSuccess) return hip_fail(x, "hipEventSynchronize");
+    hipEventElapsedTime(ms, ev.a, ev.b);
+    *ms /= reps;
+    return LME_OK;
+  };
+
+  // RK4: layout x block on a trial of the caller's step size
+  const int trial = std::min(opt->nsteps, 40);
+  const double tl[2] = {0.0, 0.01 * trial};  // cost per step does not depend on h
+  const lme_tuning saved = h->tuning;
+  h->tuning.rk4_block = 0;  // no tuned defaults while trying
+  struct Cand { int layout, block; };
+  const Cand cands[] = {{LME_LAYOUT_COLUMN, 768}, {LME_LAYOUT_COLUMN, 512},
+                        {LME_LAYOUT_ROW, 256}, {LME_LAYOUT_ROW, 512}, {LME_LAYOUT_ROW, 1024}};
+  float best = -1.0f;
+  Cand win = {0, 0};
+  for (const Cand &c : cands) {
+    lme_options o = *opt;
+    o.nsteps = trial;
+    o.layout = c.layout;
+    o.block = c.block;
+    float ms = 0.0f;
+    rc = time_ms([&]() { return evolve_impl(h, &o, 2, tl, rho0_dev, nullptr, nullptr, nullptr,
+                                            out.p, nullptr, nullptr, stream); }, 2, &ms);
+    if (rc == LME_ENOTSUP || rc == LME_EINVAL || rc == LME_EGRID) continue;  // not eligible
+    if (rc) {
+      h->tuning = saved;
+      return rc;
+    }
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      win = c;
+    }
+  }
+  if (best < 0.0f) {
+    h->tuning = saved;
+    return fail(LME_ENOTSUP, "no RK4 configuration fits this batch");
+  }
+  h->tuning.rk4_layout = win.layout;
+  h->tuning.rk4_block = win.block;
+  h->tuning.rk4_ms_per_step = best / trial;
+
+  // LDS-staged application: pack size
+  float best_a = -1.0f;
+  int best_cap = h->apply_cap;
+  for (int cap : {1024, 2048, 4096, 8192, 16384}) {
+    h->apply_cap = cap;
+    float us = 0.0f;
+    rc = time_ms([&]() { return apply_impl(h, LME_FORM_OPERATOR, 0, 0.0, nullptr, rho0_dev,
+                                           out.p, stream); }, 5, &us);
+    if (rc == LME_ENOTSUP) continue;
+    if (rc) return rc;
+    if (best_a < 0.0f || us < best_a) {
+      best_a = us;
+      best_cap = cap;
+    }
+  }
+  h->apply_cap = best_cap;
+  h->tuning.apply_cap = best_cap;
+  h->tuning.apply_us = best_a * 1e3;
+  if (result) *result = h->tuning;
+  return LME_OK;
+}
+
+extern "C" int lme_autotune(lme_handle h, const lme_options *opt, const void *rho0_dev,
+                            void *stream, lme_tuning *result) {
+  try {
+    return autotune_impl(h, opt, rho0_dev, stream, result);
   } catch (const std::bad_alloc &) {
     return fail(LME_ENOMEM, "out of host memory");
   } catch (...) {

@@ -182,6 +182,44 @@ struct GradArgs {
   double *grad;             // [n_inst][n_ctrl][n_seg]
 };
 
+// A streamed tile: elements [e0, e1) of instance `inst`.
+struct Tile {
+  int32_t inst, e0, e1, pad;
+};
+
+// Per-call arguments of the streamed (HBM-resident) Liouvillian application:
+// out[b] = L_b(t) y[b] for every tile.
+struct ApplyGArgs {
+  const Tile *tiles;
+  int32_t n_tiles;
+  const InstDesc *inst;
+  const uint8_t *ops;
+  int32_t adjoint;
+  const double *u;
+  int32_t n_ctrl, n_seg, seg;
+  const double *y;
+  double *out;
+};
+
+// Superoperator SpMV: per instance an ELL matrix of n^2 rows, width w,
+// slot-major: col[s * n^2 + e], val[s * n^2 + e].
+struct SuperDesc {
+  int64_t col_off;    // int32 elements into the column pool
+  int64_t val_off;    // complex elements into the value pool
+  int32_t w, pad;
+};
+
+struct SuperArgs {
+  const Tile *tiles;
+  int32_t n_tiles;
+  const InstDesc *inst;
+  const SuperDesc *sd;
+  const int32_t *col;
+  const double *val;
+  const double *y;
+  double *out;
+};
+
 // Per-call arguments of the one-shot Liouvillian application.
 struct ApplyArgs {
   const PackDesc *packs;

@@ -1319,6 +1319,112 @@ __global__ __launch_bounds__(T) void apply_lds_kernel(ApplyArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// One application of L to every instance, operator shape as a template
+// (monomial jumps): y staged in LDS with coalesced loads, then each element
+// issues all of its operator and gather reads at once (no index-load chains)
+// and the result is stored coalesced.  Same arithmetic order as
+// lindblad_elem().
+// ---------------------------------------------------------------------------
+template <int T, int WO, int NC, int NB, bool RE>
+__global__ __launch_bounds__(T) void apply_shape_kernel(ApplyArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, E = pk.m * n2;
+  const PackLds L = carve(smem, pk);
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  for (int b = threadIdx.x; b < pk.m; b += T) {
+    L.ids[b] = a.order[pk.first + b];
+    L.off[b] = a.inst[L.ids[b]].rho_off;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < pk.m * pk.nb; idx += T) {
+    const int b = idx / pk.nb, q = idx - b * pk.nb;
+    L.u[idx] = a.seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + a.seg] : 0.0;
+  }
+  const double2 *y = reinterpret_cast<const double2 *>(a.y);
+  for (int f = threadIdx.x; f < E; f += T) {
+    const int b = f / n2;
+    L.Y[f] = y[L.off[b] + (f - b * n2)];
+  }
+  __syncthreads();
+  double2 *out = reinterpret_cast<double2 *>(a.out);
+  for (int f = threadIdx.x; f < E; f += T) {
+    const int b = f / n2, r = f - b * n2;
+    const int i = r / n, j = r - i * n;
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+    ColData<WO, NC, NB> cd;
+    load_column<WO, NC, NB>(cd, op, j);
+    const uint32_t ri = row_indices<WO, NC>(op, i);
+    out[L.off[b] + r] =
+        lindblad_col<WO, NC, NB, RE>(op, cd, L.Y + b * n2, i, ri, j, L.Y[f], L.u + b * pk.nb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Streamed Liouvillian application: y and out in HBM, operators read through
+// the caches.  A workgroup takes one tile (a contiguous element range of one
+// instance); thread t handles elements e0 + t, e0 + t + T, ...: consecutive
+// lanes take consecutive columns, so the row gathers y[col][j], the output
+// stores and the j-side operator reads are coalesced, and the i-side reads
+// are shared by the lanes of a row.
+// ---------------------------------------------------------------------------
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2; workgroup w runs tile (w mod 8) * ceil(n_tiles/8) + w / 8,
+// so every XCD walks a contiguous eighth of the batch and the neighbouring
+// rows an instance's gathers touch stay in one L2.
+__device__ __forceinline__ int xcd_tile(int n_tiles) {
+  const int per = (n_tiles + 7) / 8;
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void apply_global_kernel(ApplyGArgs a) {
+  __shared__ double uq[kMaxWidth];
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const Tile tl = a.tiles[tix];
+  const InstDesc &d = a.inst[tl.inst];
+  const int n = d.n;
+  const Signature &sg = a.adjoint ? d.adj : d.fwd;
+  const BlobLayout BL = blob_layout(n, sg.wo, sg.nb, sg.wb, sg.nc, sg.wc);
+  const OpView op = make_view(a.ops + (a.adjoint ? d.adj_off : d.ops_off), BL);
+  for (int q = threadIdx.x; q < sg.nb; q += T)
+    uq[q] = a.seg >= 0 ? a.u[((int64_t)tl.inst * a.n_ctrl + q) * a.n_seg + a.seg] : 0.0;
+  __syncthreads();
+  const double2 *Y = reinterpret_cast<const double2 *>(a.y) + d.rho_off;
+  double2 *out = reinterpret_cast<double2 *>(a.out) + d.rho_off;
+  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += T) {
+    const int i = e / n, j = e - i * n;
+    out[e] = lindblad_elem(op, Y, i, j, Y[e], uq);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Superoperator form: out = S y with S the explicit n^2 x n^2 Liouvillian of
+// each instance in slot-major ELL (consecutive rows adjacent per slot, so the
+// column and value reads are coalesced); y read through the caches.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(T) void superop_kernel(SuperArgs a) {
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const Tile tl = a.tiles[tix];
+  const InstDesc &d = a.inst[tl.inst];
+  const SuperDesc sd = a.sd[tl.inst];
+  const int n2 = d.n * d.n;
+  const int32_t *col = a.col + sd.col_off;
+  const double2 *val = reinterpret_cast<const double2 *>(a.val) + sd.val_off;
+  const double2 *Y = reinterpret_cast<const double2 *>(a.y) + d.rho_off;
+  double2 *out = reinterpret_cast<double2 *>(a.out) + d.rho_off;
+  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += T) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = 0; s < sd.w; ++s) acc = cfma(val[(int64_t)s * n2 + e], Y[col[(int64_t)s * n2 + e]], acc);
+    out[e] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <int T, int EPT>
@@ -1450,6 +1556,42 @@ extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradA
   LME_G(1, 1) LME_G(2, 1) LME_G(4, 1) LME_G(8, 1)
   LME_G(1, 2) LME_G(2, 2) LME_G(4, 2) LME_G(8, 2)
 #undef LME_G
+  return hipErrorInvalidValue;
+}
+
+extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a, hipStream_t s) {
+  const int grid = 8 * ((a->n_tiles + 7) / 8);
+  hipLaunchKernelGGL(lme::apply_global_kernel<256>, dim3(grid), dim3(256), 0, s, *a);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s) {
+  const int grid = 8 * ((a->n_tiles + 7) / 8);
+  hipLaunchKernelGGL(lme::superop_kernel<256>, dim3(grid), dim3(256), 0, s, *a);
+  return hipGetLastError();
+}
+
+template <int WO, int NC, int NB, bool RE>
+static hipError_t launch_apply_shape_t(const lme::ApplyArgs &a, int n_packs, int lds,
+                                       hipStream_t s) {
+  auto k = lme::apply_shape_kernel<256, WO, NC, NB, RE>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+// Shape-specialised application (the shapes of the column-owner kernels).
+extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, int re,
+                                                      const lme::ApplyArgs *a, int n_packs,
+                                                      int lds, hipStream_t s) {
+#define LME_AS(W, K, B, R) \
+  if (wo == W && nc == K && nb == B && re == R) \
+    return launch_apply_shape_t<W, K, B, (R != 0)>(*a, n_packs, lds, s);
+  LME_AS(1, 2, 0, 0) LME_AS(1, 3, 0, 0) LME_AS(2, 2, 0, 0) LME_AS(1, 2, 1, 0) LME_AS(1, 3, 1, 0)
+  LME_AS(1, 2, 0, 1) LME_AS(1, 3, 0, 1) LME_AS(2, 2, 0, 1) LME_AS(1, 2, 1, 1) LME_AS(1, 3, 1, 1)
+#undef LME_AS
   return hipErrorInvalidValue;
 }
 

@@ -23,12 +23,13 @@ STATUS_NAMES = {0: "LME_OK", 1: "LME_EINVAL", 2: "LME_EGRID", 3: "LME_EMAXSTEPS"
                 7: "LME_EHIP", 8: "LME_ENOTSUP"}
 LME_RK4, LME_DOPRI5 = 0, 1
 LME_PATH_AUTO, LME_PATH_RESIDENT, LME_PATH_STREAMED = 0, 1, 2
-LME_FORM_OPERATOR, LME_FORM_SUPEROP = 0, 1
+LME_FORM_OPERATOR, LME_FORM_SUPEROP, LME_FORM_OPERATOR_STREAMED = 0, 1, 2
 LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
-           "lme_last_error", "lme_layout", "lme_evolve", "lme_apply", "lme_cost_grad"]
+           "lme_last_error", "lme_layout", "lme_evolve", "lme_apply", "lme_cost_grad",
+           "lme_get_tuning", "lme_set_tuning", "lme_autotune"]
 
 
 class LmeError(RuntimeError):
@@ -92,6 +93,10 @@ def load():
         lib.lme_cost_grad.argtypes = [H, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p]
+        lib.lme_get_tuning.argtypes = [H, C.POINTER(Tuning)]
+        lib.lme_set_tuning.argtypes = [H, C.POINTER(Tuning)]
+        lib.lme_autotune.argtypes = [H, C.POINTER(Options), C.c_void_p, C.c_void_p,
+                                     C.POINTER(Tuning)]
         _LIB = lib
     return _LIB
 
@@ -107,6 +112,15 @@ def default_options(**kw):
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+class Tuning(C.Structure):
+    _fields_ = [("rk4_layout", C.c_int32), ("rk4_block", C.c_int32), ("apply_cap", C.c_int32),
+                ("reserved", C.c_int32), ("rk4_ms_per_step", C.c_double),
+                ("apply_us", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class _CsrKeep:
@@ -253,6 +267,25 @@ class Handle:
                                _stream_ptr(stream))
         _check(rc, "lme_evolve")
         return out
+
+    def autotune(self, rho0, nsteps, stream=None):
+        """lme_autotune: picks the fastest schedule for this batch; returns it."""
+        t = Tuning()
+        opt = default_options(method=LME_RK4, nsteps=int(nsteps))
+        _check(load().lme_autotune(self._h, C.byref(opt), _ptr(rho0), _stream_ptr(stream),
+                                   C.byref(t)), "lme_autotune")
+        return t.as_dict()
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load().lme_get_tuning(self._h, C.byref(t)), "lme_get_tuning")
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.get_tuning()
+        for k, v in kw.items():
+            setattr(t, k, v)
+        _check(load().lme_set_tuning(self._h, C.byref(t)), "lme_set_tuning")
 
     def apply(self, y, t=0.0, adjoint=False, form=LME_FORM_OPERATOR, u=None, stream=None):
         """out = L(t) y (or L^+ y) for every instance of the packed batch."""

@@ -65,6 +65,42 @@ def test_apply_jc_sweep_tiles():
         assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
 
 
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_apply_streamed_matches_oracle(adjoint):
+    systems = [S.random_system(n, n_c=nc, n_ctrl=2, n_seg=3, seed=400 + n, t_end=1.0,
+                               hermitian_rho=False)
+               for n, nc in [(1, 1), (3, 0), (47, 2), (7, 3), (64, 2)]]
+    h = lme.Handle(systems)
+    y = h.pack([s.rho0 for s in systems])
+    out = h.unpack(h.apply(y, t=0.7, adjoint=adjoint, form=lme.LME_FORM_OPERATOR_STREAMED))
+    for s, got in zip(systems, out):
+        f = oracle.apply_Ldag if adjoint else oracle.apply_L
+        want = f(s, s.rho0, t=0.7)
+        assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def test_apply_superoperator_matches_oracle():
+    systems = [S.random_system(n, n_c=nc, seed=500 + n, hermitian_rho=False)
+               for n, nc in [(1, 1), (4, 0), (9, 3), (30, 2)]]
+    systems += S.jc_sweep(n_inst=6, seed=5, coherent=True).systems
+    h = lme.Handle(systems)
+    y = h.pack([s.rho0 for s in systems])
+    out = h.unpack(h.apply(y, form=lme.LME_FORM_SUPEROP))
+    for s, got in zip(systems, out):
+        want = oracle.apply_L(s, s.rho0)
+        assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+def test_apply_large_instance_routes_to_streamed():
+    """n = 2*72 = 144: the stage input (324 KB) exceeds LDS."""
+    s = S.jc_system(72, g=0.2, kappa=0.01, gamma=0.02)
+    s.rho0 = S.ket2dm(np.kron(S.coherent_ket(72, 2.0), S.ket(2, 1)))
+    h = lme.Handle([s])
+    out = h.unpack(h.apply(h.pack([s.rho0])))[0]
+    want = oracle.apply_L(s, s.rho0)
+    assert np.max(np.abs(out - want)) <= 1e-12 * np.max(np.abs(want))
+
+
 # --------------------------------------------------------------------------
 # fixed-step RK4
 # --------------------------------------------------------------------------
@@ -212,6 +248,26 @@ def test_rk4_column_layout_rejects_general_jumps():
     with pytest.raises(lme.LmeError) as e:
         h.evolve(h.pack([s.rho0]), np.array([0.0, 1.0]), nsteps=4, layout=lme.LME_LAYOUT_COLUMN)
     assert e.value.code == lme.LME_ENOTSUP
+
+
+def test_autotune_keeps_results_and_tuning_roundtrip():
+    w = S.jc_sweep(n_inst=40, seed=91, nsteps=50, t_end=1.25, n_out=6)
+    h = lme.Handle(w.systems)
+    rho0 = h.pack([s.rho0 for s in w.systems])
+    ref = h.evolve(rho0, w.tlist, nsteps=w.nsteps, layout=lme.LME_LAYOUT_ROW, block=512)
+    ref_apply = h.apply(rho0)
+    t = h.autotune(rho0, w.nsteps)
+    assert t["rk4_block"] in (256, 512, 768, 1024) and t["apply_cap"] >= 1024
+    assert t["rk4_ms_per_step"] > 0 and t["apply_us"] > 0
+    out = h.evolve(rho0, w.tlist, nsteps=w.nsteps)
+    torch.cuda.synchronize()
+    assert torch.equal(out["rho"], ref["rho"]) and torch.equal(out["expect"], ref["expect"])
+    assert torch.equal(h.apply(rho0), ref_apply)
+    h.set_tuning(apply_cap=1024, rk4_block=256, rk4_layout=lme.LME_LAYOUT_ROW)
+    tt = h.get_tuning()
+    assert tt.apply_cap == 1024 and tt.rk4_block == 256
+    with pytest.raises(lme.LmeError):
+        h.set_tuning(apply_cap=7)
 
 
 def test_rk4_deterministic_repeat():
