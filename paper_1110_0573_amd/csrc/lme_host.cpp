@@ -46,6 +46,8 @@ extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, in
                                               int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
+                                              hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, int re,
                                                       const lme::ApplyArgs *a, int n_packs,
                                                       int lds, hipStream_t s);
@@ -235,9 +237,19 @@ struct lme_ctx {
   std::vector<std::vector<Sparse>> C_host;
   DevBuf d_sd, d_scol, d_sval;
   int apply_cap = 4096;   // elements per pack of the LDS-staged application
+  // streamed steppers: workspace, per-instance tile ranges, capture stream and
+  // the instantiated one-step graph (re-captured when the arguments change)
+  DevBuf d_sws, d_tile_rng;
+  int32_t *h_active = nullptr;   // pinned
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint8_t> gkey;
   lme_tuning tuning = {0, 0, 0, 0, 0.0, 0.0};
   ~lme_ctx() {
     for (Plan *p : plans) delete p;
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (h_active) (void)hipHostFree(h_active);
   }
 };
 
@@ -802,6 +814,181 @@ static int dp5_tables(const lme_ctx *h, int32_t n_t, const double *tlist,
   return LME_OK;
 }
 
+static int ensure_tiles(lme_ctx *h);
+
+// Workspace of the streamed steppers: rho, two stage-input buffers, the
+// fifth-order solution, the RK4 accumulator, seven stage derivatives, tile
+// partial sums and per-instance control; plus per-instance tile ranges.
+static int stream_workspace(lme_ctx *h, lme::StreamArgs *a) {
+  int rc = ensure_tiles(h);
+  if (rc) return rc;
+  const size_t SE16 = (size_t)h->state_elems * 16;
+  const size_t nt = h->tiles.size();
+  const size_t ctl = lme::align16((int32_t)sizeof(lme::DpCtl)) * (size_t)h->n_inst;
+  const size_t need = 12 * SE16 + 16 * nt + ctl + 256;
+  if (h->d_sws.bytes < need) {
+    h->d_sws.release();
+    hipError_t e = hipMalloc(&h->d_sws.p, need);
+    if (e != hipSuccess) {
+      h->d_sws.p = nullptr;
+      return fail(LME_ENOMEM, "hipMalloc(streamed workspace, %zu B) failed", need);
+    }
+    h->d_sws.bytes = need;
+  }
+  if (!h->d_tile_rng.p) {
+    std::vector<int32_t> rng(2 * (size_t)h->n_inst, 0);
+    for (size_t q = 0; q < nt; ++q) {
+      const int b = h->tiles[q].inst;
+      if (rng[2 * b + 1] == 0) rng[2 * b] = (int32_t)q;
+      ++rng[2 * b + 1];
+    }
+    std::vector<int32_t> packed(2 * (size_t)h->n_inst);
+    for (int b = 0; b < h->n_inst; ++b) {
+      packed[b] = rng[2 * b];
+      packed[h->n_inst + b] = rng[2 * b + 1];
+    }
+    if ((rc = h->d_tile_rng.upload(packed.data(), packed.size() * 4, "tile ranges"))) return rc;
+  }
+  if (!h->h_active) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->h_active), 16, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+  }
+  uint8_t *p = static_cast<uint8_t *>(h->d_sws.p);
+  a->rho = reinterpret_cast<double *>(p);
+  a->yb0 = reinterpret_cast<double *>(p + SE16);
+  a->yb1 = reinterpret_cast<double *>(p + 2 * SE16);
+  a->y5 = reinterpret_cast<double *>(p + 3 * SE16);
+  a->acc = reinterpret_cast<double *>(p + 4 * SE16);
+  a->K = reinterpret_cast<double *>(p + 5 * SE16);
+  a->tile_part = reinterpret_cast<double *>(p + 12 * SE16);
+  a->ctl = reinterpret_cast<lme::DpCtl *>(p + 12 * SE16 + 16 * nt);
+  a->n_active = reinterpret_cast<int32_t *>(p + 12 * SE16 + 16 * nt + ctl);
+  a->counters = a->n_active + 4;
+  a->tiles = static_cast<const lme::Tile *>(h->d_tiles.p);
+  a->n_tiles = (int32_t)nt;
+  a->n_inst = h->n_inst;
+  a->tile_first = static_cast<const int32_t *>(h->d_tile_rng.p);
+  a->tile_count = a->tile_first + h->n_inst;
+  a->inst = static_cast<const InstDesc *>(h->d_inst.p);
+  a->ops = static_cast<const uint8_t *>(h->d_ops.p);
+  a->eops = static_cast<const uint8_t *>(h->d_eops.p);
+  a->n_ctrl = h->n_ctrl;
+  a->n_seg = h->n_seg;
+  a->n_e = h->n_e;
+  a->state_elems = h->state_elems;
+  if (!h->gstream) {
+    hipError_t e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      h->gstream = nullptr;
+      return hip_fail(e, "hipStreamCreate");
+    }
+  }
+  return LME_OK;
+}
+
+// Captures `record` (a sequence of launches on the given stream) into the
+// handle's graph unless the arguments are those of the cached graph.
+template <typename F>
+static int cached_graph(lme_ctx *h, const void *key, size_t key_bytes, F &&record) {
+  std::vector<uint8_t> k(static_cast<const uint8_t *>(key), static_cast<const uint8_t *>(key) + key_bytes);
+  if (h->gexec && k == h->gkey) return LME_OK;
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  const int rc = record(h->gstream);
+  e = hipStreamEndCapture(h->gstream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->gexec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  h->gkey.swap(k);
+  return LME_OK;
+}
+
+// Streamed Dormand-Prince: the sequence of kernels of one attempted step is
+// captured once as a graph and replayed; the host reads the active count
+// every kReplay replays.  Every replay makes one attempt for every active
+// instance and every instance stops within max_steps attempts, so the loop
+// ends after at most max_steps + 1 replays.
+static int evolve_dp5_streamed(lme_ctx *h, const lme_options *opt, int32_t n_t,
+                               const double *tlist, const void *rho0_dev,
+                               const double *u_dev, void *expect_dev, void *states_dev,
+                               void *rho_out_dev, int64_t *counts_dev, int32_t *status_dev,
+                               hipStream_t s, const lme::Dp5Args &tabs) {
+  lme::StreamArgs a;
+  std::memset(&a, 0, sizeof a);
+  int rc = stream_workspace(h, &a);
+  if (rc) return rc;
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_t = n_t;
+  a.stops = tabs.stops;
+  a.stop_out = tabs.stop_out;
+  a.stop_seg = tabs.stop_seg;
+  a.n_stops = tabs.n_stops;
+  a.t0 = tlist[0];
+  a.rtol = opt->rtol;
+  a.atol = opt->atol;
+  a.h0 = opt->h0;
+  a.h_min = opt->h_min;
+  a.max_steps = opt->max_steps;
+  a.states = static_cast<double *>(states_dev);
+  a.expect = static_cast<double *>(expect_dev);
+  a.counts = counts_dev;
+  a.status = status_dev;
+  auto L = [&](int which, int arg, hipStream_t st) -> int {
+    hipError_t e = lme_internal_launch_sdp(which, arg, &a, st);
+    return e == hipSuccess ? LME_OK : hip_fail(e, "launch streamed DOPRI5");
+  };
+  hipError_t e = hipMemcpyAsync(a.rho, rho0_dev, (size_t)h->state_elems * 16,
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "copy rho0");
+  if ((rc = L(4, 0, s)) || (rc = L(3, -1, s))) return rc;
+  if (a.n_stops > 0) {
+    if (opt->h0 <= 0.0) {
+      if ((rc = L(5, 0, s)) || (rc = L(6, 0, s)) || (rc = L(7, 0, s)) || (rc = L(8, 0, s)) ||
+          (rc = L(9, 0, s)))
+        return rc;
+    } else if ((rc = L(9, 1, s))) {
+      return rc;
+    }
+    rc = cached_graph(h, &a, sizeof a, [&](hipStream_t gs) -> int {
+      int r = 0;
+      for (int st = 0; st < 7 && !r; ++st) r = L(0, st, gs);
+      if (!r) r = L(1, 0, gs);
+      if (!r) r = L(2, 0, gs);
+      if (!r) r = L(3, -1, gs);
+      return r;
+    });
+    if (rc) return rc;
+    constexpr int kReplay = 16;
+    for (int64_t done = 0; done <= opt->max_steps; done += kReplay) {
+      for (int r = 0; r < kReplay; ++r)
+        if ((e = hipGraphLaunch(h->gexec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      if ((e = hipMemcpyAsync(h->h_active, a.n_active, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "poll active count");
+      if (*h->h_active == 0) break;
+    }
+  }
+  if ((rc = L(10, 0, s))) return rc;
+  if (rho_out_dev &&
+      (e = hipMemcpyAsync(rho_out_dev, a.rho, (size_t)h->state_elems * 16,
+                          hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "copy rho");
+  return LME_OK;
+}
+
 static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
                       const void *rho0_dev, const double *u_dev, void *expect_dev,
                       void *states_dev, void *rho_out_dev, int64_t *counts_dev,
@@ -812,8 +999,6 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   if (!std::isfinite(opt->h0) || !(opt->h_min >= 0.0) || !std::isfinite(opt->h_min))
     return fail(LME_EINVAL, "DOPRI5 needs a finite h0 and h_min >= 0");
   if (opt->max_steps < 1) return fail(LME_EINVAL, "DOPRI5 needs max_steps >= 1");
-  if (opt->path == LME_PATH_STREAMED)
-    return fail(LME_ENOTSUP, "the streamed DOPRI5 path is not available in this build");
   if (opt->layout == LME_LAYOUT_COLUMN)
     return fail(LME_ENOTSUP, "the column layout has no adaptive stepper");
   if (opt->block != 0 && opt->block != 512)
@@ -829,9 +1014,10 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   int EPT = 0;
   for (int i = 0; i < ne && !EPT; ++i)
     if (512 * epts[i] >= max_n2) EPT = epts[i];
-  if (!EPT)
+  if (!EPT && opt->path == LME_PATH_RESIDENT)
     return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the resident adaptive "
                 "workgroup", max_n2);
+  bool streamed = opt->path == LME_PATH_STREAMED || !EPT;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((rc = ensure_device(h))) return rc;
@@ -848,23 +1034,32 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
     if ((rc = h->d_stops.upload(buf.data(), buf.size(), "stop tables"))) return rc;
     h->stops_key.swap(key);
   }
-  const size_t kbytes = (size_t)7 * h->state_elems * 16;
-  if (h->d_kbuf.bytes < kbytes) {
-    h->d_kbuf.release();
-    hipError_t e = hipMalloc(&h->d_kbuf.p, kbytes);
-    if (e != hipSuccess) {
-      h->d_kbuf.p = nullptr;
-      return fail(LME_ENOMEM, "hipMalloc(stage derivatives, %zu B) failed", kbytes);
-    }
-    h->d_kbuf.bytes = kbytes;
+  Plan *plan = nullptr;
+  if (!streamed) {
+    rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan);
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)
+      streamed = true;  // a pack does not fit in LDS
+    else if (rc)
+      return rc;
   }
-  Plan *plan;
-  if ((rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan))) return rc;
+
+  if (!streamed) {
+    const size_t kbytes = (size_t)7 * h->state_elems * 16;
+    if (h->d_kbuf.bytes < kbytes) {
+      h->d_kbuf.release();
+      hipError_t e = hipMalloc(&h->d_kbuf.p, kbytes);
+      if (e != hipSuccess) {
+        h->d_kbuf.p = nullptr;
+        return fail(LME_ENOMEM, "hipMalloc(stage derivatives, %zu B) failed", kbytes);
+      }
+      h->d_kbuf.bytes = kbytes;
+    }
+  }
 
   lme::Dp5Args a;
   std::memset(&a, 0, sizeof a);
-  a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
-  a.order = static_cast<const int32_t *>(plan->d_order.p);
+  a.packs = plan ? static_cast<const PackDesc *>(plan->d_packs.p) : nullptr;
+  a.order = plan ? static_cast<const int32_t *>(plan->d_order.p) : nullptr;
   a.inst = static_cast<const InstDesc *>(h->d_inst.p);
   a.ops = static_cast<const uint8_t *>(h->d_ops.p);
   a.eops = static_cast<const uint8_t *>(h->d_eops.p);
@@ -892,6 +1087,9 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   a.expect = static_cast<double *>(expect_dev);
   a.counts = counts_dev;
   a.status = status_dev;
+  if (streamed)
+    return evolve_dp5_streamed(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev,
+                               rho_out_dev, counts_dev, status_dev, s, a);
   hipError_t e = lme_internal_launch_dp5(EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch resident DOPRI5");
   return LME_OK;

@@ -220,6 +220,49 @@ struct SuperArgs {
   double *out;
 };
 
+// Per-instance adaptive step control (LDS in the resident kernel, HBM in the
+// streamed one).
+struct DpCtl {
+  double t, h, h_try, hs;
+  int64_t n_acc, n_rej;
+  int32_t stop, status, active, accept, landing, seg, k1_seg, prev_rej, out_due, need_k1;
+};
+
+// Per-call arguments of the streamed steppers (one grid-wide kernel per
+// stage; state and stage data in HBM).
+struct StreamArgs {
+  const Tile *tiles;
+  int32_t n_tiles, n_inst;
+  const int32_t *tile_first;   // [n_inst] first tile of each instance
+  const int32_t *tile_count;   // [n_inst]
+  const InstDesc *inst;
+  const uint8_t *ops;
+  const uint8_t *eops;
+  const double *u;
+  int32_t n_ctrl, n_seg, n_e, n_t;
+  int64_t state_elems;
+  double *rho, *yb0, *yb1, *y5, *acc;
+  double *K;                   // [7][state_elems]
+  double *tile_part;           // [2 n_tiles]
+  // adaptive
+  DpCtl *ctl;
+  const double *stops;
+  const int32_t *stop_out, *stop_seg;
+  int32_t n_stops;
+  double t0, rtol, atol, h0, h_min;
+  int64_t max_steps;
+  int32_t *n_active;           // written by the control kernel
+  // fixed step
+  const int32_t *seg_of_step, *out_step;
+  int32_t nsteps;
+  double h;
+  int32_t *counters;           // [0] completed steps, [1] next output
+  // outputs
+  double *states, *expect;
+  int64_t *counts;
+  int32_t *status;
+};
+
 // Per-call arguments of the one-shot Liouvillian application.
 struct ApplyArgs {
   const PackDesc *packs;

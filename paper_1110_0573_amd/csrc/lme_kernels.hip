@@ -626,12 +626,6 @@ __constant__ double kDpE[7] = {35.0 / 384 - 5179.0 / 57600,
                                11.0 / 84 - 187.0 / 2100,
                                0.0 - 1.0 / 40};
 
-// Per-instance step control, in LDS.
-struct DpCtl {
-  double t, h, h_try, hs;
-  int64_t n_acc, n_rej;
-  int32_t stop, status, active, accept, landing, seg, k1_seg, prev_rej, out_due, need_k1;
-};
 
 __host__ __device__ inline int32_t dp_ctl_bytes(int32_t m) {
   return align16(m * (int32_t)sizeof(DpCtl));
@@ -1425,6 +1419,375 @@ __global__ __launch_bounds__(T) void superop_kernel(SuperArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Streamed steppers: one grid-wide kernel per stage over element tiles
+// (XCD-aware order), state and stage data in HBM, operators read through the
+// caches.  Used when an instance's state does not fit in LDS.  The adaptive
+// stepper keeps each instance's control (DpCtl) in HBM: the stage kernels skip
+// finished instances, a single-workgroup control kernel reduces the tile
+// partial error sums of every instance in a fixed order and takes the same
+// decisions as the resident kernel.
+// ---------------------------------------------------------------------------
+
+// Controller decision after an attempted step (same rule as the resident
+// kernel) followed by the set-up of the next attempt.
+__device__ void dp_decide_and_setup(DpCtl &c, double err, const StreamArgs &a) {
+  c.accept = 0;
+  c.k1_seg = c.seg;
+  if (!isfinite(err)) {
+    c.status = 5;  // LME_ENONFINITE
+    c.active = 0;
+  } else if (err <= 1.0) {
+    c.accept = 1;
+    ++c.n_acc;
+    double fac = (err == 0.0) ? 10.0 : 0.9 * pow(err, -0.2);
+    fac = fmin(10.0, fmax(0.2, fac));
+    if (c.prev_rej && fac > 1.0) fac = 1.0;
+    c.prev_rej = 0;
+    c.h = c.h_try * fac;
+    if (c.landing) {
+      c.t = a.stops[c.stop];
+      c.out_due = a.stop_out[c.stop];
+      if (++c.stop == a.n_stops) c.active = 0;
+    } else {
+      c.t += c.h_try;
+    }
+  } else {
+    ++c.n_rej;
+    c.prev_rej = 1;
+    c.h = c.h_try * fmax(0.2, 0.9 * pow(err, -0.2));
+  }
+}
+
+__device__ void dp_setup(DpCtl &c, const StreamArgs &a) {
+  if (!c.active) return;
+  if (c.n_acc + c.n_rej >= a.max_steps) {
+    c.status = 3;  // LME_EMAXSTEPS
+    c.active = 0;
+  } else if (c.h < a.h_min) {
+    c.status = 4;  // LME_ESTEPUNDERFLOW
+    c.active = 0;
+  } else {
+    const double ts = a.stops[c.stop];
+    c.landing = c.h >= ts - c.t;
+    c.h_try = c.landing ? ts - c.t : c.h;
+    c.seg = a.n_seg > 0 ? a.stop_seg[c.stop] : -1;
+    c.need_k1 = c.k1_seg != c.seg;
+  }
+}
+
+// Fixed-order sum of one value per thread over the workgroup.
+template <int T>
+__device__ double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < T / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+struct TileCtx {
+  int b, n, e0, e1;
+  int64_t base;
+  OpView op;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const StreamArgs &a, int tix, double *uq, int seg) {
+  const Tile tl = a.tiles[tix];
+  const InstDesc &d = a.inst[tl.inst];
+  TileCtx t;
+  t.b = tl.inst;
+  t.n = d.n;
+  t.e0 = tl.e0;
+  t.e1 = tl.e1;
+  t.base = d.rho_off;
+  const Signature &sg = d.fwd;
+  t.op = make_view(a.ops + d.ops_off, blob_layout(d.n, sg.wo, sg.nb, sg.wb, sg.nc, sg.wc));
+  for (int q = threadIdx.x; q < sg.nb; q += blockDim.x)
+    uq[q] = seg >= 0 ? a.u[((int64_t)tl.inst * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+  return t;
+}
+
+// Stage s (0..6) of the adaptive step: k_s = L(y_s); the input of stage s+1,
+// y_{s+1} = rho + h sum_{j<=s} a[s+1][j] k_j, or, after the last stage, the
+// partial sum of the squared scaled error of the tile.
+//   inputs  y_0 = rho, y_1 = yb0, y_2 = yb1, y_3 = yb0, y_4 = yb1, y_5 = yb0,
+//           y_6 = y5 (the fifth-order solution)
+template <int T>
+__global__ __launch_bounds__(T) void sdp_stage_kernel(StreamArgs a, int s) {
+  __shared__ double uq[kMaxWidth];
+  __shared__ double sh[T / 64];
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const int b = a.tiles[tix].inst;
+  const DpCtl c = a.ctl[b];
+  if (!c.active) return;
+  const TileCtx t = tile_ctx(a, tix, uq, c.seg);
+  __syncthreads();
+  double2 *rho = reinterpret_cast<double2 *>(a.rho) + t.base;
+  double2 *yb[2] = {reinterpret_cast<double2 *>(a.yb0) + t.base,
+                    reinterpret_cast<double2 *>(a.yb1) + t.base};
+  double2 *y5 = reinterpret_cast<double2 *>(a.y5) + t.base;
+  double2 *K = reinterpret_cast<double2 *>(a.K) + t.base;
+  const int64_t SE = a.state_elems;
+  const double2 *Yin = s == 0 ? rho : (s == 6 ? y5 : yb[(s + 1) & 1]);
+  double2 *Yout = s == 5 ? y5 : yb[s & 1];
+  double part = 0.0;
+  for (int e = t.e0 + threadIdx.x; e < t.e1; e += T) {
+    const int i = e / t.n, j = e - i * t.n;
+    double2 k;
+    if (s > 0 || c.need_k1) {
+      k = lindblad_elem(t.op, Yin, i, j, Yin[e], uq);
+      K[s * SE + e] = k;
+    } else {
+      k = K[e];
+    }
+    if (s < 6) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int jj = 0; jj <= s; ++jj) acc = caxpy(kDpA[s + 1][jj], jj == s ? k : K[jj * SE + e], acc);
+      Yout[e] = caxpy(c.h_try, acc, rho[e]);
+    } else {
+      double2 er = make_double2(0.0, 0.0);
+      for (int jj = 0; jj < 7; ++jj) er = caxpy(kDpE[jj], jj == 6 ? k : K[jj * SE + e], er);
+      er = make_double2(c.h_try * er.x, c.h_try * er.y);
+      const double sc = a.atol + a.rtol * fmax(hypot(rho[e].x, rho[e].y), hypot(y5[e].x, y5[e].y));
+      const double r = hypot(er.x, er.y) / sc;
+      part += r * r;
+    }
+  }
+  if (s == 6) {
+    const double tot = block_sum<T>(part, sh);
+    if (threadIdx.x == 0) a.tile_part[tix] = tot;
+  }
+}
+
+// Accept / reject for every instance and set-up of its next attempt; one
+// workgroup, instances strided over its threads; writes the active count.
+template <int T>
+__global__ __launch_bounds__(T) void sdp_control_kernel(StreamArgs a) {
+  __shared__ double sh[T / 64];
+  int act = 0;
+  for (int b = threadIdx.x; b < a.n_inst; b += T) {
+    DpCtl c = a.ctl[b];
+    if (c.active) {
+      double sum = 0.0;
+      for (int q = 0; q < a.tile_count[b]; ++q) sum += a.tile_part[a.tile_first[b] + q];
+      const int n = a.inst[b].n;
+      dp_decide_and_setup(c, sqrt(sum / ((double)n * n)), a);
+      dp_setup(c, a);
+      a.ctl[b] = c;
+    } else {
+      a.ctl[b].accept = 0;
+    }
+    act += a.ctl[b].active;
+  }
+  const double tot = block_sum<T>((double)act, sh);
+  if (threadIdx.x == 0) *a.n_active = (int32_t)tot;
+}
+
+// Accepted instances move to the fifth-order solution; k7 becomes k1.
+template <int T>
+__global__ __launch_bounds__(T) void sdp_accept_kernel(StreamArgs a) {
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const Tile tl = a.tiles[tix];
+  if (!a.ctl[tl.inst].accept) return;
+  const int64_t base = a.inst[tl.inst].rho_off;
+  double2 *rho = reinterpret_cast<double2 *>(a.rho) + base;
+  const double2 *y5 = reinterpret_cast<const double2 *>(a.y5) + base;
+  double2 *K = reinterpret_cast<double2 *>(a.K) + base;
+  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += T) {
+    rho[e] = y5[e];
+    K[e] = K[6 * a.state_elems + e];
+  }
+}
+
+// Outputs of instances whose out_due >= 0 (one workgroup per instance): the
+// expectation values (waves over operators, lanes over rows, butterfly) and
+// the state; then clears out_due.
+template <int T>
+__global__ __launch_bounds__(T) void stream_output_kernel(StreamArgs a, int fixed_k) {
+  const int b = blockIdx.x;
+  const int k = fixed_k >= 0 ? fixed_k : a.ctl[b].out_due;
+  if (k < 0) return;
+  const InstDesc &d = a.inst[b];
+  const int n = d.n, we = d.we;
+  const double2 *rho = reinterpret_cast<const double2 *>(a.rho) + d.rho_off;
+  if (a.expect && a.n_e > 0) {
+    const int32_t *Ec = reinterpret_cast<const int32_t *>(a.eops + d.eops_off);
+    const double2 *Ev = reinterpret_cast<const double2 *>(
+        a.eops + d.eops_off + eops_val_offset(n, we, a.n_e));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = wave; e < a.n_e; e += T / 64) {
+      double2 part = make_double2(0.0, 0.0);
+      for (int i = lane; i < n; i += 64)
+        for (int w = 0; w < we; ++w) {
+          const int idx = (e * we + w) * n + i;
+          part = cfma(Ev[idx], rho[Ec[idx] * n + i], part);
+        }
+      part = wave_sum(part);
+      if (lane == 0) {
+        double *dst = a.expect + 2 * (((int64_t)b * a.n_e + e) * a.n_t + k);
+        dst[0] = part.x;
+        dst[1] = part.y;
+        if (!cfinite(part) && a.status && fixed_k >= 0) a.status[b] = 5;
+      }
+    }
+  }
+  if (a.states) {
+    double2 *st = reinterpret_cast<double2 *>(a.states) + (int64_t)k * a.state_elems + d.rho_off;
+    for (int e = threadIdx.x; e < n * n; e += T) st[e] = rho[e];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && fixed_k < 0) a.ctl[b].out_due = -1;
+}
+
+// Initial control state of every instance (single workgroup).
+template <int T>
+__global__ __launch_bounds__(T) void sdp_init_kernel(StreamArgs a) {
+  for (int b = threadIdx.x; b < a.n_inst; b += T) {
+    DpCtl c;
+    c.t = a.t0;
+    c.h = a.h0;
+    c.h_try = c.hs = 0.0;
+    c.n_acc = c.n_rej = 0;
+    c.stop = 0;
+    c.status = 0;
+    c.active = a.n_stops > 0;
+    c.accept = c.landing = 0;
+    c.seg = -1;
+    c.k1_seg = -2;
+    c.prev_rej = 0;
+    c.out_due = 0;
+    c.need_k1 = 1;
+    a.ctl[b] = c;
+  }
+}
+
+// Starting step, part 1 (tiles): f0 = L(rho) with the first interval's
+// controls into k1; partial sums of |rho/sc|^2 and |f0/sc|^2.
+template <int T>
+__global__ __launch_bounds__(T) void sdp_hnw1_kernel(StreamArgs a) {
+  __shared__ double uq[kMaxWidth];
+  __shared__ double sh[T / 64];
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const int seg0 = a.n_seg > 0 ? a.stop_seg[0] : -1;
+  const TileCtx t = tile_ctx(a, tix, uq, seg0);
+  __syncthreads();
+  const double2 *rho = reinterpret_cast<const double2 *>(a.rho) + t.base;
+  double2 *K = reinterpret_cast<double2 *>(a.K) + t.base;
+  double p0 = 0.0, p1 = 0.0;
+  for (int e = t.e0 + threadIdx.x; e < t.e1; e += T) {
+    const int i = e / t.n, j = e - i * t.n;
+    const double2 f0 = lindblad_elem(t.op, rho, i, j, rho[e], uq);
+    K[e] = f0;
+    const double sc = a.atol + a.rtol * hypot(rho[e].x, rho[e].y);
+    const double r0 = hypot(rho[e].x, rho[e].y) / sc, r1 = hypot(f0.x, f0.y) / sc;
+    p0 += r0 * r0;
+    p1 += r1 * r1;
+  }
+  const double s0 = block_sum<T>(p0, sh);
+  const double s1 = block_sum<T>(p1, sh);
+  if (threadIdx.x == 0) {
+    a.tile_part[2 * tix] = s0;
+    a.tile_part[2 * tix + 1] = s1;
+  }
+}
+
+// Starting step, part 2 (single workgroup): hs = 0.01 d0/d1 (or 1e-6).
+template <int T>
+__global__ __launch_bounds__(T) void sdp_hnw2_kernel(StreamArgs a) {
+  for (int b = threadIdx.x; b < a.n_inst; b += T) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int q = 0; q < a.tile_count[b]; ++q) {
+      s0 += a.tile_part[2 * (a.tile_first[b] + q)];
+      s1 += a.tile_part[2 * (a.tile_first[b] + q) + 1];
+    }
+    const double n2 = (double)a.inst[b].n * a.inst[b].n;
+    const double d0 = sqrt(s0 / n2), d1 = sqrt(s1 / n2);
+    a.ctl[b].hs = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    a.ctl[b].h_try = d1;  // kept until the step size is set
+  }
+}
+
+// Starting step, part 3 (tiles): yb0 = rho + hs f0.
+template <int T>
+__global__ __launch_bounds__(T) void sdp_hnw3_kernel(StreamArgs a) {
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const Tile tl = a.tiles[tix];
+  const int64_t base = a.inst[tl.inst].rho_off;
+  const double hs = a.ctl[tl.inst].hs;
+  const double2 *rho = reinterpret_cast<const double2 *>(a.rho) + base;
+  const double2 *K = reinterpret_cast<const double2 *>(a.K) + base;
+  double2 *y = reinterpret_cast<double2 *>(a.yb0) + base;
+  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += T) y[e] = caxpy(hs, K[e], rho[e]);
+}
+
+// Starting step, part 4 (tiles): f1 = L(yb0); partial sums of |(f1-f0)/sc|^2.
+template <int T>
+__global__ __launch_bounds__(T) void sdp_hnw4_kernel(StreamArgs a) {
+  __shared__ double uq[kMaxWidth];
+  __shared__ double sh[T / 64];
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const int seg0 = a.n_seg > 0 ? a.stop_seg[0] : -1;
+  const TileCtx t = tile_ctx(a, tix, uq, seg0);
+  __syncthreads();
+  const double2 *rho = reinterpret_cast<const double2 *>(a.rho) + t.base;
+  const double2 *y = reinterpret_cast<const double2 *>(a.yb0) + t.base;
+  const double2 *K = reinterpret_cast<const double2 *>(a.K) + t.base;
+  double p = 0.0;
+  for (int e = t.e0 + threadIdx.x; e < t.e1; e += T) {
+    const int i = e / t.n, j = e - i * t.n;
+    const double2 f1 = lindblad_elem(t.op, y, i, j, y[e], uq);
+    const double sc = a.atol + a.rtol * hypot(rho[e].x, rho[e].y);
+    const double r = hypot(f1.x - K[e].x, f1.y - K[e].y) / sc;
+    p += r * r;
+  }
+  const double tot = block_sum<T>(p, sh);
+  if (threadIdx.x == 0) a.tile_part[tix] = tot;
+}
+
+// Starting step, part 5 (single workgroup): h, and the first attempt's set-up.
+template <int T>
+__global__ __launch_bounds__(T) void sdp_hnw5_kernel(StreamArgs a, int have_h0) {
+  for (int b = threadIdx.x; b < a.n_inst; b += T) {
+    DpCtl c = a.ctl[b];
+    if (!have_h0) {
+      double s2 = 0.0;
+      for (int q = 0; q < a.tile_count[b]; ++q) s2 += a.tile_part[a.tile_first[b] + q];
+      const double n2 = (double)a.inst[b].n * a.inst[b].n;
+      const double hs = c.hs, d1 = c.h_try;
+      const double d2 = sqrt(s2 / n2) / hs;
+      const double dm = fmax(d1, d2);
+      const double h1 = (dm <= 1e-15) ? fmax(1e-6, hs * 1e-3) : pow(0.01 / dm, 0.2);
+      c.h = fmin(100.0 * hs, h1);
+      c.k1_seg = a.n_seg > 0 ? a.stop_seg[0] : -1;
+    }
+    dp_setup(c, a);
+    a.ctl[b] = c;
+  }
+}
+
+// Counts and status of every instance (single workgroup).
+template <int T>
+__global__ __launch_bounds__(T) void sdp_final_kernel(StreamArgs a) {
+  for (int b = threadIdx.x; b < a.n_inst; b += T) {
+    if (a.counts) {
+      a.counts[2 * (int64_t)b] = a.ctl[b].n_acc;
+      a.counts[2 * (int64_t)b + 1] = a.ctl[b].n_rej;
+    }
+    if (a.status) a.status[b] = a.ctl[b].status;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <int T, int EPT>
@@ -1593,6 +1956,28 @@ extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, in
   LME_AS(1, 2, 0, 1) LME_AS(1, 3, 0, 1) LME_AS(2, 2, 0, 1) LME_AS(1, 2, 1, 1) LME_AS(1, 3, 1, 1)
 #undef LME_AS
   return hipErrorInvalidValue;
+}
+
+// Streamed adaptive stepper: kernel `which` of the sequence (see the host).
+extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
+                                              hipStream_t s) {
+  using namespace lme;
+  const int grid = 8 * ((a->n_tiles + 7) / 8);
+  switch (which) {
+    case 0: hipLaunchKernelGGL(sdp_stage_kernel<256>, dim3(grid), dim3(256), 0, s, *a, arg); break;
+    case 1: hipLaunchKernelGGL(sdp_control_kernel<1024>, dim3(1), dim3(1024), 0, s, *a); break;
+    case 2: hipLaunchKernelGGL(sdp_accept_kernel<256>, dim3(grid), dim3(256), 0, s, *a); break;
+    case 3: hipLaunchKernelGGL(stream_output_kernel<256>, dim3(a->n_inst), dim3(256), 0, s, *a, arg); break;
+    case 4: hipLaunchKernelGGL(sdp_init_kernel<1024>, dim3(1), dim3(1024), 0, s, *a); break;
+    case 5: hipLaunchKernelGGL(sdp_hnw1_kernel<256>, dim3(grid), dim3(256), 0, s, *a); break;
+    case 6: hipLaunchKernelGGL(sdp_hnw2_kernel<1024>, dim3(1), dim3(1024), 0, s, *a); break;
+    case 7: hipLaunchKernelGGL(sdp_hnw3_kernel<256>, dim3(grid), dim3(256), 0, s, *a); break;
+    case 8: hipLaunchKernelGGL(sdp_hnw4_kernel<256>, dim3(grid), dim3(256), 0, s, *a); break;
+    case 9: hipLaunchKernelGGL(sdp_hnw5_kernel<1024>, dim3(1), dim3(1024), 0, s, *a, arg); break;
+    case 10: hipLaunchKernelGGL(sdp_final_kernel<1024>, dim3(1), dim3(1024), 0, s, *a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,

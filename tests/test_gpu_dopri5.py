@@ -114,3 +114,55 @@ def test_dp5_rejects_bad_options():
     with pytest.raises(lme.LmeError) as e:
         h.evolve(h.pack([s.rho0]), np.array([0.0, 1.0]), method="dopri5", rtol=0.0)
     assert e.value.code == lme.LME_EINVAL
+
+
+# --------------------------------------------------------------------------
+# streamed path (state in HBM, one kernel per stage, one-step graph)
+# --------------------------------------------------------------------------
+
+def test_dp5_streamed_forced_small_batch():
+    systems = [S.jc_system(N, g=0.3, kappa=0.05, gamma=0.02, psi0=(1, 1 - N % 2))
+               for N in (3, 6, 9)]
+    systems += [S.random_system(5, n_c=2, seed=77)]
+    tl = np.linspace(0.0, 2.0, 5)
+    for s in systems[3:]:
+        s.E = s.E[:2]
+    h, out = run(systems, tl, 1e-8, 1e-11, path=lme.LME_PATH_STREAMED, want_states=True)
+    ex = out["expect"].cpu().numpy()
+    st = h.unpack(out["states"])
+    assert (out["status"].cpu().numpy() == 0).all()
+    for b, s in enumerate(systems):
+        r = oracle.dopri5(s, s.rho0, tl, 1e-8, 1e-11, store_states=True)
+        close(ex[b], r["expect"])
+        assert np.max(np.abs(st[b][-1] - r["states"][-1])) <= 1e-6
+
+
+def test_dp5_streamed_controls_and_first_step():
+    w = S.jc_drive(n_inst=3, N=4, n_seg=4, t_end=1.0, steps_per_seg=1, sigma_u=0.8)
+    tl = np.array([0.0, 0.3, 1.0])
+    for h0 in (0.0, 2e-3):
+        h, out = run(w.systems, tl, 1e-9, 1e-12, path=lme.LME_PATH_STREAMED, h0=h0)
+        ex = out["expect"].cpu().numpy()
+        for b, s in enumerate(w.systems):
+            r = oracle.dopri5(s, s.rho0, tl, 1e-9, 1e-12, h0=h0)
+            close(ex[b], r["expect"])
+
+
+def test_dp5_streamed_status_codes():
+    s = S.jc_system(3, g=0.4, kappa=0.3, gamma=0.2)
+    tl = np.array([0.0, 3.0])
+    _, o = run([s, s], tl, 1e-8, 1e-11, max_steps=3, path=lme.LME_PATH_STREAMED)
+    assert (o["status"].cpu().numpy() == lme.LME_EMAXSTEPS).all()
+    assert (o["counts"].cpu().numpy().sum(axis=1) == 3).all()
+
+
+def test_dp5_tfim_full_size_routes_to_streamed_short_horizon():
+    """The 8-spin chain (n = 256, 1 MiB per state) does not fit in LDS: the
+    automatic path is the streamed one.  Two realizations, t in [0, 1.5]."""
+    w = S.tfim(n_inst=2, t_end=1.5, n_out=4)
+    h, out = run(w.systems, w.tlist, w.rtol, w.atol)
+    ex = out["expect"].cpu().numpy()
+    assert (out["status"].cpu().numpy() == 0).all()
+    for b, s in enumerate(w.systems):
+        r = oracle.dopri5(s, s.rho0, w.tlist, w.rtol, w.atol)
+        close(ex[b], r["expect"])
