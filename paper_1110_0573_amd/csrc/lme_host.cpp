@@ -989,6 +989,59 @@ static int evolve_dp5_streamed(lme_ctx *h, const lme_options *opt, int32_t n_t,
   return LME_OK;
 }
 
+// Streamed fixed-step RK4: a graph of kGraphSteps steps (4 stage kernels,
+// outputs, counter update each) replayed ceil(nsteps / kGraphSteps) times;
+// steps past nsteps do nothing.
+static int evolve_rk4_streamed(lme_ctx *h, int32_t n_t, int32_t nsteps, double hstep,
+                               const double *u_dev, const void *rho0_dev, void *expect_dev,
+                               void *states_dev, void *rho_out_dev, int64_t *counts_dev,
+                               int32_t *status_dev, hipStream_t s) {
+  lme::StreamArgs a;
+  std::memset(&a, 0, sizeof a);
+  int rc = stream_workspace(h, &a);
+  if (rc) return rc;
+  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.n_t = n_t;
+  a.seg_of_step = static_cast<const int32_t *>(h->d_steps.p);
+  a.out_step = a.seg_of_step + nsteps;
+  a.nsteps = nsteps;
+  a.h = hstep;
+  a.states = static_cast<double *>(states_dev);
+  a.expect = static_cast<double *>(expect_dev);
+  a.counts = counts_dev;
+  a.status = status_dev;
+  auto L = [&](int which, int arg, hipStream_t st) -> int {
+    hipError_t e = lme_internal_launch_sdp(which, arg, &a, st);
+    return e == hipSuccess ? LME_OK : hip_fail(e, "launch streamed RK4");
+  };
+  hipError_t e = hipMemcpyAsync(a.rho, rho0_dev, (size_t)h->state_elems * 16,
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "copy rho0");
+  if ((rc = L(22, 1, s)) || (rc = L(3, 0, s))) return rc;   // counters, outputs at t0
+  if (nsteps > 0) {
+    constexpr int kGraphSteps = 16;
+    const int per = std::min(nsteps, kGraphSteps);
+    rc = cached_graph(h, &a, sizeof a, [&](hipStream_t gs) -> int {
+      int r = 0;
+      for (int q = 0; q < per && !r; ++q) {
+        for (int st = 0; st < 4 && !r; ++st) r = L(20, st, gs);
+        if (!r) r = L(21, 0, gs);
+        if (!r) r = L(22, 0, gs);
+      }
+      return r;
+    });
+    if (rc) return rc;
+    for (int done = 0; done < nsteps; done += per)
+      if ((e = hipGraphLaunch(h->gexec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  if ((rc = L(22, 2, s))) return rc;
+  if (rho_out_dev &&
+      (e = hipMemcpyAsync(rho_out_dev, a.rho, (size_t)h->state_elems * 16,
+                          hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "copy rho");
+  return LME_OK;
+}
+
 static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
                       const void *rho0_dev, const double *u_dev, void *expect_dev,
                       void *states_dev, void *rho_out_dev, int64_t *counts_dev,
@@ -1114,8 +1167,6 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
                       counts_dev, status_dev, stream);
   if (opt->method != LME_RK4) return fail(LME_EINVAL, "unknown method %d", opt->method);
   if (n_t > 1 && opt->nsteps < 1) return fail(LME_EINVAL, "RK4 needs nsteps >= 1");
-  if (opt->path == LME_PATH_STREAMED)
-    return fail(LME_ENOTSUP, "the streamed RK4 path is not available in this build");
   const int32_t nsteps = n_t > 1 ? opt->nsteps : 0;
   const double hstep = n_t > 1 ? (tlist[n_t - 1] - tlist[0]) / nsteps : 0.0;
   std::vector<int32_t> tab;
@@ -1143,11 +1194,16 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
       }
     }
   }
-  if (!column) {
+  bool streamed = opt->path == LME_PATH_STREAMED;
+  if (!column && !streamed) {
     if (opt->layout == LME_LAYOUT_COLUMN)
       return fail(LME_ENOTSUP, "the column layout does not cover these operators / block size");
     if (opt->block == 768) return fail(LME_EINVAL, "block 768 exists only in the column layout");
-    if ((rc = pick_rk4_config(h, opt->block, &T, &EPT))) return rc;
+    rc = pick_rk4_config(h, opt->block, &T, &EPT);
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)
+      streamed = true;  // an instance is too large for a resident workgroup
+    else if (rc)
+      return rc;
   }
 
   // validation done: from here on the device is used
@@ -1155,8 +1211,17 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if ((rc = ensure_device(h))) return rc;
   if ((rc = upload_tables(h, tab, s))) return rc;
   hipError_t e;
-  Plan *plan;
-  if ((rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan))) return rc;
+  Plan *plan = nullptr;
+  if (!streamed) {
+    rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan);
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !column)
+      streamed = true;
+    else if (rc)
+      return rc;
+  }
+  if (streamed)
+    return evolve_rk4_streamed(h, n_t, nsteps, hstep, u_dev, rho0_dev, expect_dev, states_dev,
+                               rho_out_dev, counts_dev, status_dev, s);
 
   lme::Rk4Args a;
   std::memset(&a, 0, sizeof a);

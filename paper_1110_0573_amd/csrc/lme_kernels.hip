@@ -1610,10 +1610,7 @@ __global__ __launch_bounds__(T) void sdp_accept_kernel(StreamArgs a) {
 // expectation values (waves over operators, lanes over rows, butterfly) and
 // the state; then clears out_due.
 template <int T>
-__global__ __launch_bounds__(T) void stream_output_kernel(StreamArgs a, int fixed_k) {
-  const int b = blockIdx.x;
-  const int k = fixed_k >= 0 ? fixed_k : a.ctl[b].out_due;
-  if (k < 0) return;
+__device__ void instance_outputs(const StreamArgs &a, int b, int k, bool check) {
   const InstDesc &d = a.inst[b];
   const int n = d.n, we = d.we;
   const double2 *rho = reinterpret_cast<const double2 *>(a.rho) + d.rho_off;
@@ -1634,7 +1631,7 @@ __global__ __launch_bounds__(T) void stream_output_kernel(StreamArgs a, int fixe
         double *dst = a.expect + 2 * (((int64_t)b * a.n_e + e) * a.n_t + k);
         dst[0] = part.x;
         dst[1] = part.y;
-        if (!cfinite(part) && a.status && fixed_k >= 0) a.status[b] = 5;
+        if (check && !cfinite(part) && a.status) a.status[b] = 5;  // LME_ENONFINITE
       }
     }
   }
@@ -1642,8 +1639,88 @@ __global__ __launch_bounds__(T) void stream_output_kernel(StreamArgs a, int fixe
     double2 *st = reinterpret_cast<double2 *>(a.states) + (int64_t)k * a.state_elems + d.rho_off;
     for (int e = threadIdx.x; e < n * n; e += T) st[e] = rho[e];
   }
+}
+
+// Outputs of the adaptive stepper: instances whose out_due >= 0 (one
+// workgroup per instance), then out_due is cleared.  fixed_k >= 0 writes
+// output fixed_k of every instance (the initial state).
+template <int T>
+__global__ __launch_bounds__(T) void stream_output_kernel(StreamArgs a, int fixed_k) {
+  const int b = blockIdx.x;
+  const int k = fixed_k >= 0 ? fixed_k : a.ctl[b].out_due;
+  if (k < 0) return;
+  instance_outputs<T>(a, b, k, fixed_k >= 0);
   __syncthreads();
   if (threadIdx.x == 0 && fixed_k < 0) a.ctl[b].out_due = -1;
+}
+
+// ---- streamed fixed-step RK4 ------------------------------------------------
+// counters[0] = completed steps, counters[1] = next output index; kernels of a
+// step past nsteps return at once, so a graph of several steps may overrun.
+
+// Stage s of RK4: k = L(y_s) with y_0 = rho, y_1 = yb0, y_2 = yb1, y_3 = yb0;
+// the accumulator k1 + 2k2 + 2k3 (+ k4) and the next input (or the update of
+// rho) in the same operation order as the resident kernels.
+template <int T>
+__global__ __launch_bounds__(T) void srk_stage_kernel(StreamArgs a, int s) {
+  __shared__ double uq[kMaxWidth];
+  const int st = a.counters[0];
+  if (st >= a.nsteps) return;
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const TileCtx t = tile_ctx(a, tix, uq, a.seg_of_step[st]);
+  __syncthreads();
+  double2 *rho = reinterpret_cast<double2 *>(a.rho) + t.base;
+  double2 *acc = reinterpret_cast<double2 *>(a.acc) + t.base;
+  double2 *yb[2] = {reinterpret_cast<double2 *>(a.yb0) + t.base,
+                    reinterpret_cast<double2 *>(a.yb1) + t.base};
+  const double2 *Yin = s == 0 ? rho : yb[(s + 1) & 1];
+  double2 *Yout = yb[s & 1];
+  const double h = a.h;
+  const double cnext = s < 2 ? 0.5 * h : h;
+  const double wgt = (s == 0 || s == 3) ? 1.0 : 2.0;
+  for (int e = t.e0 + threadIdx.x; e < t.e1; e += T) {
+    const int i = e / t.n, j = e - i * t.n;
+    const double2 k = lindblad_elem(t.op, Yin, i, j, Yin[e], uq);
+    const double2 ac = caxpy(wgt, k, s == 0 ? make_double2(0.0, 0.0) : acc[e]);
+    if (s < 3) {
+      acc[e] = ac;
+      Yout[e] = caxpy(cnext, k, rho[e]);
+    } else {
+      rho[e] = caxpy(h / 6.0, ac, rho[e]);
+    }
+  }
+}
+
+// Outputs due after the step just completed (one workgroup per instance).
+template <int T>
+__global__ __launch_bounds__(T) void srk_output_kernel(StreamArgs a) {
+  const int st = a.counters[0], k = a.counters[1];
+  if (st >= a.nsteps || k >= a.n_t || a.out_step[k] != st + 1) return;
+  instance_outputs<T>(a, blockIdx.x, k, true);
+}
+
+// Advances the counters after a step (one thread); mode 1: initialise them
+// (and the status) before the first step.
+__global__ void srk_tail_kernel(StreamArgs a, int mode) {
+  if (mode == 1) {
+    a.counters[0] = 0;
+    a.counters[1] = (a.n_t > 0 && a.out_step[0] == 0) ? 1 : 0;
+    for (int b = 0; b < a.n_inst && a.status; ++b) a.status[b] = 0;
+    return;
+  }
+  if (mode == 2) {  // counts after the last step
+    for (int b = 0; b < a.n_inst && a.counts; ++b) {
+      a.counts[2 * (int64_t)b] = a.nsteps;
+      a.counts[2 * (int64_t)b + 1] = 0;
+    }
+    return;
+  }
+  const int st = a.counters[0];
+  if (st >= a.nsteps) return;
+  const int k = a.counters[1];
+  if (k < a.n_t && a.out_step[k] == st + 1) a.counters[1] = k + 1;
+  a.counters[0] = st + 1;
 }
 
 // Initial control state of every instance (single workgroup).
@@ -1958,7 +2035,7 @@ extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, in
   return hipErrorInvalidValue;
 }
 
-// Streamed adaptive stepper: kernel `which` of the sequence (see the host).
+// Streamed steppers: kernel `which` of the sequences (see the host).
 extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
                                               hipStream_t s) {
   using namespace lme;
@@ -1975,6 +2052,9 @@ extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::Str
     case 8: hipLaunchKernelGGL(sdp_hnw4_kernel<256>, dim3(grid), dim3(256), 0, s, *a); break;
     case 9: hipLaunchKernelGGL(sdp_hnw5_kernel<1024>, dim3(1), dim3(1024), 0, s, *a, arg); break;
     case 10: hipLaunchKernelGGL(sdp_final_kernel<1024>, dim3(1), dim3(1024), 0, s, *a); break;
+    case 20: hipLaunchKernelGGL(srk_stage_kernel<256>, dim3(grid), dim3(256), 0, s, *a, arg); break;
+    case 21: hipLaunchKernelGGL(srk_output_kernel<256>, dim3(a->n_inst), dim3(256), 0, s, *a); break;
+    case 22: hipLaunchKernelGGL(srk_tail_kernel, dim3(1), dim3(1), 0, s, *a, arg); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -311,3 +311,49 @@ def test_rk4_sweep_full_size_sampled():
         r = rho[b]
         assert abs(np.trace(r) - 1) < 1e-12
         assert np.max(np.abs(r - r.conj().T)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# streamed RK4 (state in HBM, graph of 16 steps replayed)
+# --------------------------------------------------------------------------
+
+def test_rk4_streamed_bitwise_equals_resident_across_replays():
+    w = S.jc_sweep(n_inst=10, seed=111, nsteps=37, t_end=0.925, n_out=38)
+    _, ref = run(w.systems, w.tlist, w.nsteps, layout=lme.LME_LAYOUT_ROW, block=512)
+    ref_ex, ref_rho = ref["expect"].cpu().numpy(), ref["rho"].cpu().numpy()
+    h = lme.Handle(w.systems)
+    rho0 = h.pack([s.rho0 for s in w.systems])
+    for rep in range(3):
+        o = h.evolve(rho0, w.tlist, nsteps=w.nsteps, path=lme.LME_PATH_STREAMED)
+        torch.cuda.synchronize()
+        assert np.array_equal(o["expect"].cpu().numpy(), ref_ex), rep
+        assert np.array_equal(o["rho"].cpu().numpy(), ref_rho), rep
+        assert (o["status"].cpu().numpy() == 0).all()
+        assert (o["counts"].cpu().numpy()[:, 0] == w.nsteps).all()
+        # eager work on the same handle between graph replays (re-captures the graph)
+        h.evolve(rho0, w.tlist[:2], nsteps=1, path=lme.LME_PATH_STREAMED)
+        h.apply(rho0)
+        torch.cuda.synchronize()
+
+
+def test_rk4_streamed_controls():
+    w = S.jc_drive(n_inst=4, N=5, n_seg=10, t_end=2.0, steps_per_seg=4, sigma_u=0.5)
+    tl = np.linspace(0.0, 2.0, 11)
+    h, out = run(w.systems, tl, w.nsteps, path=lme.LME_PATH_STREAMED)
+    _, ref = run(w.systems, tl, w.nsteps, layout=lme.LME_LAYOUT_ROW)
+    assert np.array_equal(out["rho"].cpu().numpy(), ref["rho"].cpu().numpy())
+    ex = out["expect"].cpu().numpy()
+    for b, s in enumerate(w.systems):
+        oex, _ = oracle.rk4(s, s.rho0, tl, w.nsteps)
+        assert np.max(np.abs(ex[b] - oex)) <= TD_BAR
+
+
+def test_rk4_large_instance_routes_to_streamed():
+    """N = 72 (dim 144, 324 KB per state): too large for a resident workgroup."""
+    s = S.jc_system(72, g=0.2, kappa=0.01, gamma=0.02)
+    s.rho0 = S.ket2dm(np.kron(S.coherent_ket(72, 2.0), S.ket(2, 1)))
+    tl = np.linspace(0.0, 0.5, 3)
+    h, out = run([s], tl, 50, want_states=True)
+    st = h.unpack(out["states"])[0]
+    _, ost = oracle.rk4(s, s.rho0, tl, 50, store_states=True)
+    assert max(td(a, b) for a, b in zip(st, ost)) <= TD_BAR
