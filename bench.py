@@ -102,6 +102,57 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
     return res
 
 
+def other_configs(lme, systems, torch):
+    """Wall time of each of the other headline configurations, one run after a
+    warm-up (HIP events on the launch stream; the adaptive streamed path
+    includes its host polling)."""
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), out
+
+    w = systems.jc_single()
+    h = lme.Handle(w.systems)
+    r0 = h.pack([s.rho0 for s in w.systems])
+    ms, _ = timed(lambda: h.evolve(r0, w.tlist, nsteps=w.nsteps))
+    res["jc_single_N10_rk4_2500"] = {"ms": ms, "instance_steps_per_s": w.nsteps / (ms * 1e-3)}
+
+    w = systems.kerr_single()
+    h = lme.Handle(w.systems)
+    r0 = h.pack([s.rho0 for s in w.systems])
+    ms, out = timed(lambda: h.evolve(r0, w.tlist, method="dopri5", rtol=w.rtol, atol=w.atol))
+    acc, rej = (int(x) for x in out["counts"].cpu().numpy()[0])
+    res["kerr_N60_dopri5_t50"] = {"ms": ms, "accepted": acc, "rejected": rej,
+                                  "instance_steps_per_s": acc / (ms * 1e-3)}
+
+    w = systems.jc_drive()
+    h = lme.Handle(w.systems)
+    r0 = h.pack([s.rho0 for s in w.systems])
+    O = h.pack([w.extra["target"]] * len(w.systems))
+    u = torch.from_numpy(w.extra["u"]).cuda()
+    ms, _ = timed(lambda: lme._cost_grad(h, r0, O, u, 0.0, 10.0, w.nsteps, 10))
+    res["jc_drive_256_cost_grad"] = {"ms": ms, "forward_instance_steps_per_s":
+                                     len(w.systems) * w.nsteps / (ms * 1e-3)}
+
+    w = systems.tfim()
+    h = lme.Handle(w.systems)
+    r0 = h.pack([s.rho0 for s in w.systems])
+    ms, out = timed(lambda: h.evolve(r0, w.tlist, method="dopri5", rtol=w.rtol, atol=w.atol))
+    acc = out["counts"].cpu().numpy()[:, 0]
+    res["tfim_8spin_64_dopri5_t20"] = {"ms": ms, "accepted_mean": float(acc.mean()),
+                                       "instance_steps_per_s": float(acc.sum()) / (ms * 1e-3),
+                                       "path": "streamed"}
+    return res
+
+
 def pmc_pass(lme, systems, torch):
     """One dispatch of each kernel of interest plus a copy of known size."""
     w = systems.jc_sweep()
@@ -132,6 +183,8 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other headline configurations")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run one of each kernel (and a 256 MiB device copy as the counter "
                          "reference) for a rocprofv3 --pmc pass, then exit")
@@ -237,6 +290,8 @@ def main():
                              "plain_sample": int(args.plain_sample)},
     }
     rec["streamed_apply"] = streamed_apply_bench(lme, systems, torch)
+    if not args.no_configs:
+        rec["other_configs"] = other_configs(lme, systems, torch)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, w.nsteps)
     print(json.dumps(rec), flush=True)
