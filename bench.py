@@ -77,11 +77,12 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
     w = systems.jc_sweep()
     h = lme.Handle(w.systems)
     y = h.pack([s.rho0 for s in w.systems], device="cuda:0")
+    tuned = h.autotune(y, w.nsteps)          # picks the application's LDS budget
     out = torch.empty_like(y)
     nbytes = 32.0 * h.state_elems
     stream = torch.cuda.current_stream()
     res = {"workload": "jc_sweep batch, 4096 instances (161 MB per state copy)",
-           "algorithmic_bytes": nbytes}
+           "algorithmic_bytes": nbytes, "apply_lds_kb": tuned["apply_lds_kb"]}
     for name, form in (("operator_lds", lme.LME_FORM_OPERATOR),
                        ("operator_global", lme.LME_FORM_OPERATOR_STREAMED),
                        ("superop", lme.LME_FORM_SUPEROP)):
@@ -158,7 +159,7 @@ def pmc_pass(lme, systems, torch):
     w = systems.jc_sweep()
     h = lme.Handle(w.systems)
     rho0 = h.pack([s.rho0 for s in w.systems], device="cuda:0")
-    h.set_tuning(rk4_layout=lme.LME_LAYOUT_COLUMN, rk4_block=768, apply_cap=1024)
+    h.set_tuning(rk4_layout=lme.LME_LAYOUT_COLUMN, rk4_block=768, apply_cap=8192)
     h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps)
     out = torch.empty_like(rho0)
     for form in (lme.LME_FORM_OPERATOR, lme.LME_FORM_OPERATOR_STREAMED, lme.LME_FORM_SUPEROP):

@@ -250,12 +250,15 @@ int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, d
  *   rk4_layout, rk4_block: used by lme_evolve (RK4) when the options leave
  *                          layout = LME_LAYOUT_AUTO and block = 0;
  *   apply_cap: elements per workgroup of the LDS-staged application
- *              (lme_apply, LME_FORM_OPERATOR), 256 .. 65536. */
+ *              (lme_apply, LME_FORM_OPERATOR, general operators), 256 .. 65536;
+ *   apply_lds_kb: see the field; 0 or 16 .. 160. */
 typedef struct lme_tuning {
   int32_t rk4_layout;
   int32_t rk4_block;
   int32_t apply_cap;
-  int32_t reserved;
+  int32_t apply_lds_kb;     /* LDS budget of one application workgroup (KB);
+                               0 = the device maximum; instances larger than
+                               the budget run alone                        */
   double rk4_ms_per_step;   /* lme_autotune: best trial time per RK4 step      */
   double apply_us;          /* lme_autotune: best trial time per application  */
 } lme_tuning;

@@ -32,6 +32,7 @@ using lme::PackDesc;
 
 extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap);
 extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb);
+extern "C" int lme_internal_blob_stride(int blob_bytes);
 extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
                                               int n_packs, int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb, int re,
@@ -48,6 +49,9 @@ extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a,
 extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
                                               hipStream_t s);
+extern "C" hipError_t lme_internal_launch_apply_col(int wo, int nc, int nb, int re,
+                                                    const lme::ApplyArgs *a, int n_packs,
+                                                    int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, int re,
                                                       const lme::ApplyArgs *a, int n_packs,
                                                       int lds, hipStream_t s);
@@ -198,7 +202,7 @@ struct DevBuf {
 // the handle
 // ---------------------------------------------------------------------------
 struct Plan {
-  int T = 0, EPT = 0, adjoint = 0, cap = 0, column = 0, dp = 0;
+  int T = 0, EPT = 0, adjoint = 0, cap = 0, column = 0, dp = 0, lds_budget = 0;
   std::vector<PackDesc> packs;
   std::vector<int32_t> order;
   int max_lds = 0;
@@ -229,14 +233,16 @@ struct lme_ctx {
   DevBuf d_kbuf;
   // gradient: checkpoints and one interval of stage inputs
   DevBuf d_ckpt;
-  // streamed kernels: element tiles
+  // streamed kernels: element tiles (per instance; packed-buffer chunks)
   std::vector<lme::Tile> tiles;
-  DevBuf d_tiles;
+  DevBuf d_tiles, d_ptiles;
+  int32_t n_ptiles = 0;
   // superoperator form (assembled on first use from the folded operators)
   std::vector<Sparse> A_host;
   std::vector<std::vector<Sparse>> C_host;
   DevBuf d_sd, d_scol, d_sval;
   int apply_cap = 4096;   // elements per pack of the LDS-staged application
+  int apply_lds_kb = 0;   // LDS budget per column-application workgroup (0: device)
   // streamed steppers: workspace, per-instance tile ranges, capture stream and
   // the instantiated one-step graph (re-captured when the arguments change)
   DevBuf d_sws, d_tile_rng;
@@ -556,10 +562,10 @@ static int ensure_device(lme_ctx *h) {
 // column) and m (instances per pack) with m*n*G <= T and ceil(n/G) <= EPT,
 // maximising the fraction of the workgroup's T*ept element slots in use.
 static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, int dp,
-                      Plan **out) {
+                      Plan **out, int lds_budget = 0) {
   for (Plan *p : h->plans)
     if (p->T == T && p->EPT == EPT && p->adjoint == adjoint && p->cap == cap &&
-        p->column == column && p->dp == dp) {
+        p->column == column && p->dp == dp && p->lds_budget == lds_budget) {
       *out = p;
       return LME_OK;
     }
@@ -581,7 +587,9 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
   p->cap = cap;
   p->column = column;
   p->dp = dp;
+  p->lds_budget = lds_budget;
   // LDS of a pack of m instances (the adaptive kernel adds its step control)
+  // dp: 1 adaptive kernel (step control), 2 gradient kernel (sums)
   auto pack_lds = [&](int n, int m, int blob, int nb) {
     return lme_internal_pack_lds_bytes(n, m, blob, nb) +
            (dp == 1 ? lme_internal_dp5_extra_lds(m) : dp == 2 ? lme::align16(8 * m) : 0);
@@ -594,17 +602,26 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
     const int n = s.n;
     const int64_t n2 = (int64_t)n * n;
     const int cnt = (int)g.second.size();
-    auto lds_fit = [&](int64_t m) {
+    // m instances that fit the LDS budget; an instance larger than the
+    // budget alone gets the device limit
+    auto lds_fit_in = [&](int64_t m, int64_t limit) {
       // at most kMaxPack instances (the kernels encode the pack slot in 10 bits)
       m = std::min<int64_t>(m, lme::kMaxPack);
-      const int64_t per_inst = 16 * n2 + blob + 8LL * s.nb + 12 + (dp ? 128 : 0);  // upper bound
-      m = std::min<int64_t>(m, std::max<int64_t>(0, (h->lds_limit - 48) / per_inst));
-      while (m > 0 && pack_lds(n, (int)m, blob, s.nb) > h->lds_limit) --m;
+      const int64_t per_inst = 16 * n2 + blob + 16 + 8LL * s.nb + 12 +
+                               (dp ? 128 : 0);  // upper bound
+      m = std::min<int64_t>(m, std::max<int64_t>(0, (limit - 48) / per_inst));
+      while (m > 0 && pack_lds(n, (int)m, blob, s.nb) > limit) --m;
       return (int)m;
+    };
+    auto lds_fit = [&](int64_t m) {
+      const int64_t budget = lds_budget > 0 ? std::min<int64_t>(lds_budget, h->lds_limit)
+                                            : h->lds_limit;
+      const int r = lds_fit_in(m, budget);
+      return (r > 0 || budget == h->lds_limit) ? r : lds_fit_in(std::min<int64_t>(m, 1), h->lds_limit);
     };
     int m_max = 0, G = 0;
     if (!column) {
-      m_max = lds_fit(cap / n2);
+      m_max = lds_fit(std::max<int64_t>(1, cap / n2));  // an instance larger than cap: alone
     } else {
       double best = -1.0;
       for (int gg = (n + EPT - 1) / EPT; gg <= n && gg * n <= T; ++gg) {
@@ -644,6 +661,8 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       pk.awb = d0.adj.wb;
       pk.awc = d0.adj.wc;
       pk.fwd_bytes = d0.fwd_bytes;
+      pk.blob_stride = lme_internal_blob_stride(blob);
+      pk.pad_ = 0;
       for (int r = 0; r < m; ++r) p->order.push_back(g.second[done + r]);
       done += m;
       p->packs.push_back(pk);
@@ -1300,14 +1319,37 @@ static int ensure_tiles(lme_ctx *h) {
   return LME_OK;
 }
 
+// Tiles of the streamed application: fixed kTileElems-element chunks of the
+// packed state buffer (spanning instances), each with its first instance.
+static int ensure_packed_tiles(lme_ctx *h) {
+  if (h->d_ptiles.p) return LME_OK;
+  std::vector<lme::Tile> t;
+  int b = 0;
+  for (int64_t e0 = 0; e0 < h->state_elems; e0 += kTileElems) {
+    while (h->offsets[b] + (int64_t)h->dims[b] * h->dims[b] <= e0) ++b;
+    lme::Tile x;
+    x.inst = b;
+    x.e0 = (int32_t)e0;
+    x.e1 = (int32_t)std::min<int64_t>(h->state_elems, e0 + kTileElems);
+    x.pad = 0;
+    t.push_back(x);
+  }
+  int rc = h->d_ptiles.upload(t.data(), t.size() * sizeof(lme::Tile), "packed tiles");
+  if (rc) return rc;
+  h->n_ptiles = (int32_t)t.size();
+  return LME_OK;
+}
+
 static int apply_streamed(lme_ctx *h, int adjoint, double t, const double *u_dev,
                           const void *y_dev, void *out_dev, hipStream_t s) {
-  int rc = ensure_tiles(h);
+  if (h->state_elems >= (int64_t)1 << 31)
+    return fail(LME_ENOTSUP, "the streamed application addresses states below 2^31 elements");
+  int rc = ensure_packed_tiles(h);
   if (rc) return rc;
   lme::ApplyGArgs a;
   std::memset(&a, 0, sizeof a);
-  a.tiles = static_cast<const lme::Tile *>(h->d_tiles.p);
-  a.n_tiles = (int32_t)h->tiles.size();
+  a.tiles = static_cast<const lme::Tile *>(h->d_ptiles.p);
+  a.n_tiles = h->n_ptiles;
   a.inst = static_cast<const InstDesc *>(h->d_inst.p);
   a.adjoint = adjoint;
   a.ops = static_cast<const uint8_t *>(adjoint ? h->d_adj.p : h->d_ops.p);
@@ -1415,12 +1457,34 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   }
   if (form == LME_FORM_OPERATOR_STREAMED)
     return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
+  int wo, nc, nb;
+  if (!adjoint && column_eligible(h, &wo, &nc, &nb)) {
+    // column-owner application: 1024 threads, up to 64 rows per thread
+    Plan *cp;
+    rc = plan_packs(h, 1024, 64, 0, 1024 * 64, 1, 0, &cp, h->apply_lds_kb * 1024);
+    if (rc == LME_OK) {
+      lme::ApplyArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.packs = static_cast<const PackDesc *>(cp->d_packs.p);
+      a.order = static_cast<const int32_t *>(cp->d_order.p);
+      a.inst = static_cast<const InstDesc *>(h->d_inst.p);
+      a.ops = static_cast<const uint8_t *>(h->d_ops.p);
+      a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+      a.n_ctrl = h->n_ctrl;
+      a.n_seg = h->n_seg;
+      a.seg = segment_at(h, t);
+      a.y = static_cast<const double *>(y_dev);
+      a.out = static_cast<double *>(out_dev);
+      hipError_t e = lme_internal_launch_apply_col(wo, nc, nb, real_structure(h), &a,
+                                                   (int)cp->packs.size(), cp->max_lds, s);
+      return e == hipSuccess ? LME_OK : hip_fail(e, "launch column application");
+    }
+    if (rc != LME_ENOTSUP) return rc;
+  }
   // packs of at most apply_cap elements: several workgroups per CU keep
   // enough HBM reads in flight
-  int max_n2 = 0;
-  for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
   Plan *plan;
-  rc = plan_packs(h, 256, 0, adjoint, std::max(h->apply_cap, max_n2), 0, 0, &plan);
+  rc = plan_packs(h, 256, 0, adjoint, h->apply_cap, 0, 0, &plan);
   if (rc == LME_ENOTSUP) return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
   if (rc) return rc;
   lme::ApplyArgs a;
@@ -1436,7 +1500,6 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   a.seg = segment_at(h, t);
   a.y = static_cast<const double *>(y_dev);
   a.out = static_cast<double *>(out_dev);
-  int wo, nc, nb;
   hipError_t e;
   if (!adjoint && column_eligible(h, &wo, &nc, &nb))
     e = lme_internal_launch_apply_shape(wo, nc, nb, real_structure(h), &a,
@@ -1552,6 +1615,7 @@ extern "C" int lme_get_tuning(lme_handle h, lme_tuning *t) {
   if (!h || !t) return fail(LME_EINVAL, "handle and tuning must not be NULL");
   *t = h->tuning;
   t->apply_cap = h->apply_cap;
+  t->apply_lds_kb = h->apply_lds_kb;
   return LME_OK;
 }
 
@@ -1564,9 +1628,12 @@ extern "C" int lme_set_tuning(lme_handle h, const lme_tuning *t) {
     return fail(LME_EINVAL, "block must be 0, 256, 512, 768 or 1024");
   if (t->apply_cap != 0 && (t->apply_cap < 256 || t->apply_cap > 65536))
     return fail(LME_EINVAL, "apply_cap must be 0 or in [256, 65536]");
+  if (t->apply_lds_kb != 0 && (t->apply_lds_kb < 16 || t->apply_lds_kb > 160))
+    return fail(LME_EINVAL, "apply_lds_kb must be 0 or in [16, 160]");
   h->tuning = *t;
   h->apply_cap = t->apply_cap ? t->apply_cap : 4096;
   h->tuning.apply_cap = h->apply_cap;
+  h->apply_lds_kb = t->apply_lds_kb;
   return LME_OK;
 }
 
@@ -1648,23 +1715,28 @@ static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_
   h->tuning.rk4_block = win.block;
   h->tuning.rk4_ms_per_step = best / trial;
 
-  // LDS-staged application: pack size
+  // application: pack size (row layout) and LDS budget (column layout)
   float best_a = -1.0f;
-  int best_cap = h->apply_cap;
-  for (int cap : {1024, 2048, 4096, 8192, 16384}) {
-    h->apply_cap = cap;
-    float us = 0.0f;
-    rc = time_ms([&]() { return apply_impl(h, LME_FORM_OPERATOR, 0, 0.0, nullptr, rho0_dev,
-                                           out.p, stream); }, 5, &us);
-    if (rc == LME_ENOTSUP) continue;
-    if (rc) return rc;
-    if (best_a < 0.0f || us < best_a) {
-      best_a = us;
-      best_cap = cap;
+  int best_cap = h->apply_cap, best_kb = h->apply_lds_kb;
+  for (int kb : {0, 80, 53, 40})
+    for (int cap : {512, 2048, 8192}) {
+      h->apply_cap = cap;
+      h->apply_lds_kb = kb;
+      float us = 0.0f;
+      rc = time_ms([&]() { return apply_impl(h, LME_FORM_OPERATOR, 0, 0.0, nullptr, rho0_dev,
+                                             out.p, stream); }, 5, &us);
+      if (rc == LME_ENOTSUP) continue;
+      if (rc) return rc;
+      if (best_a < 0.0f || us < best_a) {
+        best_a = us;
+        best_cap = cap;
+        best_kb = kb;
+      }
     }
-  }
   h->apply_cap = best_cap;
+  h->apply_lds_kb = best_kb;
   h->tuning.apply_cap = best_cap;
+  h->tuning.apply_lds_kb = best_kb;
   h->tuning.apply_us = best_a * 1e3;
   if (result) *result = h->tuning;
   return LME_OK;

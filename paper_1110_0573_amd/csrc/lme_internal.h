@@ -102,6 +102,8 @@ struct PackDesc {
   int32_t ept;        // column-owner kernels: rows per thread, ceil(n / G)
   int32_t awo, awb, awc;  // gradient kernel: widths of the adjoint blob
   int32_t fwd_bytes;      // gradient kernel: forward part of blob_bytes
+  int32_t blob_stride;    // LDS distance between consecutive instances' blobs
+  int32_t pad_;
 };
 
 // Column-owner kernels hold one column's operator entries in registers; they

@@ -79,14 +79,14 @@ __device__ __forceinline__ double2 two_sided(const double2 *D, const double2 *Ov
 }
 
 // Element (i, j) of L y for one instance; Y is that instance's n x n stage
-// input, uq its nb control amplitudes for the current step.
+// input, uq[q * ustride] its nb control amplitudes for the current step.
 __device__ __forceinline__ double2 lindblad_elem(const OpView &op, const double2 *Y,
                                                  int i, int j, double2 yij,
-                                                 const double *uq) {
+                                                 const double *uq, int ustride = 1) {
   const int n = op.n;
   double2 acc = two_sided(op.D, op.Oval, op.Ocol, op.wo, n, Y, i, j, yij);
   for (int q = 0; q < op.nb; ++q) {
-    const double u = uq[q];
+    const double u = uq[q * ustride];
     if (u != 0.0) {
       const double2 t = two_sided(op.DB + q * n, op.OBval + q * op.wb * n,
                                   op.OBcol + q * op.wb * n, op.wb, n, Y, i, j, yij);
@@ -118,7 +118,7 @@ __device__ __forceinline__ void stage_blobs(uint8_t *dst, const PackDesc &pk,
     const int b = idx / nvec, r = idx - b * nvec;
     const InstDesc &d = inst[order[pk.first + b]];
     const uint4 *src = reinterpret_cast<const uint4 *>(pool + (adjoint ? d.adj_off : d.ops_off));
-    reinterpret_cast<uint4 *>(dst + (size_t)b * pk.blob_bytes)[r] = src[r];
+    reinterpret_cast<uint4 *>(dst + (size_t)b * pk.blob_stride)[r] = src[r];
   }
 }
 
@@ -142,10 +142,17 @@ struct PackLds {
   int32_t *ids;
 };
 
+// LDS stride between the op blobs of a pack: an odd number of 16-byte units,
+// so that the lanes of one wave reading the same row of different instances
+// fall into different LDS banks.
+__host__ __device__ inline int32_t blob_stride_of(int32_t blob_bytes) {
+  return ((blob_bytes / 16) & 1) ? blob_bytes : blob_bytes + 16;
+}
+
 __host__ __device__ inline int32_t pack_lds_bytes(int32_t n, int32_t m, int32_t blob_bytes,
                                                   int32_t nb) {
-  return align16(16 * m * n * n) + m * blob_bytes + align16(8 * m * nb) + align16(8 * m) +
-         align16(4 * m);
+  return align16(16 * m * n * n) + m * blob_stride_of(blob_bytes) + align16(8 * m * nb) +
+         align16(8 * m) + align16(4 * m);
 }
 
 __device__ __forceinline__ PackLds carve(uint8_t *smem, const PackDesc &pk) {
@@ -153,7 +160,7 @@ __device__ __forceinline__ PackLds carve(uint8_t *smem, const PackDesc &pk) {
   const int E = pk.m * pk.n * pk.n;
   p.Y = reinterpret_cast<double2 *>(smem);
   p.blobs = smem + align16(16 * E);
-  p.u = reinterpret_cast<double *>(p.blobs + (size_t)pk.m * pk.blob_bytes);
+  p.u = reinterpret_cast<double *>(p.blobs + (size_t)pk.m * pk.blob_stride);
   p.off = reinterpret_cast<int64_t *>(reinterpret_cast<uint8_t *>(p.u) + align16(8 * pk.m * pk.nb));
   p.ids = reinterpret_cast<int32_t *>(reinterpret_cast<uint8_t *>(p.off) + align16(8 * pk.m));
   return p;
@@ -297,7 +304,7 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
           // hoisted out of the step loop (which costs ~20 VGPRs per slot)
           asm volatile("" : "+v"(v));
           const int b = slot_b(v);
-          const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+          const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
           const double2 kv =
               lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), yn[s], L.u + b * pk.nb);
           acc[s] = caxpy(wgt, kv, acc[s]);
@@ -500,7 +507,7 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   const int g = active ? tid / C : 0;
   const int c = active ? tid - g * C : 0;
   const int b = c / n, j = c - b * n;
-  const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+  const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
   double2 *Yb = L.Y + b * n2;
   ColData<WO, NC, NB> cd;
   load_column<WO, NC, NB>(cd, op, j);
@@ -764,7 +771,7 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     uint32_t v = bij[s];
     asm volatile("" : "+v"(v));  // no per-slot addresses hoisted across steps
     const int b = slot_b(v);
-    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
     return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), y, L.u + b * pk.nb);
   };
 
@@ -1034,7 +1041,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
       const InstDesc &d = a.inst[a.order[pk.first + b]];
       const uint4 *src = r < nf ? reinterpret_cast<const uint4 *>(a.ops + d.ops_off) + r
                                 : reinterpret_cast<const uint4 *>(a.adj + d.adj_off) + (r - nf);
-      reinterpret_cast<uint4 *>(L.blobs + (size_t)b * pk.blob_bytes)[r] = *src;
+      reinterpret_cast<uint4 *>(L.blobs + (size_t)b * pk.blob_stride)[r] = *src;
     }
   }
   for (int b = tid; b < m; b += T) {
@@ -1073,7 +1080,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
     uint32_t v = bij[s];
     asm volatile("" : "+v"(v));
     const int b = slot_b(v);
-    const uint8_t *blob = L.blobs + (size_t)b * pk.blob_bytes;
+    const uint8_t *blob = L.blobs + (size_t)b * pk.blob_stride;
     const OpView op = adjoint ? make_view(blob + pk.fwd_bytes, BA) : make_view(blob, BF);
     return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), yij, L.u + b * pk.nb);
   };
@@ -1247,7 +1254,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
             if (valid(s)) {
               const uint32_t v = bij[s];
               const int b = slot_b(v), i = slot_i(v), j = slot_j(v);
-              const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BF);
+              const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BF);
               const double2 *Yb = L.Y + b * n2;
               const double2 yij = Yb[i * n + j];
 #pragma unroll
@@ -1306,7 +1313,7 @@ __global__ __launch_bounds__(T) void apply_lds_kernel(ApplyArgs a) {
   for (int f = threadIdx.x; f < E; f += T) {
     const int b = f / n2, r = f - b * n2;
     const int i = r / n, j = r - i * n;
-    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
     const double2 kv = lindblad_elem(op, L.Y + b * n2, i, j, L.Y[f], L.u + b * pk.nb);
     reinterpret_cast<double2 *>(a.out)[L.off[b] + r] = kv;
   }
@@ -1346,12 +1353,58 @@ __global__ __launch_bounds__(T) void apply_shape_kernel(ApplyArgs a) {
   for (int f = threadIdx.x; f < E; f += T) {
     const int b = f / n2, r = f - b * n2;
     const int i = r / n, j = r - i * n;
-    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_bytes, BL);
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
     ColData<WO, NC, NB> cd;
     load_column<WO, NC, NB>(cd, op, j);
     const uint32_t ri = row_indices<WO, NC>(op, i);
     out[L.off[b] + r] =
         lindblad_col<WO, NC, NB, RE>(op, cd, L.Y + b * n2, i, ri, j, L.Y[f], L.u + b * pk.nb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One application of L, column-owner layout (the pack plan of the column
+// kernels: thread t < m*n*G owns column j of instance b and rows g, g+G, ...):
+// each thread copies its own elements of y into LDS (coalesced along j),
+// loads its column's operator data once, then computes and stores its
+// elements (coalesced).  No per-element index division.
+// ---------------------------------------------------------------------------
+template <int T, int WO, int NC, int NB, bool RE>
+__global__ __launch_bounds__(T) void apply_col_kernel(ApplyArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, C = pk.m * n, G = pk.G;
+  const PackLds L = carve(smem, pk);
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  const int tid = threadIdx.x;
+  for (int b = tid; b < pk.m; b += T) {
+    L.ids[b] = a.order[pk.first + b];
+    L.off[b] = a.inst[L.ids[b]].rho_off;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
+  __syncthreads();
+  for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+    const int b = idx / pk.nb, q = idx - b * pk.nb;
+    L.u[idx] = a.seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + a.seg] : 0.0;
+  }
+  const bool active = tid < C * G;
+  const int g = active ? tid / C : 0;
+  const int c = active ? tid - g * C : 0;
+  const int b = c / n, j = c - b * n;
+  double2 *Yb = L.Y + b * n2;
+  const double2 *y = reinterpret_cast<const double2 *>(a.y) + L.off[b];
+  double2 *out = reinterpret_cast<double2 *>(a.out) + L.off[b];
+  if (active)
+    for (int i = g; i < n; i += G) Yb[i * n + j] = y[i * n + j];
+  __syncthreads();
+  if (!active) return;
+  const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
+  ColData<WO, NC, NB> cd;
+  load_column<WO, NC, NB>(cd, op, j);
+  for (int i = g; i < n; i += G) {
+    const uint32_t ri = row_indices<WO, NC>(op, i);
+    out[i * n + j] = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, Yb[i * n + j],
+                                                  L.u + b * pk.nb);
   }
 }
 
@@ -1374,23 +1427,31 @@ __device__ __forceinline__ int xcd_tile(int n_tiles) {
 
 template <int T>
 __global__ __launch_bounds__(T) void apply_global_kernel(ApplyGArgs a) {
-  __shared__ double uq[kMaxWidth];
+  // tiles are fixed 2048-element chunks of the packed state buffer and may
+  // span several instances; e0/e1 are packed offsets, inst the first instance
   const int tix = xcd_tile(a.n_tiles);
   if (tix >= a.n_tiles) return;
   const Tile tl = a.tiles[tix];
-  const InstDesc &d = a.inst[tl.inst];
-  const int n = d.n;
-  const Signature &sg = a.adjoint ? d.adj : d.fwd;
-  const BlobLayout BL = blob_layout(n, sg.wo, sg.nb, sg.wb, sg.nc, sg.wc);
-  const OpView op = make_view(a.ops + (a.adjoint ? d.adj_off : d.ops_off), BL);
-  for (int q = threadIdx.x; q < sg.nb; q += T)
-    uq[q] = a.seg >= 0 ? a.u[((int64_t)tl.inst * a.n_ctrl + q) * a.n_seg + a.seg] : 0.0;
-  __syncthreads();
-  const double2 *Y = reinterpret_cast<const double2 *>(a.y) + d.rho_off;
-  double2 *out = reinterpret_cast<double2 *>(a.out) + d.rho_off;
-  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += T) {
+  const double2 *Y = reinterpret_cast<const double2 *>(a.y);
+  double2 *out = reinterpret_cast<double2 *>(a.out);
+  int b = tl.inst;
+  int64_t lo = a.inst[b].rho_off, hi = lo + (int64_t)a.inst[b].n * a.inst[b].n;
+  for (int64_t g = tl.e0 + threadIdx.x; g < tl.e1; g += T) {
+    while (g >= hi) {  // next instance (monotone)
+      ++b;
+      lo = hi;
+      hi = lo + (int64_t)a.inst[b].n * a.inst[b].n;
+    }
+    const InstDesc &d = a.inst[b];
+    const int n = d.n;
+    const Signature &sg = a.adjoint ? d.adj : d.fwd;
+    OpView op = make_view(a.ops + (a.adjoint ? d.adj_off : d.ops_off),
+                          blob_layout(n, sg.wo, sg.nb, sg.wb, sg.nc, sg.wc));
+    if (a.seg < 0) op.nb = 0;  // no control amplitude outside all segments
+    const double *uq = a.u + (int64_t)b * a.n_ctrl * a.n_seg + (a.seg < 0 ? 0 : a.seg);
+    const int e = (int)(g - lo);
     const int i = e / n, j = e - i * n;
-    out[e] = lindblad_elem(op, Y, i, j, Y[e], uq);
+    out[g] = lindblad_elem(op, Y + lo, i, j, Y[g], uq, a.n_seg);
   }
 }
 
@@ -1892,6 +1953,8 @@ extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap) {
   return nc;
 }
 
+extern "C" int lme_internal_blob_stride(int blob_bytes) { return lme::blob_stride_of(blob_bytes); }
+
 extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb) {
   return lme::pack_lds_bytes(n, m, blob_bytes, nb);
 }
@@ -2014,12 +2077,36 @@ extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipSt
 template <int WO, int NC, int NB, bool RE>
 static hipError_t launch_apply_shape_t(const lme::ApplyArgs &a, int n_packs, int lds,
                                        hipStream_t s) {
-  auto k = lme::apply_shape_kernel<256, WO, NC, NB, RE>;
+  auto k = lme::apply_shape_kernel<1024, WO, NC, NB, RE>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(n_packs), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(1024), lds, s, a);
   return hipGetLastError();
+}
+
+template <int WO, int NC, int NB, bool RE>
+static hipError_t launch_apply_col_t(const lme::ApplyArgs &a, int n_packs, int lds,
+                                     hipStream_t s) {
+  auto k = lme::apply_col_kernel<1024, WO, NC, NB, RE>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(1024), lds, s, a);
+  return hipGetLastError();
+}
+
+// Column-owner application, 1024 threads (the column-kernel shapes).
+extern "C" hipError_t lme_internal_launch_apply_col(int wo, int nc, int nb, int re,
+                                                    const lme::ApplyArgs *a, int n_packs,
+                                                    int lds, hipStream_t s) {
+#define LME_AC(W, K, B, R) \
+  if (wo == W && nc == K && nb == B && re == R) \
+    return launch_apply_col_t<W, K, B, (R != 0)>(*a, n_packs, lds, s);
+  LME_AC(1, 2, 0, 0) LME_AC(1, 3, 0, 0) LME_AC(2, 2, 0, 0) LME_AC(1, 2, 1, 0) LME_AC(1, 3, 1, 0)
+  LME_AC(1, 2, 0, 1) LME_AC(1, 3, 0, 1) LME_AC(2, 2, 0, 1) LME_AC(1, 2, 1, 1) LME_AC(1, 3, 1, 1)
+#undef LME_AC
+  return hipErrorInvalidValue;
 }
 
 // Shape-specialised application (the shapes of the column-owner kernels).
@@ -2062,10 +2149,10 @@ extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::Str
 
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s) {
-  auto k = lme::apply_lds_kernel<256>;
+  auto k = lme::apply_lds_kernel<1024>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(n_packs), dim3(256), lds, s, *a);
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(1024), lds, s, *a);
   return hipGetLastError();
 }

@@ -116,11 +116,11 @@ def default_options(**kw):
 
 class Tuning(C.Structure):
     _fields_ = [("rk4_layout", C.c_int32), ("rk4_block", C.c_int32), ("apply_cap", C.c_int32),
-                ("reserved", C.c_int32), ("rk4_ms_per_step", C.c_double),
+                ("apply_lds_kb", C.c_int32), ("rk4_ms_per_step", C.c_double),
                 ("apply_us", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class _CsrKeep:
