@@ -53,6 +53,12 @@ def rk4_step_flops(s):
     return 4.0 * apply_flops(s) + 36.0 * s.n * s.n
 
 
+def rk4_step_flops_hermitian(s):
+    """The same step when rho is Hermitian: each of the n(n+1)/2 pairs {i, j}
+    is computed once (the element flops above scale with the elements)."""
+    return rk4_step_flops(s) * (s.n + 1) / (2.0 * s.n)
+
+
 def cpu_baseline(w, sample, nsteps_full):
     """The oracle (plain C, -O3) on a bounded sample of the same workload,
     one instance per host thread."""
@@ -159,8 +165,10 @@ def pmc_pass(lme, systems, torch):
     w = systems.jc_sweep()
     h = lme.Handle(w.systems)
     rho0 = h.pack([s.rho0 for s in w.systems], device="cuda:0")
-    h.set_tuning(rk4_layout=lme.LME_LAYOUT_COLUMN, rk4_block=768, apply_cap=8192)
+    h.set_tuning(rk4_layout=lme.LME_LAYOUT_COLUMN, rk4_block=768, apply_cap=8192,
+                 herm_layout=lme.LME_LAYOUT_COLUMN, herm_block=1024)
     h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps)
+    h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps, hermitian=True)
     out = torch.empty_like(rho0)
     for form in (lme.LME_FORM_OPERATOR, lme.LME_FORM_OPERATOR_STREAMED, lme.LME_FORM_SUPEROP):
         rc = lme.load().lme_apply(h._h, form, 0, 0.0, None, lme._ptr(rho0), lme._ptr(out),
@@ -181,6 +189,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--layout", type=int, default=0)
+    ap.add_argument("--full", action="store_true",
+                    help="headline without the Hermitian path (every element computed)")
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
@@ -212,35 +222,50 @@ def main():
     rho0 = h.pack([s.rho0 for s in w.systems], device="cuda:0")
     stream = torch.cuda.current_stream()
 
+    herm = not args.full   # density matrices: rho0 is Hermitian
     tuning = None
     if args.block == 0 and args.layout == 0:
-        tuning = h.autotune(rho0, w.nsteps, stream=stream)   # outside the timed region
+        # outside the timed region; the full-path tuning serves the comparison
+        tuning = h.autotune(rho0, w.nsteps, hermitian=herm, stream=stream)
+        if herm:
+            h.autotune(rho0, w.nsteps, hermitian=False, stream=stream)
 
-    def one():
+    def one(hermitian=herm):
         return h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block,
-                        layout=args.layout, stream=stream)
+                        layout=args.layout, hermitian=hermitian, stream=stream)
 
-    for _ in range(args.warmup):
-        one()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        out = one()
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    assert (out["status"].cpu().numpy() == 0).all()
+    def timed_steps(hermitian):
+        for _ in range(args.warmup):
+            one(hermitian)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            out = one(hermitian)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert (out["status"].cpu().numpy() == 0).all()
+        return wall * 1e3 / args.steps, [a.elapsed_time(b) for a, b in ev]
 
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step, kern_ms = timed_steps(herm)
     inst_steps = n_inst * w.nsteps
     value = inst_steps / (ms_per_step * 1e-3)
+    full_path = None
+    if herm:
+        f_ms, f_kern = timed_steps(False)
+        f_flops = sum(rk4_step_flops(s) for s in w.systems) * w.nsteps
+        f_kms = float(np.mean(f_kern))
+        full_path = {"value": inst_steps / (f_ms * 1e-3), "ms_per_step": f_ms,
+                     "kernel_ms": f_kms,
+                     "achieved_tflops": f_flops / (f_kms * 1e-3) / 1e12,
+                     "frac": f_flops / (f_kms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
 
-    flops = sum(rk4_step_flops(s) for s in w.systems) * w.nsteps
+    step_flops = rk4_step_flops_hermitian if herm else rk4_step_flops
+    flops = sum(step_flops(s) for s in w.systems) * w.nsteps
     k_ms = float(np.mean(kern_ms))
     achieved = flops / (k_ms * 1e-3) / 1e12
     # HBM bytes the path must move: rho0 in, final rho out, expectations out
@@ -253,12 +278,12 @@ def main():
     prho = [p.pack([w.systems[i].rho0], device="cuda:0") for p, i in zip(plain, pidx)]
     for p, r in zip(plain, prho):
         p.evolve(r, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block,
-                 layout=args.layout, stream=stream)
+                 layout=args.layout, hermitian=herm, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for p, r in zip(plain, prho):
         p.evolve(r, w.tlist, method="rk4", nsteps=w.nsteps, block=args.block,
-                 layout=args.layout, stream=stream)
+                 layout=args.layout, hermitian=herm, stream=stream)
     torch.cuda.synchronize()
     plain_rate = args.plain_sample * w.nsteps / (time.perf_counter() - t1)
 
@@ -279,17 +304,21 @@ def main():
                                "(dims 10..80), fixed-step RK4, 1000 steps, 101 outputs",
                    "instances": n_inst, "rk_steps": w.nsteps, "outputs": len(w.tlist),
                    "state_MB": 16 * h.state_elems / 1e6, "path": "resident",
+                   "hermitian": herm,
                    "block": args.block or "tuned", "layout": args.layout or "tuned",
                    "tuning": tuning},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "rk4_colown_kernel",
+                     "traffic": None,
+                     "kernel": "rk4_colown_kernel" + (" (Hermitian)" if herm else ""),
                      "kernel_ms": k_ms, "algorithmic_flops": flops},
         "hbm": {"algorithmic_bytes": hbm_bytes, "GBs": hbm_bytes / (k_ms * 1e-3) / 1e9,
                 "note": "state stays on chip for all steps; HBM moves rho0, rho, outputs"},
         "batched_vs_plain": {"plain_value": plain_rate, "speedup": value / plain_rate,
                              "plain_sample": int(args.plain_sample)},
     }
+    if full_path:
+        rec["full_path"] = full_path
     rec["streamed_apply"] = streamed_apply_bench(lme, systems, torch)
     if not args.no_configs:
         rec["other_configs"] = other_configs(lme, systems, torch)

@@ -61,7 +61,9 @@ typedef enum lme_status {
   LME_ENONFINITE = 5,      /* NaN/Inf in an error norm or expectation (device)*/
   LME_ENOMEM = 6,          /* host or device allocation failed                */
   LME_EHIP = 7,            /* a HIP runtime call failed (no device, launch)   */
-  LME_ENOTSUP = 8          /* valid input outside what this build supports    */
+  LME_ENOTSUP = 8,         /* valid input outside what this build supports    */
+  LME_ENOTHERM = 9         /* hermitian option with a non-Hermitian rho0 of
+                              that instance (device, per instance)            */
 } lme_status;
 
 typedef struct lme_ctx *lme_handle;
@@ -134,7 +136,8 @@ typedef struct lme_options {
                               every output time must be on this grid          */
   int32_t block;           /* resident path: threads per workgroup; 0 = tuned
                               default.  Row layout: 256, 512 or 1024.
-                              Column layout: 512 or 768                       */
+                              Column layout: 512 or 768 (768 or 1024 with
+                              hermitian = 1)                                  */
   int32_t layout;          /* resident path, thread-to-element layout:
                               LME_LAYOUT_AUTO, LME_LAYOUT_ROW (any operator)
                               or LME_LAYOUT_COLUMN (monomial collapse
@@ -148,10 +151,24 @@ typedef struct lme_options {
   double h_min;            /* DOPRI5: smallest allowed step                   */
   int64_t max_steps;       /* DOPRI5: attempts (accepted + rejected) per
                               instance                                        */
+  int32_t hermitian;       /* 1: rho0 is Hermitian (a density matrix).  The
+                              Lindblad generator maps Hermitian matrices to
+                              Hermitian matrices, so every stage input and
+                              every state stays Hermitian; the resident RK4
+                              column-layout kernel then computes each pair
+                              {i, j} once and writes its mirror as the
+                              conjugate (half the arithmetic).  rho0 is read
+                              as its Hermitian part; an instance with
+                              |rho_ij - conj(rho_ji)| > 1e-12 sqrt(2(|rho_ij|^2
+                              + |rho_ji|^2)) for some pair gets status
+                              LME_ENOTHERM (and is integrated from that
+                              Hermitian part).  Other paths ignore the flag
+                              and compute every element.  0: no assumption  */
+  int32_t reserved;        /* unused; set to 0                                */
 } lme_options;
 
 /* Fills defaults: RK4, AUTO path, nsteps 0 (must be set), block 0, layout 0,
- * rtol 1e-6, atol 1e-9, h0 0, h_min 0, max_steps 10^7. */
+ * rtol 1e-6, atol 1e-9, h0 0, h_min 0, max_steps 10^7, hermitian 0. */
 void lme_default_options(lme_options *opt);
 
 /* Create a handle for a batch of n_inst independent systems.
@@ -249,6 +266,7 @@ int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, d
  * results).  0 in a field means "library default".
  *   rk4_layout, rk4_block: used by lme_evolve (RK4) when the options leave
  *                          layout = LME_LAYOUT_AUTO and block = 0;
+ *   herm_layout, herm_block: the same for runs with options.hermitian = 1;
  *   apply_cap: elements per workgroup of the LDS-staged application
  *              (lme_apply, LME_FORM_OPERATOR, general operators), 256 .. 65536;
  *   apply_lds_kb: see the field; 0 or 16 .. 160. */
@@ -261,6 +279,9 @@ typedef struct lme_tuning {
                                the budget run alone                        */
   double rk4_ms_per_step;   /* lme_autotune: best trial time per RK4 step      */
   double apply_us;          /* lme_autotune: best trial time per application  */
+  int32_t herm_layout;
+  int32_t herm_block;       /* column layout: 768 or 1024                      */
+  double herm_ms_per_step;  /* lme_autotune (hermitian = 1): best trial time   */
 } lme_tuning;
 
 int lme_get_tuning(lme_handle h, lme_tuning *t);
@@ -270,6 +291,8 @@ int lme_set_tuning(lme_handle h, const lme_tuning *t);
  * size) on a trial of min(opt->nsteps, 40) steps of this batch from rho0_dev,
  * and every pack size of the LDS-staged application, with HIP events on
  * `stream`; stores the fastest in the handle and in *result (may be NULL).
+ * With opt->hermitian = 1 the RK4 trials use the Hermitian kernels and fill
+ * herm_layout / herm_block / herm_ms_per_step instead of the rk4_ fields.
  * Synchronises the stream.  Uses a device scratch of two states.
  * Errors as lme_evolve. */
 int lme_autotune(lme_handle h, const lme_options *opt, const void *rho0_dev, void *stream,

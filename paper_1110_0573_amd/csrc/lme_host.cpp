@@ -35,7 +35,8 @@ extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb)
 extern "C" int lme_internal_blob_stride(int blob_bytes);
 extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
                                               int n_packs, int lds, hipStream_t s);
-extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb, int re,
+extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int herm, int wo, int nc, int nb,
+                                                     int re,
                                                      const lme::Rk4Args *a, int n_packs,
                                                      int lds, hipStream_t s);
 extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
@@ -561,6 +562,8 @@ static int ensure_device(lme_ctx *h) {
 // Column layout (column == 1): per signature group choose G (threads per
 // column) and m (instances per pack) with m*n*G <= T and ceil(n/G) <= EPT,
 // maximising the fraction of the workgroup's T*ept element slots in use.
+// Hermitian column layout (column == 2): the same with n/2 + 1 rows per
+// column.
 static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, int dp,
                       Plan **out, int lds_budget = 0) {
   for (Plan *p : h->plans)
@@ -620,15 +623,16 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       return (r > 0 || budget == h->lds_limit) ? r : lds_fit_in(std::min<int64_t>(m, 1), h->lds_limit);
     };
     int m_max = 0, G = 0;
+    const int R = column == 2 ? n / 2 + 1 : n;  // rows per column
     if (!column) {
       m_max = lds_fit(std::max<int64_t>(1, cap / n2));  // an instance larger than cap: alone
     } else {
       double best = -1.0;
-      for (int gg = (n + EPT - 1) / EPT; gg <= n && gg * n <= T; ++gg) {
-        const int ept = (n + gg - 1) / gg;
+      for (int gg = (R + EPT - 1) / EPT; gg <= R && gg * n <= T; ++gg) {
+        const int ept = (R + gg - 1) / gg;
         const int m = lds_fit(std::min<int64_t>(T / (gg * n), cnt));
         if (m < 1) continue;
-        const double eff = (double)m * n2 / ((double)ept * T);
+        const double eff = (double)m * n * R / ((double)ept * T);
         if (eff > best + 1e-12) {
           best = eff;
           m_max = m;
@@ -656,7 +660,7 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       pk.blob_bytes = blob;
       pk.lds_bytes = pack_lds(n, m, blob, s.nb);
       pk.G = G;
-      pk.ept = G > 0 ? (n + G - 1) / G : 0;
+      pk.ept = G > 0 ? (R + G - 1) / G : 0;
       pk.awo = d0.adj.wo;
       pk.awb = d0.adj.wb;
       pk.awc = d0.adj.wc;
@@ -798,10 +802,10 @@ static int real_structure(const lme_ctx *h) {
   return 1;
 }
 
-static bool column_fits(const lme_ctx *h, int T, int EPT) {
+static bool column_fits(const lme_ctx *h, int T, int EPT, bool herm) {
   for (auto &d : h->inst) {
-    const int n = d.n;
-    if ((int64_t)n * ((n + EPT - 1) / EPT) > T) return false;
+    const int n = d.n, R = herm ? n / 2 + 1 : n;
+    if ((int64_t)n * ((R + EPT - 1) / EPT) > T) return false;
   }
   return true;
 }
@@ -1181,6 +1185,8 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if (opt->block != 0 && opt->block != 256 && opt->block != 512 && opt->block != 768 &&
       opt->block != 1024)
     return fail(LME_EINVAL, "block must be 0, 256, 512, 768 or 1024");
+  if (opt->hermitian != 0 && opt->hermitian != 1)
+    return fail(LME_EINVAL, "hermitian must be 0 or 1");
   if (opt->method == LME_DOPRI5)
     return evolve_dp5(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
                       counts_dev, status_dev, stream);
@@ -1193,21 +1199,26 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
     return fail(LME_EINVAL, "unknown layout %d", opt->layout);
   lme_options tuned = *opt;  // tuned defaults fill the fields left open
-  if (tuned.layout == LME_LAYOUT_AUTO && tuned.block == 0 && h->tuning.rk4_block > 0) {
-    tuned.layout = h->tuning.rk4_layout;
-    tuned.block = h->tuning.rk4_block;
+  const bool herm = opt->hermitian == 1;
+  const int tl_layout = herm ? h->tuning.herm_layout : h->tuning.rk4_layout;
+  const int tl_block = herm ? h->tuning.herm_block : h->tuning.rk4_block;
+  if (tuned.layout == LME_LAYOUT_AUTO && tuned.block == 0 && tl_block > 0) {
+    tuned.layout = tl_layout;
+    tuned.block = tl_block;
   }
   opt = &tuned;
-  // column layout: T in {512, 768}; row layout: T in {256, 512, 1024}
+  // column layout: T in {512, 768} (Hermitian: {768, 1024}); row layout:
+  // T in {256, 512, 1024}
   int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0;
   const int re = real_structure(h);
   if (opt->layout != LME_LAYOUT_ROW && column_eligible(h, &wo, &nc, &nb)) {
-    for (int c = 1; c >= 0; --c) {   // prefer the 768-thread configuration
-      const int cT = lme::kColCfg[c][0], cE = lme::kColCfg[c][1];
-      if ((opt->block == 0 || opt->block == cT) && column_fits(h, cT, cE)) {
+    for (int c = 1; c >= 0; --c) {   // prefer the larger workgroup
+      const int cT = herm ? lme::kHermCfg[c][0] : lme::kColCfg[c][0];
+      const int cE = herm ? lme::kHermCfg[c][1] : lme::kColCfg[c][1];
+      if ((opt->block == 0 || opt->block == cT) && column_fits(h, cT, cE, herm)) {
         T = cT;
         EPT = cE;
-        column = 1;
+        column = herm ? 2 : 1;
         col_cfg = c;
         break;
       }
@@ -1218,6 +1229,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     if (opt->layout == LME_LAYOUT_COLUMN)
       return fail(LME_ENOTSUP, "the column layout does not cover these operators / block size");
     if (opt->block == 768) return fail(LME_EINVAL, "block 768 exists only in the column layout");
+    // the row layout has no Hermitian variant: it computes every element
     rc = pick_rk4_config(h, opt->block, &T, &EPT);
     if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)
       streamed = true;  // an instance is too large for a resident workgroup
@@ -1267,8 +1279,8 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   a.counts = counts_dev;
   a.status = status_dev;
   if (column)
-    e = lme_internal_launch_rk4_colown(col_cfg, wo, nc, nb, re, &a, (int)plan->packs.size(),
-                                       plan->max_lds, s);
+    e = lme_internal_launch_rk4_colown(col_cfg, column == 2, wo, nc, nb, re, &a,
+                                       (int)plan->packs.size(), plan->max_lds, s);
   else
     e = lme_internal_launch_rk4(T, EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch resident RK4");
@@ -1630,6 +1642,11 @@ extern "C" int lme_set_tuning(lme_handle h, const lme_tuning *t) {
     return fail(LME_EINVAL, "apply_cap must be 0 or in [256, 65536]");
   if (t->apply_lds_kb != 0 && (t->apply_lds_kb < 16 || t->apply_lds_kb > 160))
     return fail(LME_EINVAL, "apply_lds_kb must be 0 or in [16, 160]");
+  if (t->herm_layout < LME_LAYOUT_AUTO || t->herm_layout > LME_LAYOUT_COLUMN)
+    return fail(LME_EINVAL, "unknown layout %d", t->herm_layout);
+  if (t->herm_block != 0 && t->herm_block != 256 && t->herm_block != 512 &&
+      t->herm_block != 768 && t->herm_block != 1024)
+    return fail(LME_EINVAL, "herm_block must be 0, 256, 512, 768 or 1024");
   h->tuning = *t;
   h->apply_cap = t->apply_cap ? t->apply_cap : 4096;
   h->tuning.apply_cap = h->apply_cap;
@@ -1668,13 +1685,13 @@ static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_
   auto time_ms = [&](auto &&launch, int reps, float *ms) -> int {
     int r = launch();  // warm-up (plans, uploads)
     if (r) return r;
-    hipEventRecord(ev.a, s);
+    (void)hipEventRecord(ev.a, s);
     for (int i = 0; i < reps && !r; ++i) r = launch();
-    hipEventRecord(ev.b, s);
+    (void)hipEventRecord(ev.b, s);
     hipError_t x = hipEventSynchronize(ev.b);
     if (r) return r;
     if (x != hipSuccess) return hip_fail(x, "hipEventSynchronize");
-    hipEventElapsedTime(ms, ev.a, ev.b);
+    (void)hipEventElapsedTime(ms, ev.a, ev.b);
     *ms /= reps;
     return LME_OK;
   };
@@ -1683,10 +1700,13 @@ static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_
   const int trial = std::min(opt->nsteps, 40);
   const double tl[2] = {0.0, 0.01 * trial};  // cost per step does not depend on h
   const lme_tuning saved = h->tuning;
+  const bool herm = opt->hermitian == 1;
   h->tuning.rk4_block = 0;  // no tuned defaults while trying
+  h->tuning.herm_block = 0;
   struct Cand { int layout, block; };
-  const Cand cands[] = {{LME_LAYOUT_COLUMN, 768}, {LME_LAYOUT_COLUMN, 512},
-                        {LME_LAYOUT_ROW, 256}, {LME_LAYOUT_ROW, 512}, {LME_LAYOUT_ROW, 1024}};
+  const Cand cands[] = {{LME_LAYOUT_COLUMN, 1024}, {LME_LAYOUT_COLUMN, 768},
+                        {LME_LAYOUT_COLUMN, 512}, {LME_LAYOUT_ROW, 256},
+                        {LME_LAYOUT_ROW, 512}, {LME_LAYOUT_ROW, 1024}};
   float best = -1.0f;
   Cand win = {0, 0};
   for (const Cand &c : cands) {
@@ -1711,9 +1731,17 @@ static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_
     h->tuning = saved;
     return fail(LME_ENOTSUP, "no RK4 configuration fits this batch");
   }
-  h->tuning.rk4_layout = win.layout;
-  h->tuning.rk4_block = win.block;
-  h->tuning.rk4_ms_per_step = best / trial;
+  h->tuning.rk4_block = saved.rk4_block;
+  h->tuning.herm_block = saved.herm_block;
+  if (herm) {
+    h->tuning.herm_layout = win.layout;
+    h->tuning.herm_block = win.block;
+    h->tuning.herm_ms_per_step = best / trial;
+  } else {
+    h->tuning.rk4_layout = win.layout;
+    h->tuning.rk4_block = win.block;
+    h->tuning.rk4_ms_per_step = best / trial;
+  }
 
   // application: pack size (row layout) and LDS budget (column layout)
   float best_a = -1.0f;

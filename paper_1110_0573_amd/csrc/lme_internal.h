@@ -113,6 +113,8 @@ constexpr int kColNC = 3;   // collapse operators
 constexpr int kColWB = 2;   // off-diagonal entries per row of a control term
 // (threads per workgroup, rows per thread) of the column-owner kernels
 constexpr int kColCfg[2][2] = {{512, 14}, {768, 9}};
+// Hermitian column-owner configurations (about half the rows per column)
+constexpr int kHermCfg[2][2] = {{768, 7}, {1024, 5}};
 
 // Per-call arguments of the resident RK4 kernel.
 struct Rk4Args {

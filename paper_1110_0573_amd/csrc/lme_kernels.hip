@@ -485,11 +485,20 @@ __device__ __forceinline__ double2 lindblad_col(const OpView &op, const ColData<
   return acc;
 }
 
-template <int T, int EPT, int WO, int NC, int NB, bool RE>
+// HM (Hermitian variant): rho0 = rho0^+ makes every stage input and every
+// L(y) Hermitian, so each unordered pair {i, j} is computed once and its
+// mirror written as the conjugate.  Column j owns the rows i = (j + d) mod n
+// for d = 0 .. floor(n/2): every pair exactly once (for even n the pair at
+// d = n/2 goes to the smaller column index), n/2 + 1 rows per column, so
+// the threads of an instance stay balanced.  The input is read as its
+// Hermitian part; an instance whose rho0 is not Hermitian to 1e-12 relative
+// gets status 9 (LME_ENOTHERM).
+template <int T, int EPT, int WO, int NC, int NB, bool RE, bool HM>
 __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const PackDesc pk = a.packs[blockIdx.x];
   const int n = pk.n, n2 = n * n, C = pk.m * n, G = pk.G, ept = pk.ept;
+  const int R = HM ? n / 2 + 1 : n;  // row slots per column
   const PackLds L = carve(smem, pk);
   const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
   const int tid = threadIdx.x;
@@ -512,20 +521,45 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   ColData<WO, NC, NB> cd;
   load_column<WO, NC, NB>(cd, op, j);
 
-  // Slot r holds row g + r*G; past n the row is clamped to n-1 (computed,
-  // never stored).  Rows are re-derived from an opaque copy of g wherever
-  // they are used, so no per-row address lives across stages in a register.
-  auto row_of = [&](int gg, int r) { return min(gg + r * G, n - 1); };
-  auto owns = [&](int gg, int r) { return active && r < ept && gg + r * G < n; };
+  // Slot r holds row offset d = g + r*G (row d, or row j + d mod n in the
+  // Hermitian variant); past the last offset the slot is clamped to it
+  // (computed, never stored).  Rows are re-derived from an opaque copy of g
+  // wherever they are used, so no per-row address lives across stages in a
+  // register.
+  auto row_of = [&](int gg, int r) {
+    const int d = min(gg + r * G, R - 1);
+    if (!HM) return d;
+    const int i = j + d;
+    return i >= n ? i - n : i;
+  };
+  auto owns = [&](int gg, int r) {
+    const int d = gg + r * G;
+    return active && r < ept && d < R && (!HM || 2 * d != n || 2 * j < n);
+  };
 
   double2 rho[EPT], acc[EPT], yn[EPT];
   uint32_t ridx[EPT];
   const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
+  bool not_herm = false;
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     ridx[r] = row_indices<WO, NC>(op, row_of(g, r));
-    rho[r] = owns(g, r) ? rho0[L.off[b] + row_of(g, r) * n + j] : make_double2(0.0, 0.0);
+    if constexpr (HM) {
+      rho[r] = make_double2(0.0, 0.0);
+      if (owns(g, r)) {
+        const int i = row_of(g, r);
+        const double2 x = rho0[L.off[b] + i * n + j];
+        const double2 y = rho0[L.off[b] + j * n + i];
+        const double dx = x.x - y.x, dy = x.y + y.y;
+        not_herm |= dx * dx + dy * dy >
+                    2e-24 * (x.x * x.x + x.y * x.y + y.x * y.x + y.y * y.y);
+        rho[r] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+      }
+    } else {
+      rho[r] = owns(g, r) ? rho0[L.off[b] + row_of(g, r) * n + j] : make_double2(0.0, 0.0);
+    }
   }
+  if (HM && not_herm && a.status) a.status[L.ids[b]] = 9;  // LME_ENOTHERM
 
   const bool want_expect = a.expect != nullptr && a.n_e > 0;
   int next_out = 0;
@@ -539,10 +573,15 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       for (int r = 0; r < EPT; ++r)
         if (owns(gg, r)) {
           const int i = row_of(gg, r);
-          Yb[mul24(i, n) + j] = rho[r];
-          if (a.states)
+          if (HM) Yb[mul24(j, n) + i] = cconj(rho[r]);  // mirror first: the
+          Yb[mul24(i, n) + j] = rho[r];                  // diagonal keeps rho
+          if (a.states) {
             reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems + L.off[b] +
                                                   i * n + j] = rho[r];
+            if (HM && i != j)
+              reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems +
+                                                    L.off[b] + j * n + i] = cconj(rho[r]);
+          }
         }
       __syncthreads();
       if (want_expect) write_outputs<T>(a, pk, L, next_out);
@@ -570,7 +609,11 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       asm volatile("" : "+v"(gg));
 #pragma unroll
       for (int r = 0; r < EPT; ++r)
-        if (owns(gg, r)) Yb[mul24(row_of(gg, r), n) + j] = yn[r];
+        if (owns(gg, r)) {
+          const int i = row_of(gg, r);
+          if (HM) Yb[mul24(j, n) + i] = cconj(yn[r]);
+          Yb[mul24(i, n) + j] = yn[r];
+        }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
@@ -578,8 +621,11 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
           uint32_t ri = ridx[r];
           int i = row_of(gg, r);
           asm volatile("" : "+v"(i), "+v"(ri));
-          const double2 kv = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, yn[r],
-                                                      L.u + b * pk.nb);
+          double2 kv = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, yn[r],
+                                                L.u + b * pk.nb);
+          // the diagonal of L(y) is real for Hermitian y: drop the rounding
+          // residue of its imaginary part (slot 0 of row group 0 is d = 0)
+          if (HM && r == 0) kv.y = gg == 0 ? 0.0 : kv.y;
           acc[r] = caxpy(wgt, kv, acc[r]);
           yn[r] = caxpy(cnext, kv, rho[r]);
         }
@@ -593,8 +639,12 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   if (a.rho_out) {
 #pragma unroll
     for (int r = 0; r < EPT; ++r)
-      if (owns(g, r))
-        reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + row_of(g, r) * n + j] = rho[r];
+      if (owns(g, r)) {
+        const int i = row_of(g, r);
+        reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + i * n + j] = rho[r];
+        if (HM && i != j)
+          reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + j * n + i] = cconj(rho[r]);
+      }
   }
   if (a.counts)
     for (int bb = tid; bb < pk.m; bb += T) {
@@ -1973,9 +2023,9 @@ extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args
   return hipErrorInvalidValue;
 }
 
-template <int T, int EPT, int WO, int NC, int NB, bool RE>
+template <int T, int EPT, int WO, int NC, int NB, bool RE, bool HM>
 static hipError_t launch_colown_t(const lme::Rk4Args &a, int n_packs, int lds, hipStream_t s) {
-  auto k = lme::rk4_colown_kernel<T, EPT, WO, NC, NB, RE>;
+  auto k = lme::rk4_colown_kernel<T, EPT, WO, NC, NB, RE, HM>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -1983,21 +2033,24 @@ static hipError_t launch_colown_t(const lme::Rk4Args &a, int n_packs, int lds, h
   return hipGetLastError();
 }
 
-// Column-owner kernels: (T, EPT) configuration index cfg into kColCfg, the
-// operator shape (wo, nc, nb) and the real/imaginary specialisation re;
-// returns hipErrorInvalidValue for shapes that have no instantiation.
-extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int wo, int nc, int nb, int re,
-                                                     const lme::Rk4Args *a, int n_packs,
+// Column-owner kernels: (T, EPT) configuration index cfg into kColCfg (or
+// kHermCfg when herm), the operator shape (wo, nc, nb) and the
+// real/imaginary specialisation re; returns hipErrorInvalidValue for shapes
+// that have no instantiation.
+extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int herm, int wo, int nc, int nb,
+                                                     int re, const lme::Rk4Args *a, int n_packs,
                                                      int lds, hipStream_t s) {
-#define LME_COL_CASE(CFG, TT, EE, W, K, B, R)                          \
-  if (cfg == CFG && wo == W && nc == K && nb == B && re == R)          \
-    return launch_colown_t<TT, EE, W, K, B, (R != 0)>(*a, n_packs, lds, s);
-#define LME_COL_SHAPES(CFG, TT, EE, R)                                                        \
-  LME_COL_CASE(CFG, TT, EE, 1, 2, 0, R) LME_COL_CASE(CFG, TT, EE, 1, 3, 0, R)                 \
-  LME_COL_CASE(CFG, TT, EE, 2, 2, 0, R) LME_COL_CASE(CFG, TT, EE, 1, 2, 1, R)                 \
-  LME_COL_CASE(CFG, TT, EE, 1, 3, 1, R)
-  LME_COL_SHAPES(0, 512, 14, 0) LME_COL_SHAPES(0, 512, 14, 1)
-  LME_COL_SHAPES(1, 768, 9, 0) LME_COL_SHAPES(1, 768, 9, 1)
+#define LME_COL_CASE(CFG, HM, TT, EE, W, K, B, R)                                    \
+  if (cfg == CFG && herm == HM && wo == W && nc == K && nb == B && re == R)          \
+    return launch_colown_t<TT, EE, W, K, B, (R != 0), (HM != 0)>(*a, n_packs, lds, s);
+#define LME_COL_SHAPES(CFG, HM, TT, EE, R)                                            \
+  LME_COL_CASE(CFG, HM, TT, EE, 1, 2, 0, R) LME_COL_CASE(CFG, HM, TT, EE, 1, 3, 0, R) \
+  LME_COL_CASE(CFG, HM, TT, EE, 2, 2, 0, R) LME_COL_CASE(CFG, HM, TT, EE, 1, 2, 1, R) \
+  LME_COL_CASE(CFG, HM, TT, EE, 1, 3, 1, R)
+  LME_COL_SHAPES(0, 0, 512, 14, 0) LME_COL_SHAPES(0, 0, 512, 14, 1)
+  LME_COL_SHAPES(1, 0, 768, 9, 0) LME_COL_SHAPES(1, 0, 768, 9, 1)
+  LME_COL_SHAPES(0, 1, 768, 7, 0) LME_COL_SHAPES(0, 1, 768, 7, 1)
+  LME_COL_SHAPES(1, 1, 1024, 5, 0) LME_COL_SHAPES(1, 1, 1024, 5, 1)
 #undef LME_COL_SHAPES
 #undef LME_COL_CASE
   return hipErrorInvalidValue;

@@ -17,10 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "liblme.so")
 
 LME_OK, LME_EINVAL, LME_EGRID, LME_EMAXSTEPS, LME_ESTEPUNDERFLOW, LME_ENONFINITE, \
-    LME_ENOMEM, LME_EHIP, LME_ENOTSUP = range(9)
+    LME_ENOMEM, LME_EHIP, LME_ENOTSUP, LME_ENOTHERM = range(10)
 STATUS_NAMES = {0: "LME_OK", 1: "LME_EINVAL", 2: "LME_EGRID", 3: "LME_EMAXSTEPS",
                 4: "LME_ESTEPUNDERFLOW", 5: "LME_ENONFINITE", 6: "LME_ENOMEM",
-                7: "LME_EHIP", 8: "LME_ENOTSUP"}
+                7: "LME_EHIP", 8: "LME_ENOTSUP", 9: "LME_ENOTHERM"}
 LME_RK4, LME_DOPRI5 = 0, 1
 LME_PATH_AUTO, LME_PATH_RESIDENT, LME_PATH_STREAMED = 0, 1, 2
 LME_FORM_OPERATOR, LME_FORM_SUPEROP, LME_FORM_OPERATOR_STREAMED = 0, 1, 2
@@ -56,7 +56,8 @@ class Segments(C.Structure):
 class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("path", C.c_int32), ("nsteps", C.c_int32),
                 ("block", C.c_int32), ("layout", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
-                ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int64)]
+                ("h0", C.c_double), ("h_min", C.c_double), ("max_steps", C.c_int64),
+                ("hermitian", C.c_int32), ("reserved", C.c_int32)]
 
 
 _LIB = None
@@ -117,7 +118,8 @@ def default_options(**kw):
 class Tuning(C.Structure):
     _fields_ = [("rk4_layout", C.c_int32), ("rk4_block", C.c_int32), ("apply_cap", C.c_int32),
                 ("apply_lds_kb", C.c_int32), ("rk4_ms_per_step", C.c_double),
-                ("apply_us", C.c_double)]
+                ("apply_us", C.c_double), ("herm_layout", C.c_int32), ("herm_block", C.c_int32),
+                ("herm_ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -241,8 +243,10 @@ class Handle:
     # -- entry points ----------------------------------------------------------
     def evolve(self, rho0, tlist, method="rk4", nsteps=0, rtol=1e-6, atol=1e-9, h0=0.0,
                h_min=0.0, max_steps=10**7, path=LME_PATH_AUTO, block=0, layout=0, u=None,
-               want_expect=True, want_states=False, want_rho=True, stream=None):
+               want_expect=True, want_states=False, want_rho=True, hermitian=False,
+               stream=None):
         """Runs lme_evolve.  rho0: complex128 device tensor [state_elems].
+        hermitian: rho0 is Hermitian (options.hermitian).
         Returns a dict of device tensors (expect, states, rho, counts, status)."""
         import torch
         dev = rho0.device
@@ -251,7 +255,8 @@ class Handle:
         opt = default_options(method=LME_RK4 if method == "rk4" else LME_DOPRI5,
                               path=path, nsteps=int(nsteps), block=int(block),
                               layout=int(layout), rtol=rtol,
-                              atol=atol, h0=h0, h_min=h_min, max_steps=int(max_steps))
+                              atol=atol, h0=h0, h_min=h_min, max_steps=int(max_steps),
+                              hermitian=1 if hermitian else 0)
         out = {}
         out["expect"] = (torch.zeros((self.n_inst, self.n_e, n_t), dtype=torch.complex128,
                                      device=dev) if want_expect and self.n_e else None)
@@ -268,10 +273,11 @@ class Handle:
         _check(rc, "lme_evolve")
         return out
 
-    def autotune(self, rho0, nsteps, stream=None):
+    def autotune(self, rho0, nsteps, hermitian=False, stream=None):
         """lme_autotune: picks the fastest schedule for this batch; returns it."""
         t = Tuning()
-        opt = default_options(method=LME_RK4, nsteps=int(nsteps))
+        opt = default_options(method=LME_RK4, nsteps=int(nsteps),
+                              hermitian=1 if hermitian else 0)
         _check(load().lme_autotune(self._h, C.byref(opt), _ptr(rho0), _stream_ptr(stream),
                                    C.byref(t)), "lme_autotune")
         return t.as_dict()

@@ -32,6 +32,10 @@ def test_default_options():
     o = lme.default_options()
     assert o.method == lme.LME_RK4 and o.path == lme.LME_PATH_AUTO
     assert o.rtol == 1e-6 and o.atol == 1e-9 and o.max_steps == 10**7
+    assert o.hermitian == 0
+    # the ctypes mirrors have the C layout (fields appended at the end)
+    assert C.sizeof(lme.Options) == 72 and lme.Options.hermitian.offset == 64
+    assert C.sizeof(lme.Tuning) == 48 and lme.Tuning.herm_ms_per_step.offset == 40
 
 
 def _jc():
@@ -137,6 +141,7 @@ def test_evolve_validation_precedes_device_use():
     assert _evolve_rc(h, [0.0, 1.0], nsteps=10, block=300)[0] == lme.LME_EINVAL
     assert _evolve_rc(h, [0.0, np.nan], nsteps=10)[0] == lme.LME_EINVAL
     assert _evolve_rc(h, [0.0, 1.0], nsteps=10, method=7)[0] == lme.LME_EINVAL
+    assert _evolve_rc(h, [0.0, 1.0], nsteps=10, hermitian=2)[0] == lme.LME_EINVAL
     rc, msg = _evolve_rc(h, [0.0, 1.0], nsteps=10)
     import torch
     if not torch.cuda.is_available():

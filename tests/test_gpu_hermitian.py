@@ -1,0 +1,176 @@
+"""GPU parity of the Hermitian RK4 path (options.hermitian = 1).
+
+The Lindblad generator maps Hermitian matrices to Hermitian matrices and RK4
+combines stages with real coefficients, so a Hermitian rho0 stays Hermitian;
+the Hermitian kernels compute each pair {i, j} once and write the mirror as
+its conjugate.  Bars: as the full path (trace distance 1e-10 to the oracle,
+expectation values 1e-10 absolute), results exactly Hermitian, within 1e-13
+of the full path (the mirrored half is computed with the operands of the
+transposed element, so the two differ by rounding only), and identical bits
+across workgroup sizes, packings and repeats.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1110_0573_amd import systems as S
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1110_0573_amd import lme  # noqa: E402
+
+TD_BAR = 1e-10
+
+
+def run(systems, tlist, nsteps, rhos=None, **kw):
+    h = lme.Handle(systems)
+    rho0 = h.pack(rhos if rhos is not None else [s.rho0 for s in systems])
+    kw.setdefault("hermitian", True)
+    out = h.evolve(rho0, tlist, method="rk4", nsteps=nsteps, **kw)
+    torch.cuda.synchronize()
+    return h, out
+
+
+def assert_exactly_hermitian(mats):
+    for r in mats:
+        assert np.array_equal(r, r.conj().T)
+
+
+def check_against_oracle(systems, tlist, nsteps, h, out, sample=None):
+    ex = out["expect"].cpu().numpy()
+    rho = h.unpack(out["rho"])
+    assert (out["status"].cpu().numpy() == 0).all()
+    for b in (range(len(systems)) if sample is None else sample):
+        s = systems[b]
+        oex, ost = oracle.rk4(s, s.rho0, tlist, nsteps, store_states=True)
+        assert np.max(np.abs(ex[b] - oex)) <= TD_BAR, b
+        assert brute.trace_distance(rho[b], ost[-1]) <= TD_BAR, b
+    assert_exactly_hermitian(rho)
+
+
+def test_herm_sweep_matches_oracle_and_full_path():
+    """64 instances, dims 10..80: several packs per signature, ragged tails."""
+    w = S.jc_sweep(n_inst=64, seed=21, nsteps=200, t_end=5.0, n_out=21, coherent=True)
+    h, out = run(w.systems, w.tlist, w.nsteps, want_states=True)
+    check_against_oracle(w.systems, w.tlist, w.nsteps, h, out, sample=range(0, 64, 5))
+    for k in (0, 7, 20):
+        assert_exactly_hermitian(h.unpack(out["states"][k]))
+    _, full = run(w.systems, w.tlist, w.nsteps, hermitian=False)
+    assert torch.max(torch.abs(out["rho"] - full["rho"])).item() <= 1e-13
+    assert torch.max(torch.abs(out["expect"] - full["expect"])).item() <= 1e-13
+
+
+def test_herm_odd_dimensions_two_offdiagonals():
+    """Kerr oscillators of odd and even cutoff (two off-diagonal entries per
+    row of H, jumps a and a^+) from a coherent state."""
+    systems = []
+    for N, seed in [(5, 1), (7, 2), (8, 3), (13, 4), (21, 5)]:
+        rng = np.random.default_rng(seed)
+        d, E, kap = rng.uniform(0.1, 1.0, 3)
+        K = rng.uniform(0.01, 0.05)  # h K N^2 well inside the RK4 stability region
+        s = S.kerr_system(N, d, K, E, kap)
+        s.rho0 = S.ket2dm(S.coherent_ket(N, 0.8))
+        systems.append(s)
+    tl = np.linspace(0.0, 1.0, 6)
+    h, out = run(systems, tl, 100, layout=lme.LME_LAYOUT_COLUMN)
+    check_against_oracle(systems, tl, 100, h, out)
+
+
+def test_herm_controls_thermal_and_complex_coupling():
+    w = S.jc_drive(n_inst=5, N=6, n_seg=5, t_end=1.0, steps_per_seg=4, sigma_u=0.7)
+    for s in w.systems:
+        s.C.append(S.tidy(np.sqrt(0.02) * S.dag(S.jc_ops(6)[0])))
+    tl = np.linspace(0.0, 1.0, 6)
+    h, out = run(w.systems, tl, w.nsteps, layout=lme.LME_LAYOUT_COLUMN)
+    check_against_oracle(w.systems, tl, w.nsteps, h, out)
+
+    systems = [S.jc_system(N, g=0.3, kappa=0.02, gamma=0.04, phase=0.7 + 0.1 * N, n_th=0.1)
+               for N in (3, 7, 12, 20)]
+    for N, s in zip((3, 7, 12, 20), systems):
+        s.rho0 = S.ket2dm(np.kron(S.coherent_ket(N, 0.7), S.ket(2, 1)))
+    tl = np.linspace(0.0, 2.0, 5)
+    h, out = run(systems, tl, 80, layout=lme.LME_LAYOUT_COLUMN)
+    check_against_oracle(systems, tl, 80, h, out)
+
+
+def test_herm_block_sizes_packing_and_repeat_bitwise():
+    w = S.jc_sweep(n_inst=24, seed=51, nsteps=60, t_end=1.5, n_out=7, coherent=True)
+    _, ref = run(w.systems, w.tlist, w.nsteps, block=768, layout=lme.LME_LAYOUT_COLUMN)
+    ref_ex, ref_rho = ref["expect"].cpu().numpy(), ref["rho"].cpu().numpy()
+    for block in (1024, 0, 768):
+        _, o = run(w.systems, w.tlist, w.nsteps, block=block,
+                   layout=lme.LME_LAYOUT_COLUMN if block else 0)
+        assert np.array_equal(o["expect"].cpu().numpy(), ref_ex), block
+        assert np.array_equal(o["rho"].cpu().numpy(), ref_rho), block
+    h_all = lme.Handle(w.systems)
+    rho_all = h_all.unpack(torch.from_numpy(ref_rho))
+    for b in (0, 9, 23):
+        hs, o = run([w.systems[b]], w.tlist, w.nsteps)
+        assert np.array_equal(o["expect"].cpu().numpy()[0], ref_ex[b])
+        assert np.array_equal(hs.unpack(o["rho"])[0], rho_all[b])
+
+
+def test_herm_flags_non_hermitian_input():
+    w = S.jc_sweep(n_inst=4, seed=71, nsteps=20, t_end=0.5, n_out=3, coherent=True)
+    rhos = [s.rho0.copy() for s in w.systems]
+    rhos[2][1, 0] += 1e-6  # breaks rho = rho^+ far above the 1e-12 tolerance
+    rhos[1][3, 2] *= 1 + 1e-15  # within it
+    _, out = run(w.systems, w.tlist, w.nsteps, rhos=rhos)
+    st = out["status"].cpu().numpy()
+    assert st[2] == lme.LME_ENOTHERM
+    assert st[0] == 0 and st[1] == 0 and st[3] == 0
+
+
+def test_herm_row_layout_ignores_flag():
+    """The row layout has no Hermitian variant: the flag changes nothing."""
+    w = S.jc_sweep(n_inst=6, seed=81, nsteps=30, t_end=0.75, n_out=4)
+    _, a = run(w.systems, w.tlist, w.nsteps, layout=lme.LME_LAYOUT_ROW, block=512)
+    _, b = run(w.systems, w.tlist, w.nsteps, layout=lme.LME_LAYOUT_ROW, block=512,
+               hermitian=False)
+    assert torch.equal(a["rho"], b["rho"]) and torch.equal(a["expect"], b["expect"])
+
+
+def test_herm_autotune_fills_hermitian_fields():
+    w = S.jc_sweep(n_inst=40, seed=91, nsteps=50, t_end=1.25, n_out=6, coherent=True)
+    h = lme.Handle(w.systems)
+    rho0 = h.pack([s.rho0 for s in w.systems])
+    ref = h.evolve(rho0, w.tlist, nsteps=w.nsteps, layout=lme.LME_LAYOUT_COLUMN, block=768,
+                   hermitian=True)
+    before = h.get_tuning()
+    t = h.autotune(rho0, w.nsteps, hermitian=True)
+    assert t["herm_block"] in (256, 512, 768, 1024) and t["herm_ms_per_step"] > 0
+    assert t["rk4_block"] == before.rk4_block
+    out = h.evolve(rho0, w.tlist, nsteps=w.nsteps, hermitian=True)
+    torch.cuda.synchronize()
+    if t["herm_layout"] == lme.LME_LAYOUT_COLUMN:
+        assert torch.equal(out["rho"], ref["rho"]) and torch.equal(out["expect"], ref["expect"])
+    else:
+        assert torch.max(torch.abs(out["rho"] - ref["rho"])).item() <= 1e-13
+
+
+def test_herm_sweep_full_size_sampled():
+    """The full sweep (4096 instances, 1000 steps) with the Hermitian path, in
+    the launch configuration the benchmark times; sampled against the oracle."""
+    w = S.jc_sweep()
+    h, out = run(w.systems, w.tlist, w.nsteps)
+    ex = out["expect"].cpu().numpy()
+    rho = h.unpack(out["rho"])
+    assert (out["status"].cpu().numpy() == 0).all()
+    rng = np.random.default_rng(1)
+    dims = np.array([s.n for s in w.systems])
+    sample = list(rng.choice(4096, 8, replace=False)) + [int(np.argmax(dims)),
+                                                          int(np.argmin(dims))]
+    for b in sample:
+        s = w.systems[b]
+        oex, ost = oracle.rk4(s, s.rho0, w.tlist, w.nsteps, store_states=True)
+        assert np.max(np.abs(ex[b] - oex)) <= TD_BAR
+        assert brute.trace_distance(rho[b], ost[-1]) <= TD_BAR
+    for b in range(0, 4096, 97):
+        r = rho[b]
+        assert abs(np.trace(r) - 1) < 1e-12
+        assert np.array_equal(r, r.conj().T)
