@@ -136,8 +136,7 @@ typedef struct lme_options {
                               every output time must be on this grid          */
   int32_t block;           /* resident path: threads per workgroup; 0 = tuned
                               default.  Row layout: 256, 512 or 1024.
-                              Column layout: 512 or 768 (768 or 1024 with
-                              hermitian = 1)                                  */
+                              Column layout: 512 or 768                       */
   int32_t layout;          /* resident path, thread-to-element layout:
                               LME_LAYOUT_AUTO, LME_LAYOUT_ROW (any operator)
                               or LME_LAYOUT_COLUMN (monomial collapse
@@ -280,7 +279,7 @@ typedef struct lme_tuning {
   double rk4_ms_per_step;   /* lme_autotune: best trial time per RK4 step      */
   double apply_us;          /* lme_autotune: best trial time per application  */
   int32_t herm_layout;
-  int32_t herm_block;       /* column layout: 768 or 1024                      */
+  int32_t herm_block;       /* column layout: 512 or 768                       */
   double herm_ms_per_step;  /* lme_autotune (hermitian = 1): best trial time   */
 } lme_tuning;
 

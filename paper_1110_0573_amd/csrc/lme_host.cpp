@@ -563,7 +563,13 @@ static int ensure_device(lme_ctx *h) {
 // column) and m (instances per pack) with m*n*G <= T and ceil(n/G) <= EPT,
 // maximising the fraction of the workgroup's T*ept element slots in use.
 // Hermitian column layout (column == 2): the same with n/2 + 1 rows per
-// column.
+// column.  Column application (column == 3): as column == 1.
+// LDS operator data per instance: the op blob (row and column RK4 kernels),
+// one record per operator row (column application, Hermitian kernel) or
+// nothing (Hermitian kernel with real structure and no control terms: its
+// row data lives in registers).
+static int real_structure(const lme_ctx *h);
+
 static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, int dp,
                       Plan **out, int lds_budget = 0) {
   for (Plan *p : h->plans)
@@ -600,7 +606,9 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
   for (auto &g : groups) {
     const InstDesc &d0 = h->inst[g.second[0]];
     const lme::Signature &s = adjoint == 1 ? d0.adj : d0.fwd;
-    const int blob = adjoint == 1 ? d0.adj_bytes
+    const int blob = column == 2 && lme::herm_slots(real_structure(h), s.wo, s.nc, s.nb) ? 0
+                     : column >= 2 ? s.n * lme::rec_bytes(s.wo, s.nc, s.nb)
+                     : adjoint == 1 ? d0.adj_bytes
                      : adjoint == 2 ? d0.fwd_bytes + d0.adj_bytes : d0.fwd_bytes;
     const int n = s.n;
     const int64_t n2 = (int64_t)n * n;
@@ -1207,7 +1215,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     tuned.block = tl_block;
   }
   opt = &tuned;
-  // column layout: T in {512, 768} (Hermitian: {768, 1024}); row layout:
+  // column layout: T in {512, 768} (also Hermitian); row layout:
   // T in {256, 512, 1024}
   int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0;
   const int re = real_structure(h);
@@ -1473,7 +1481,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   if (!adjoint && column_eligible(h, &wo, &nc, &nb)) {
     // column-owner application: 1024 threads, up to 64 rows per thread
     Plan *cp;
-    rc = plan_packs(h, 1024, 64, 0, 1024 * 64, 1, 0, &cp, h->apply_lds_kb * 1024);
+    rc = plan_packs(h, 1024, 64, 0, 1024 * 64, 3, 0, &cp, h->apply_lds_kb * 1024);
     if (rc == LME_OK) {
       lme::ApplyArgs a;
       std::memset(&a, 0, sizeof a);

@@ -114,7 +114,26 @@ constexpr int kColWB = 2;   // off-diagonal entries per row of a control term
 // (threads per workgroup, rows per thread) of the column-owner kernels
 constexpr int kColCfg[2][2] = {{512, 14}, {768, 9}};
 // Hermitian column-owner configurations (about half the rows per column)
-constexpr int kHermCfg[2][2] = {{768, 7}, {1024, 5}};
+constexpr int kHermCfg[2][2] = {{512, 8}, {768, 5}};
+
+// The Hermitian RK4 kernel keeps each slot's row data in registers (and no
+// operator data in LDS) for real structure with at most 3 monomial operator
+// columns per row and no control terms; otherwise it reads row records.
+LME_HD constexpr bool herm_slots(bool re, int32_t wo, int32_t nc, int32_t nb) {
+  return re && nb == 0 && wo + nc <= 3;
+}
+
+// Row records of the column-owner kernels (one per operator row, in LDS):
+// 1 + wo + nc + nb*kColWB int32 byte offsets, padded to 16 bytes, then
+// 1 + wo + nc + nb*(1 + kColWB) complex coefficients; the record is an odd
+// number of 16-byte units.
+LME_HD constexpr int32_t rec_hdr_bytes(int32_t wo, int32_t nc, int32_t nb) {
+  return (4 * (1 + wo + nc + nb * kColWB) + 15) & ~15;
+}
+LME_HD constexpr int32_t rec_bytes(int32_t wo, int32_t nc, int32_t nb) {
+  return rec_hdr_bytes(wo, nc, nb) + 16 * (1 + wo + nc + nb * (1 + kColWB)) +
+         ((((rec_hdr_bytes(wo, nc, nb) / 16) + 1 + wo + nc + nb * (1 + kColWB)) & 1) ? 0 : 16);
+}
 
 // Per-call arguments of the resident RK4 kernel.
 struct Rk4Args {

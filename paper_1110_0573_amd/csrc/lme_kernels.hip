@@ -485,20 +485,431 @@ __device__ __forceinline__ double2 lindblad_col(const OpView &op, const ColData<
   return acc;
 }
 
-// HM (Hermitian variant): rho0 = rho0^+ makes every stage input and every
-// L(y) Hermitian, so each unordered pair {i, j} is computed once and its
-// mirror written as the conjugate.  Column j owns the rows i = (j + d) mod n
-// for d = 0 .. floor(n/2): every pair exactly once (for even n the pair at
-// d = n/2 goes to the smaller column index), n/2 + 1 rows per column, so
-// the threads of an instance stay balanced.  The input is read as its
-// Hermitian part; an instance whose rho0 is not Hermitian to 1e-12 relative
-// gets status 9 (LME_ENOTHERM).
-template <int T, int EPT, int WO, int NC, int NB, bool RE, bool HM>
+// ---------------------------------------------------------------------------
+// Row records (column-owner kernels).  One record per row i of an instance,
+// built in LDS from the op blob: the byte offsets, relative to the
+// instance's stage input, of the rows the row-i products read (own row
+// i*n*16, off-diagonal sources Ocol[w][i]*n*16, jump sources
+// Jcol[k][i]*n*16, control sources OBcol[q][w][i]*n*16), then the row's
+// coefficients D_i, Oval[w][i], Jval[k][i], DB[q][i], OBval[q][w][i].  With
+// the column-j positions in registers, each y gather is one add on a record
+// field and each coefficient an immediate offset from the record address.
+// Records are an odd number of 16-byte units, so lanes reading consecutive
+// rows hit distinct LDS banks.
+// ---------------------------------------------------------------------------
+template <int WO, int NC, int NB>
+struct Rec {
+  static constexpr int NH = 1 + WO + NC + NB * kColWB;   // header ints
+  static constexpr int H = rec_hdr_bytes(WO, NC, NB);
+  static constexpr int S = rec_bytes(WO, NC, NB);
+  // coefficient slots (double2) after the header
+  static constexpr int D = 0, O = 1, J = 1 + WO, CB = 1 + WO + NC, CQ = 1 + kColWB;
+};
+
+template <int WO, int NC, int NB>
+__device__ void stage_records(uint8_t *dst, const PackDesc &pk, const int32_t *order,
+                              const InstDesc *inst, const uint8_t *pool, int adjoint) {
+  using RL = Rec<WO, NC, NB>;
+  const int n = pk.n, n16 = 16 * n;
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  for (int idx = threadIdx.x; idx < pk.m * n; idx += blockDim.x) {
+    const int b = idx / n, i = idx - b * n;
+    const InstDesc &d = inst[order[pk.first + b]];
+    const OpView op = make_view(pool + (adjoint ? d.adj_off : d.ops_off), BL);
+    uint8_t *r = dst + (size_t)b * pk.blob_stride + i * RL::S;
+    int32_t *hd = reinterpret_cast<int32_t *>(r);
+    double2 *v = reinterpret_cast<double2 *>(r + RL::H);
+    hd[0] = i * n16;
+    v[RL::D] = op.D[i];
+#pragma unroll
+    for (int w = 0; w < WO; ++w) {
+      hd[1 + w] = op.Ocol[w * n + i] * n16;
+      v[RL::O + w] = op.Oval[w * n + i];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      hd[1 + WO + k] = op.Jcol[k * n + i] * n16;
+      v[RL::J + k] = op.Jval[k * n + i];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      v[RL::CB + q * RL::CQ] = op.DB[q * n + i];
+#pragma unroll
+      for (int w = 0; w < kColWB; ++w) {
+        const bool on = w < op.wb;
+        hd[1 + WO + NC + q * kColWB + w] = (on ? op.OBcol[(q * op.wb + w) * n + i] : i) * n16;
+        v[RL::CB + q * RL::CQ + 1 + w] =
+            on ? op.OBval[(q * op.wb + w) * n + i] : make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int t = RL::NH; t < RL::H / 4; ++t) hd[t] = 0;
+  }
+}
+
+// Column-j data in registers: conjugated coefficients of row j and the LDS
+// byte addresses of the column-j entries the products read (row 0; a record
+// offset selects the row).
+template <int WO, int NC, int NB>
+struct ColPos {
+  double2 dj;
+  double2 oval[WO > 0 ? WO : 1];     // conj(O_jw)
+  double2 jval[NC > 0 ? NC : 1];     // conj(J_kj)
+  double2 dbj[NB > 0 ? NB : 1];
+  double2 obval[NB > 0 ? NB : 1][kColWB];
+  uint32_t ybj;                      // Y_b[0][j]
+  uint32_t yo[WO > 0 ? WO : 1];      // Y_b[0][Ocol[w][j]]
+  uint32_t yj[NC > 0 ? NC : 1];      // Y_b[0][Jcol[k][j]]
+  uint32_t yob[NB > 0 ? NB : 1][kColWB];
+};
+
+template <int WO, int NC, int NB>
+__device__ __forceinline__ void load_column_pos(ColPos<WO, NC, NB> &cd, const OpView &op, int j,
+                                                uint32_t yb) {
+  const int n = op.n;
+  cd.dj = cconj(op.D[j]);
+  cd.ybj = yb + 16 * j;
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    cd.yo[w] = yb + 16 * op.Ocol[w * n + j];
+    cd.oval[w] = cconj(op.Oval[w * n + j]);
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    cd.yj[k] = yb + 16 * op.Jcol[k * n + j];
+    cd.jval[k] = cconj(op.Jval[k * n + j]);
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    cd.dbj[q] = cconj(op.DB[q * n + j]);
+#pragma unroll
+    for (int w = 0; w < kColWB; ++w) {
+      const bool on = w < op.wb;
+      cd.yob[q][w] = yb + 16 * (on ? op.OBcol[(q * op.wb + w) * n + j] : j);
+      cd.obval[q][w] = on ? cconj(op.OBval[(q * op.wb + w) * n + j]) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// (L y)_ij from the row-i record at LDS byte address rec and the column-j
+// registers; the arithmetic of lindblad_col() in the same order.
+template <int WO, int NC, int NB, bool RE>
+__device__ __forceinline__ double2 lindblad_rec(const uint8_t *base, uint32_t rec,
+                                                const ColPos<WO, NC, NB> &cd, double2 yij,
+                                                const double *uq, int wb) {
+  using RL = Rec<WO, NC, NB>;
+  int32_t hd[RL::H / 4];
+#pragma unroll
+  for (int t = 0; t < RL::H / 16; ++t) {
+    const int4 q = *reinterpret_cast<const int4 *>(base + rec + 16 * t);
+    hd[4 * t] = q.x;
+    hd[4 * t + 1] = q.y;
+    hd[4 * t + 2] = q.z;
+    hd[4 * t + 3] = q.w;
+  }
+  const double2 *v = reinterpret_cast<const double2 *>(base + rec + RL::H);
+  auto Y = [&](uint32_t addr) { return *reinterpret_cast<const double2 *>(base + addr); };
+  double2 acc = cmul(cadd(v[RL::D], cd.dj), yij);
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    const double2 yv = Y(cd.ybj + hd[1 + w]);
+    if (RE) {
+      const double o = reinterpret_cast<const double *>(v + RL::O + w)[1];
+      acc = make_double2(fma(-o, yv.y, acc.x), fma(o, yv.x, acc.y));
+    } else {
+      acc = cfma(v[RL::O + w], yv, acc);
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    const double2 yv = Y(cd.yo[w] + hd[0]);
+    if (RE)
+      acc = make_double2(fma(-cd.oval[w].y, yv.y, acc.x), fma(cd.oval[w].y, yv.x, acc.y));
+    else
+      acc = cfma(cd.oval[w], yv, acc);
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const double u = uq[q];
+    if (u != 0.0) {
+      const double2 *cv = v + RL::CB + q * RL::CQ;
+      double2 t = cmul(cadd(cv[0], cd.dbj[q]), yij);
+#pragma unroll
+      for (int w = 0; w < kColWB; ++w)
+        if (w < wb) {
+          const double2 yv = Y(cd.ybj + hd[1 + WO + NC + q * kColWB + w]);
+          if (RE) {
+            const double o = reinterpret_cast<const double *>(cv + 1 + w)[1];
+            t = make_double2(fma(-o, yv.y, t.x), fma(o, yv.x, t.y));
+          } else {
+            t = cfma(cv[1 + w], yv, t);
+          }
+        }
+#pragma unroll
+      for (int w = 0; w < kColWB; ++w)
+        if (w < wb) {
+          const double2 yv = Y(cd.yob[q][w] + hd[0]);
+          if (RE)
+            t = make_double2(fma(-cd.obval[q][w].y, yv.y, t.x), fma(cd.obval[q][w].y, yv.x, t.y));
+          else
+            t = cfma(cd.obval[q][w], yv, t);
+        }
+      acc = caxpy(u, t, acc);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double2 yv = Y(cd.yj[k] + hd[1 + WO + k]);
+    if (RE) {
+      const double p = reinterpret_cast<const double *>(v + RL::J + k)[0] * cd.jval[k].x;
+      acc = make_double2(fma(p, yv.x, acc.x), fma(p, yv.y, acc.y));
+    } else {
+      const double2 p = cmul(v[RL::J + k], cd.jval[k]);
+      acc = cfma(p, yv, acc);
+    }
+  }
+  return acc;
+}
+
+// Per-slot constants of the Hermitian kernel for real structure without
+// control terms: D_i + conj(D_j), Im O_iw, the jump products
+// Re J_ik Re J_jk and the row-i column indices (8 bits each).  They are the
+// only row-i data an element needs, so the element reads nothing from LDS
+// but the y gathers.
+template <int WO, int NC>
+struct SlotC {
+  double2 dsum;
+  double o[WO > 0 ? WO : 1];
+  double p[NC > 0 ? NC : 1];
+  uint32_t ri;
+};
+
+template <int WO, int NC>
+__device__ __forceinline__ void load_slot(SlotC<WO, NC> &s, const OpView &op,
+                                          const ColPos<WO, NC, 0> &cd, int i) {
+  const int n = op.n;
+  s.dsum = cadd(op.D[i], cd.dj);
+#pragma unroll
+  for (int w = 0; w < WO; ++w) s.o[w] = reinterpret_cast<const double *>(op.Oval + w * n + i)[1];
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+    s.p[k] = reinterpret_cast<const double *>(op.Jval + k * n + i)[0] * cd.jval[k].x;
+  s.ri = row_indices<WO, NC>(op, i);
+}
+
+// (L y)_ij from the slot constants; the arithmetic of lindblad_col() (real
+// structure, no control terms) in the same order.  rowoff = i*n*16.
+template <int WO, int NC>
+__device__ __forceinline__ double2 lindblad_slot(const uint8_t *base, const ColPos<WO, NC, 0> &cd,
+                                                 const SlotC<WO, NC> &s, uint32_t rowoff,
+                                                 int n16, double2 yij) {
+  auto Y = [&](uint32_t addr) { return *reinterpret_cast<const double2 *>(base + addr); };
+  double2 acc = cmul(s.dsum, yij);
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    const double2 yv = Y(cd.ybj + mul24(field8(s.ri, w), n16));
+    acc = make_double2(fma(-s.o[w], yv.y, acc.x), fma(s.o[w], yv.x, acc.y));
+  }
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    const double2 yv = Y(cd.yo[w] + rowoff);
+    acc = make_double2(fma(-cd.oval[w].y, yv.y, acc.x), fma(cd.oval[w].y, yv.x, acc.y));
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double2 yv = Y(cd.yj[k] + mul24(field8(s.ri, WO + k), n16));
+    acc = make_double2(fma(s.p[k], yv.x, acc.x), fma(s.p[k], yv.y, acc.y));
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Resident fixed-step RK4 for Hermitian rho0 (density matrices).  rho0 = rho0^+
+// makes every stage input and every L(y) Hermitian, so each unordered pair
+// {i, j} is computed once and its mirror written as the conjugate.  Threads
+// are laid out as in the column-owner kernel (thread t < m*n*G owns column j
+// of instance b), but column j owns the rows i = (j + d) mod n for
+// d = g, g+G, ... <= floor(n/2): every pair exactly once (for even n the pair
+// at d = n/2 goes to the smaller column index), n/2 + 1 rows per column, so
+// the threads of an instance stay balanced.  The row index then differs from
+// lane to lane; for real structure without control terms (the Jaynes-Cummings
+// sweep, one off-diagonal and two jump columns per row) each slot keeps its
+// row data in registers (SlotC) and an element reads nothing from LDS but its
+// y gathers; otherwise the row-i records are read.  The input is read as its Hermitian part; an instance whose rho0 is
+// not Hermitian to 1e-12 relative gets status 9 (LME_ENOTHERM).
+// ---------------------------------------------------------------------------
+template <int T, int EPT, int WO, int NC, int NB, bool RE>
+__global__ __launch_bounds__(T) void rk4_herm_kernel(Rk4Args a) {
+  using RL = Rec<WO, NC, NB>;
+  constexpr bool SLOTS = herm_slots(RE, WO, NC, NB);
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, C = pk.m * n, G = pk.G, ept = pk.ept;
+  const int R = n / 2 + 1;  // row slots per column
+  const PackLds L = carve(smem, pk);
+  const int tid = threadIdx.x;
+
+  for (int bb = tid; bb < pk.m; bb += T) {
+    const int id = a.order[pk.first + bb];
+    L.ids[bb] = id;
+    L.off[bb] = a.inst[id].rho_off;
+    if (a.status) a.status[id] = 0;
+  }
+  if (!SLOTS) stage_records<WO, NC, NB>(L.blobs, pk, a.order, a.inst, a.ops, 0);
+  __syncthreads();
+
+  const bool active = tid < C * G;
+  const int g = active ? tid / C : 0;
+  const int c = active ? tid - g * C : 0;
+  const int b = c / n, j = c - b * n;
+  double2 *Yb = L.Y + b * n2;
+  const uint32_t yb = (uint32_t)(reinterpret_cast<uint8_t *>(Yb) - smem);
+  const uint32_t recb = (uint32_t)(L.blobs + (size_t)b * pk.blob_stride - smem);
+  const uint32_t ybjn = yb + 16 * n * j;  // Y_b[j][0]
+  const OpView gop = make_view(a.ops + a.inst[L.ids[b]].ops_off,
+                               blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc));
+  ColPos<WO, NC, NB> cd;
+  load_column_pos<WO, NC, NB>(cd, gop, j, yb);
+
+  // Slot r: row offset d = min(g + r*G, n/2), row i = j + d mod n (past the
+  // last offset the slot repeats it: computed, never stored).  pos[r] packs
+  // the row's record offset (high half) and 16*i (low half).  The thread
+  // owns its slots r < nown.
+  int nown = 0;
+  if (active) {
+    const int Rown = ((n & 1) == 0 && 2 * j >= n) ? R - 1 : R;
+    nown = g < Rown ? (Rown - g + G - 1) / G : 0;
+  }
+  uint32_t pos[EPT];
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    int i = j + min(g + r * G, R - 1);
+    i = i >= n ? i - n : i;
+    pos[r] = ((uint32_t)(i * RL::S) << 16) | (uint32_t)(16 * i);
+  }
+  auto row_of = [](uint32_t p) { return (int)((p & 0xffffu) >> 4); };
+  SlotC<WO, NC> sc[SLOTS ? EPT : 1];
+  if constexpr (SLOTS) {
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) load_slot<WO, NC>(sc[r], gop, cd, row_of(pos[r]));
+  }
+  // stage input element (i, j) and its mirror into LDS; the mirror goes
+  // first, so on the diagonal the element itself is what remains
+  auto put = [&](uint32_t p, double2 v) {
+    const uint32_t i16 = p & 0xffffu;
+    *reinterpret_cast<double2 *>(smem + ybjn + i16) = cconj(v);
+    *reinterpret_cast<double2 *>(smem + cd.ybj + mul24(i16, n)) = v;
+  };
+  // element (i, j) and its mirror into global memory
+  auto put_global = [&](double2 *dst, uint32_t p, double2 v) {
+    const int i = row_of(p);
+    dst[i * n + j] = v;
+    if (i != j) dst[j * n + i] = cconj(v);
+  };
+
+  double2 rho[EPT], acc[EPT], yn[EPT];
+  const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0) + L.off[b];
+  bool not_herm = false;
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    rho[r] = make_double2(0.0, 0.0);
+    if (r < nown) {
+      const int i = row_of(pos[r]);
+      const double2 x = rho0[i * n + j], y = rho0[j * n + i];
+      const double dx = x.x - y.x, dy = x.y + y.y;
+      not_herm |= dx * dx + dy * dy > 2e-24 * (x.x * x.x + x.y * x.y + y.x * y.x + y.y * y.y);
+      rho[r] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    }
+  }
+  if (not_herm && a.status) a.status[L.ids[b]] = 9;  // LME_ENOTHERM
+
+  const bool want_expect = a.expect != nullptr && a.n_e > 0;
+  int next_out = 0;
+  const double h = a.h;
+  for (int st = 0;; ++st) {
+    while (next_out < a.n_t && a.out_step[next_out] == st) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < EPT; ++r)
+        if (r < nown) {
+          uint32_t p = pos[r];
+          asm volatile("" : "+v"(p));
+          put(p, rho[r]);
+          if (a.states)
+            put_global(reinterpret_cast<double2 *>(a.states) +
+                           (int64_t)next_out * a.state_elems + L.off[b], p, rho[r]);
+        }
+      __syncthreads();
+      if (want_expect) write_outputs<T>(a, pk, L, next_out);
+      ++next_out;
+    }
+    if (st == a.nsteps) break;
+
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) {
+      yn[r] = rho[r];
+      acc[r] = make_double2(0.0, 0.0);
+    }
+    for (int stage = 0; stage < 4; ++stage) {
+      const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
+      const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+      __syncthreads();
+      if (stage == 0 && NB > 0) {
+        const int seg = a.seg_of_step[st];
+        for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+          const int bb = idx / pk.nb, q = idx - bb * pk.nb;
+          L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < EPT; ++r)
+        if (r < nown) {
+          uint32_t p = pos[r];
+          asm volatile("" : "+v"(p));
+          put(p, yn[r]);
+        }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < EPT; ++r) {
+        if (r < ept) {
+          uint32_t p = pos[r];
+          asm volatile("" : "+v"(p));
+          double2 kv;
+          if constexpr (SLOTS)
+            kv = lindblad_slot<WO, NC>(smem, cd, sc[r], mul24(p & 0xffffu, n), 16 * n, yn[r]);
+          else
+            kv = lindblad_rec<WO, NC, NB, RE>(smem, recb + (p >> 16), cd, yn[r],
+                                              L.u + b * pk.nb, pk.wb);
+          // the diagonal of L(y) is real for Hermitian y: drop the rounding
+          // residue of its imaginary part (slot 0 of row group 0 is d = 0)
+          if (r == 0) kv.y = g == 0 ? 0.0 : kv.y;
+          acc[r] = caxpy(wgt, kv, acc[r]);
+          yn[r] = caxpy(cnext, kv, rho[r]);
+        }
+        if (r & 1) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < EPT; ++r) rho[r] = caxpy(h / 6.0, acc[r], rho[r]);
+  }
+
+  if (a.rho_out) {
+#pragma unroll
+    for (int r = 0; r < EPT; ++r)
+      if (r < nown) put_global(reinterpret_cast<double2 *>(a.rho_out) + L.off[b], pos[r], rho[r]);
+  }
+  if (a.counts)
+    for (int bb = tid; bb < pk.m; bb += T) {
+      a.counts[2 * (int64_t)L.ids[bb]] = a.nsteps;
+      a.counts[2 * (int64_t)L.ids[bb] + 1] = 0;
+    }
+}
+
+template <int T, int EPT, int WO, int NC, int NB, bool RE>
 __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const PackDesc pk = a.packs[blockIdx.x];
   const int n = pk.n, n2 = n * n, C = pk.m * n, G = pk.G, ept = pk.ept;
-  const int R = HM ? n / 2 + 1 : n;  // row slots per column
   const PackLds L = carve(smem, pk);
   const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
   const int tid = threadIdx.x;
@@ -521,45 +932,20 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   ColData<WO, NC, NB> cd;
   load_column<WO, NC, NB>(cd, op, j);
 
-  // Slot r holds row offset d = g + r*G (row d, or row j + d mod n in the
-  // Hermitian variant); past the last offset the slot is clamped to it
-  // (computed, never stored).  Rows are re-derived from an opaque copy of g
-  // wherever they are used, so no per-row address lives across stages in a
-  // register.
-  auto row_of = [&](int gg, int r) {
-    const int d = min(gg + r * G, R - 1);
-    if (!HM) return d;
-    const int i = j + d;
-    return i >= n ? i - n : i;
-  };
-  auto owns = [&](int gg, int r) {
-    const int d = gg + r * G;
-    return active && r < ept && d < R && (!HM || 2 * d != n || 2 * j < n);
-  };
+  // Slot r holds row g + r*G; past n the row is clamped to n-1 (computed,
+  // never stored).  Rows are re-derived from an opaque copy of g wherever
+  // they are used, so no per-row address lives across stages in a register.
+  auto row_of = [&](int gg, int r) { return min(gg + r * G, n - 1); };
+  auto owns = [&](int gg, int r) { return active && r < ept && gg + r * G < n; };
 
   double2 rho[EPT], acc[EPT], yn[EPT];
   uint32_t ridx[EPT];
   const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
-  bool not_herm = false;
 #pragma unroll
   for (int r = 0; r < EPT; ++r) {
     ridx[r] = row_indices<WO, NC>(op, row_of(g, r));
-    if constexpr (HM) {
-      rho[r] = make_double2(0.0, 0.0);
-      if (owns(g, r)) {
-        const int i = row_of(g, r);
-        const double2 x = rho0[L.off[b] + i * n + j];
-        const double2 y = rho0[L.off[b] + j * n + i];
-        const double dx = x.x - y.x, dy = x.y + y.y;
-        not_herm |= dx * dx + dy * dy >
-                    2e-24 * (x.x * x.x + x.y * x.y + y.x * y.x + y.y * y.y);
-        rho[r] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
-      }
-    } else {
-      rho[r] = owns(g, r) ? rho0[L.off[b] + row_of(g, r) * n + j] : make_double2(0.0, 0.0);
-    }
+    rho[r] = owns(g, r) ? rho0[L.off[b] + row_of(g, r) * n + j] : make_double2(0.0, 0.0);
   }
-  if (HM && not_herm && a.status) a.status[L.ids[b]] = 9;  // LME_ENOTHERM
 
   const bool want_expect = a.expect != nullptr && a.n_e > 0;
   int next_out = 0;
@@ -573,15 +959,10 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       for (int r = 0; r < EPT; ++r)
         if (owns(gg, r)) {
           const int i = row_of(gg, r);
-          if (HM) Yb[mul24(j, n) + i] = cconj(rho[r]);  // mirror first: the
-          Yb[mul24(i, n) + j] = rho[r];                  // diagonal keeps rho
-          if (a.states) {
+          Yb[mul24(i, n) + j] = rho[r];
+          if (a.states)
             reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems + L.off[b] +
                                                   i * n + j] = rho[r];
-            if (HM && i != j)
-              reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems +
-                                                    L.off[b] + j * n + i] = cconj(rho[r]);
-          }
         }
       __syncthreads();
       if (want_expect) write_outputs<T>(a, pk, L, next_out);
@@ -609,11 +990,7 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       asm volatile("" : "+v"(gg));
 #pragma unroll
       for (int r = 0; r < EPT; ++r)
-        if (owns(gg, r)) {
-          const int i = row_of(gg, r);
-          if (HM) Yb[mul24(j, n) + i] = cconj(yn[r]);
-          Yb[mul24(i, n) + j] = yn[r];
-        }
+        if (owns(gg, r)) Yb[mul24(row_of(gg, r), n) + j] = yn[r];
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
@@ -621,11 +998,8 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
           uint32_t ri = ridx[r];
           int i = row_of(gg, r);
           asm volatile("" : "+v"(i), "+v"(ri));
-          double2 kv = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, yn[r],
-                                                L.u + b * pk.nb);
-          // the diagonal of L(y) is real for Hermitian y: drop the rounding
-          // residue of its imaginary part (slot 0 of row group 0 is d = 0)
-          if (HM && r == 0) kv.y = gg == 0 ? 0.0 : kv.y;
+          const double2 kv = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, yn[r],
+                                                      L.u + b * pk.nb);
           acc[r] = caxpy(wgt, kv, acc[r]);
           yn[r] = caxpy(cnext, kv, rho[r]);
         }
@@ -639,12 +1013,8 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   if (a.rho_out) {
 #pragma unroll
     for (int r = 0; r < EPT; ++r)
-      if (owns(g, r)) {
-        const int i = row_of(g, r);
-        reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + i * n + j] = rho[r];
-        if (HM && i != j)
-          reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + j * n + i] = cconj(rho[r]);
-      }
+      if (owns(g, r))
+        reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + row_of(g, r) * n + j] = rho[r];
   }
   if (a.counts)
     for (int bb = tid; bb < pk.m; bb += T) {
@@ -1421,17 +1791,17 @@ __global__ __launch_bounds__(T) void apply_shape_kernel(ApplyArgs a) {
 // ---------------------------------------------------------------------------
 template <int T, int WO, int NC, int NB, bool RE>
 __global__ __launch_bounds__(T) void apply_col_kernel(ApplyArgs a) {
+  using RL = Rec<WO, NC, NB>;
   extern __shared__ __align__(16) uint8_t smem[];
   const PackDesc pk = a.packs[blockIdx.x];
   const int n = pk.n, n2 = n * n, C = pk.m * n, G = pk.G;
   const PackLds L = carve(smem, pk);
-  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
   const int tid = threadIdx.x;
   for (int b = tid; b < pk.m; b += T) {
     L.ids[b] = a.order[pk.first + b];
     L.off[b] = a.inst[L.ids[b]].rho_off;
   }
-  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
+  stage_records<WO, NC, NB>(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
   __syncthreads();
   for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
     const int b = idx / pk.nb, q = idx - b * pk.nb;
@@ -1448,14 +1818,18 @@ __global__ __launch_bounds__(T) void apply_col_kernel(ApplyArgs a) {
     for (int i = g; i < n; i += G) Yb[i * n + j] = y[i * n + j];
   __syncthreads();
   if (!active) return;
-  const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
-  ColData<WO, NC, NB> cd;
-  load_column<WO, NC, NB>(cd, op, j);
-  for (int i = g; i < n; i += G) {
-    const uint32_t ri = row_indices<WO, NC>(op, i);
-    out[i * n + j] = lindblad_col<WO, NC, NB, RE>(op, cd, Yb, i, ri, j, Yb[i * n + j],
-                                                  L.u + b * pk.nb);
+  const uint32_t yb = (uint32_t)(reinterpret_cast<uint8_t *>(Yb) - smem);
+  const uint32_t recb = (uint32_t)(L.blobs + (size_t)b * pk.blob_stride - smem);
+  ColPos<WO, NC, NB> cd;
+  {
+    const InstDesc &d = a.inst[L.ids[b]];
+    const OpView gop = make_view(a.ops + (a.adjoint ? d.adj_off : d.ops_off),
+                                 blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc));
+    load_column_pos<WO, NC, NB>(cd, gop, j, yb);
   }
+  for (int i = g; i < n; i += G)
+    out[i * n + j] = lindblad_rec<WO, NC, NB, RE>(smem, recb + i * RL::S, cd, Yb[i * n + j],
+                                                  L.u + b * pk.nb, pk.wb);
 }
 
 // ---------------------------------------------------------------------------
@@ -2025,7 +2399,10 @@ extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args
 
 template <int T, int EPT, int WO, int NC, int NB, bool RE, bool HM>
 static hipError_t launch_colown_t(const lme::Rk4Args &a, int n_packs, int lds, hipStream_t s) {
-  auto k = lme::rk4_colown_kernel<T, EPT, WO, NC, NB, RE, HM>;
+  auto k = [] {
+    if constexpr (HM) return lme::rk4_herm_kernel<T, EPT, WO, NC, NB, RE>;
+    else return lme::rk4_colown_kernel<T, EPT, WO, NC, NB, RE>;
+  }();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -2049,8 +2426,8 @@ extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int herm, int wo, 
   LME_COL_CASE(CFG, HM, TT, EE, 1, 3, 1, R)
   LME_COL_SHAPES(0, 0, 512, 14, 0) LME_COL_SHAPES(0, 0, 512, 14, 1)
   LME_COL_SHAPES(1, 0, 768, 9, 0) LME_COL_SHAPES(1, 0, 768, 9, 1)
-  LME_COL_SHAPES(0, 1, 768, 7, 0) LME_COL_SHAPES(0, 1, 768, 7, 1)
-  LME_COL_SHAPES(1, 1, 1024, 5, 0) LME_COL_SHAPES(1, 1, 1024, 5, 1)
+  LME_COL_SHAPES(0, 1, 512, 8, 0) LME_COL_SHAPES(0, 1, 512, 8, 1)
+  LME_COL_SHAPES(1, 1, 768, 5, 0) LME_COL_SHAPES(1, 1, 768, 5, 1)
 #undef LME_COL_SHAPES
 #undef LME_COL_CASE
   return hipErrorInvalidValue;

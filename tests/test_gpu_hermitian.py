@@ -102,7 +102,7 @@ def test_herm_block_sizes_packing_and_repeat_bitwise():
     w = S.jc_sweep(n_inst=24, seed=51, nsteps=60, t_end=1.5, n_out=7, coherent=True)
     _, ref = run(w.systems, w.tlist, w.nsteps, block=768, layout=lme.LME_LAYOUT_COLUMN)
     ref_ex, ref_rho = ref["expect"].cpu().numpy(), ref["rho"].cpu().numpy()
-    for block in (1024, 0, 768):
+    for block in (512, 0, 768):
         _, o = run(w.systems, w.tlist, w.nsteps, block=block,
                    layout=lme.LME_LAYOUT_COLUMN if block else 0)
         assert np.array_equal(o["expect"].cpu().numpy(), ref_ex), block
