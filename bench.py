@@ -88,7 +88,8 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
     nbytes = 32.0 * h.state_elems
     stream = torch.cuda.current_stream()
     res = {"workload": "jc_sweep batch, 4096 instances (161 MB per state copy)",
-           "algorithmic_bytes": nbytes, "apply_lds_kb": tuned["apply_lds_kb"]}
+           "algorithmic_bytes": nbytes, "apply_lds_kb": tuned["apply_lds_kb"],
+           "apply_block": tuned["apply_block"]}
     for name, form in (("operator_lds", lme.LME_FORM_OPERATOR),
                        ("operator_global", lme.LME_FORM_OPERATOR_STREAMED),
                        ("superop", lme.LME_FORM_SUPEROP)):
@@ -106,6 +107,19 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
         us = a.elapsed_time(b) * 1e3 / reps
         gbs = nbytes / (us * 1e-6) / 1e9
         res[name] = {"us_per_apply": us, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    # device copy of the same bytes (one state read, one written) for reference
+    src = torch.empty_like(y)
+    for _ in range(2):
+        out.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        out.copy_(src)
+    b.record(stream)
+    torch.cuda.synchronize()
+    cus = a.elapsed_time(b) * 1e3 / reps
+    res["device_copy"] = {"us": cus, "GBs": nbytes / (cus * 1e-6) / 1e9}
+    res["operator_lds"]["frac_of_copy"] = res["device_copy"]["us"] / res["operator_lds"]["us_per_apply"]
     return res
 
 
@@ -166,7 +180,7 @@ def pmc_pass(lme, systems, torch):
     h = lme.Handle(w.systems)
     rho0 = h.pack([s.rho0 for s in w.systems], device="cuda:0")
     h.set_tuning(rk4_layout=lme.LME_LAYOUT_COLUMN, rk4_block=768, apply_cap=8192,
-                 herm_layout=lme.LME_LAYOUT_COLUMN, herm_block=1024)
+                 herm_layout=lme.LME_LAYOUT_COLUMN, herm_block=768)
     h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps)
     h.evolve(rho0, w.tlist, method="rk4", nsteps=w.nsteps, hermitian=True)
     out = torch.empty_like(rho0)

@@ -268,7 +268,12 @@ int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, d
  *   herm_layout, herm_block: the same for runs with options.hermitian = 1;
  *   apply_cap: elements per workgroup of the LDS-staged application
  *              (lme_apply, LME_FORM_OPERATOR, general operators), 256 .. 65536;
- *   apply_lds_kb: see the field; 0 or 16 .. 160. */
+ *   apply_lds_kb: see the field; 0 or 16 .. 160;
+ *   apply_block: threads per workgroup of the column-layout application
+ *                (256, 512 or 1024; 0 = 1024);
+ *   apply_path: column-layout application as pipelined tiles (0: one
+ *               persistent workgroup per CU streaming row tiles through two
+ *               LDS stages) or as packs of whole instances (1). */
 typedef struct lme_tuning {
   int32_t rk4_layout;
   int32_t rk4_block;
@@ -281,6 +286,8 @@ typedef struct lme_tuning {
   int32_t herm_layout;
   int32_t herm_block;       /* column layout: 512 or 768                       */
   double herm_ms_per_step;  /* lme_autotune (hermitian = 1): best trial time   */
+  int32_t apply_block;
+  int32_t apply_path;
 } lme_tuning;
 
 int lme_get_tuning(lme_handle h, lme_tuning *t);

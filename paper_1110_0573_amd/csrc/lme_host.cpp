@@ -50,7 +50,10 @@ extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a,
 extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
                                               hipStream_t s);
-extern "C" hipError_t lme_internal_launch_apply_col(int wo, int nc, int nb, int re,
+extern "C" hipError_t lme_internal_launch_apply_pipe(int wo, int nc, int nb, int re,
+                                                     const lme::PipeArgs *a, int grid,
+                                                     hipStream_t s);
+extern "C" hipError_t lme_internal_launch_apply_col(int T, int wo, int nc, int nb, int re,
                                                     const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, int re,
@@ -244,6 +247,12 @@ struct lme_ctx {
   DevBuf d_sd, d_scol, d_sval;
   int apply_cap = 4096;   // elements per pack of the LDS-staged application
   int apply_lds_kb = 0;   // LDS budget per column-application workgroup (0: device)
+  int apply_block = 1024; // threads per column-application workgroup
+  int apply_path = 0;     // column application: 0 pipelined tiles, 1 packs
+  // pipelined application: row records in HBM and the tile list
+  int pipe_state = 0;     // 0 not built, 1 ready, -1 not applicable
+  int32_t n_pipe = 0, pipe_grid = 0;
+  DevBuf d_recs, d_pt;
   // streamed steppers: workspace, per-instance tile ranges, capture stream and
   // the instantiated one-step graph (re-captured when the arguments change)
   DevBuf d_sws, d_tile_rng;
@@ -1446,6 +1455,175 @@ static int ensure_superop(lme_ctx *h) {
   return LME_OK;
 }
 
+// Pipelined column application: row records of every instance (the layout
+// of the device's Rec<wo, nc, nb>) in HBM, and the tile list.  Instances
+// whose y and records fit a stage go whole, several of one signature per
+// tile; larger ones are cut into row tiles, each staged with the band of
+// rows its products read.  LME_ENOTSUP when an operator is too wide for a
+// row tile to fit a stage.
+static int ensure_pipe(lme_ctx *h, int wo, int nc, int nb) {
+  if (h->pipe_state == 1) return LME_OK;
+  if (h->pipe_state == -1) return LME_ENOTSUP;
+  h->pipe_state = -1;
+  const int S = lme::rec_bytes(wo, nc, nb), H = lme::rec_hdr_bytes(wo, nc, nb);
+  const int NH = 1 + wo + nc + nb * lme::kColWB;
+  const int CB = 1 + wo + nc, CQ = 1 + lme::kColWB;
+  // records
+  std::vector<int64_t> roff(h->n_inst);
+  int64_t total = 0;
+  for (int b = 0; b < h->n_inst; ++b) {
+    roff[b] = total;
+    total += (int64_t)h->inst[b].n * S;
+  }
+  std::vector<uint8_t> recs((size_t)total, 0);
+  std::vector<std::vector<int32_t>> lo(h->n_inst), hi(h->n_inst);
+  for (int b = 0; b < h->n_inst; ++b) {
+    const InstDesc &d = h->inst[b];
+    const lme::Signature &g = d.fwd;
+    const int n = g.n, n16 = 16 * n;
+    const lme::BlobLayout L = lme::blob_layout(n, g.wo, g.nb, g.wb, g.nc, g.wc);
+    const uint8_t *blob = h->ops.data() + d.ops_off;
+    auto val = [&](int off, int idx) {
+      double v[2];
+      std::memcpy(v, blob + off + 16 * idx, 16);
+      return std::pair<double, double>(v[0], v[1]);
+    };
+    auto col = [&](int off, int idx) {
+      int32_t c;
+      std::memcpy(&c, blob + off + 4 * idx, 4);
+      return c;
+    };
+    lo[b].resize(n);
+    hi[b].resize(n);
+    for (int i = 0; i < n; ++i) {
+      uint8_t *r = recs.data() + roff[b] + (size_t)i * S;
+      int32_t hd[32] = {0};
+      std::vector<std::pair<double, double>> v((size_t)(S - H) / 16, {0.0, 0.0});
+      int l = i, u = i;
+      auto ref = [&](int c) { l = std::min(l, c); u = std::max(u, c); return c * n16; };
+      hd[0] = i * n16;
+      v[0] = val(L.offD, i);
+      for (int w = 0; w < wo; ++w) {
+        hd[1 + w] = ref(col(L.offOcol, w * n + i));
+        v[1 + w] = val(L.offOval, w * n + i);
+      }
+      for (int k = 0; k < nc; ++k) {
+        hd[1 + wo + k] = ref(col(L.offJcol, k * n + i));
+        v[1 + wo + k] = val(L.offJval, k * n + i);
+      }
+      for (int q = 0; q < nb; ++q) {
+        v[CB + q * CQ] = val(L.offDB, q * n + i);
+        for (int w = 0; w < lme::kColWB; ++w) {
+          const bool on = w < g.wb;
+          hd[1 + wo + nc + q * lme::kColWB + w] =
+              ref(on ? col(L.offOBcol, (q * g.wb + w) * n + i) : i);
+          if (on) v[CB + q * CQ + 1 + w] = val(L.offOBval, (q * g.wb + w) * n + i);
+        }
+      }
+      std::memcpy(r, hd, 4 * NH);
+      for (size_t k = 0; k < v.size(); ++k) {
+        std::memcpy(r + H + 16 * k, &v[k].first, 8);
+        std::memcpy(r + H + 16 * k + 8, &v[k].second, 8);
+      }
+      lo[b][i] = l;
+      hi[b][i] = u;
+    }
+  }
+  // tiles
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int32_t>> groups;
+  for (int b = 0; b < h->n_inst; ++b) {
+    const lme::Signature &g = h->inst[b].fwd;
+    groups[std::make_tuple(g.n, g.wo, g.wb, g.nc, g.wc, g.nb)].push_back(b);
+  }
+  std::vector<lme::PTile> tiles;
+  const int T = lme::kPipeT, stage = lme::kPipeStage;
+  auto add = [&](lme::PTile &t, int k, int b) {
+    t.yoff[k] = h->inst[b].rho_off;
+    t.roff[k] = roff[b];
+    t.id[k] = b;
+  };
+  for (auto &gr : groups) {
+    const std::vector<int32_t> &ids = gr.second;
+    const int n = std::get<0>(gr.first), wb = std::get<2>(gr.first);
+    const int yb = 16 * n * n, rb = n * S;
+    if (yb + rb <= stage && n <= T) {
+      const int m_max = std::min({stage / (yb + rb), T / n, (int)ids.size(), lme::kPipeMaxM});
+      const int cnt = (int)ids.size(), n_t = (cnt + m_max - 1) / m_max;
+      int done = 0;
+      for (int q = 0; q < n_t; ++q) {
+        const int m = (cnt - done + (n_t - q) - 1) / (n_t - q);
+        lme::PTile t;
+        std::memset(&t, 0, sizeof t);
+        t.m = m;
+        t.n = n;
+        t.G = std::min(T / (m * n), n);
+        t.r0 = 0;
+        t.r1 = n;
+        t.h0 = 0;
+        t.span = n;
+        t.wb = wb;
+        t.rec_lds = m * yb;
+        for (int k = 0; k < m; ++k) add(t, k, ids[done + k]);
+        tiles.push_back(t);
+        done += m;
+      }
+    } else {
+      const int max_span = (stage - rb) / (16 * n);
+      if (rb > stage / 2 || max_span < 1 || n > T) return LME_ENOTSUP;
+      for (int b : ids) {
+        int r0 = 0;
+        while (r0 < n) {
+          int l = lo[b][r0], u = hi[b][r0];
+          if (u - l + 1 > max_span) return LME_ENOTSUP;  // one row's band is too wide
+          int r1 = r0 + 1;
+          while (r1 < n) {
+            const int l2 = std::min(l, lo[b][r1]), u2 = std::max(u, hi[b][r1]);
+            if (u2 - l2 + 1 > max_span) break;
+            l = l2;
+            u = u2;
+            ++r1;
+          }
+          lme::PTile t;
+          std::memset(&t, 0, sizeof t);
+          t.m = 1;
+          t.n = n;
+          t.G = std::min(T / n, r1 - r0);
+          t.r0 = r0;
+          t.r1 = r1;
+          t.h0 = l;
+          t.span = u - l + 1;
+          t.wb = wb;
+          t.rec_lds = t.span * 16 * n;
+          add(t, 0, b);
+          tiles.push_back(t);
+          r0 = r1;
+        }
+      }
+    }
+  }
+  // largest tiles first, so that the workgroups' round-robin shares even out
+  std::vector<int> ord(tiles.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+  auto cost = [&](const lme::PTile &t) { return (int64_t)t.m * t.span * t.n; };
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int x, int y) { return cost(tiles[x]) > cost(tiles[y]); });
+  std::vector<lme::PTile> sorted;
+  for (int k : ord) sorted.push_back(tiles[k]);
+  int rc;
+  if ((rc = h->d_recs.upload(recs.data(), recs.size(), "row records"))) return rc;
+  if ((rc = h->d_pt.upload(sorted.data(), sorted.size() * sizeof(lme::PTile), "tiles"))) return rc;
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CUs)");
+  h->n_pipe = (int32_t)sorted.size();
+  // one workgroup per CU; more when a workgroup would hold more descriptors
+  // than its LDS table
+  h->pipe_grid = std::min(h->n_pipe, std::max(cus, (h->n_pipe + lme::kPipeMaxTiles - 1) /
+                                                       lme::kPipeMaxTiles));
+  h->pipe_state = 1;
+  return LME_OK;
+}
+
 static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, const double *u_dev,
                       const void *y_dev, void *out_dev, void *stream) {
   if (!h) return fail(LME_EINVAL, "handle is NULL");
@@ -1478,10 +1656,32 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   if (form == LME_FORM_OPERATOR_STREAMED)
     return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
   int wo, nc, nb;
+  if (!adjoint && column_eligible(h, &wo, &nc, &nb) && h->apply_path == 0 &&
+      2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile) <= h->lds_limit) {
+    rc = ensure_pipe(h, wo, nc, nb);
+    if (rc != LME_OK && rc != LME_ENOTSUP) return rc;
+    if (rc == LME_OK) {
+      lme::PipeArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.tiles = static_cast<const lme::PTile *>(h->d_pt.p);
+      a.n_tiles = h->n_pipe;
+      a.recs = static_cast<const uint8_t *>(h->d_recs.p);
+      a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+      a.n_ctrl = h->n_ctrl;
+      a.n_seg = h->n_seg;
+      a.seg = segment_at(h, t);
+      a.y = static_cast<const double *>(y_dev);
+      a.out = static_cast<double *>(out_dev);
+      hipError_t e = lme_internal_launch_apply_pipe(wo, nc, nb, real_structure(h), &a,
+                                                    h->pipe_grid, s);
+      return e == hipSuccess ? LME_OK : hip_fail(e, "launch pipelined application");
+    }
+  }
   if (!adjoint && column_eligible(h, &wo, &nc, &nb)) {
-    // column-owner application: 1024 threads, up to 64 rows per thread
+    // column-owner application: apply_block threads, up to 64 rows per thread
     Plan *cp;
-    rc = plan_packs(h, 1024, 64, 0, 1024 * 64, 3, 0, &cp, h->apply_lds_kb * 1024);
+    const int T = h->apply_block;
+    rc = plan_packs(h, T, 64, 0, T * 64, 3, 0, &cp, h->apply_lds_kb * 1024);
     if (rc == LME_OK) {
       lme::ApplyArgs a;
       std::memset(&a, 0, sizeof a);
@@ -1495,7 +1695,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
       a.seg = segment_at(h, t);
       a.y = static_cast<const double *>(y_dev);
       a.out = static_cast<double *>(out_dev);
-      hipError_t e = lme_internal_launch_apply_col(wo, nc, nb, real_structure(h), &a,
+      hipError_t e = lme_internal_launch_apply_col(T, wo, nc, nb, real_structure(h), &a,
                                                    (int)cp->packs.size(), cp->max_lds, s);
       return e == hipSuccess ? LME_OK : hip_fail(e, "launch column application");
     }
@@ -1636,6 +1836,8 @@ extern "C" int lme_get_tuning(lme_handle h, lme_tuning *t) {
   *t = h->tuning;
   t->apply_cap = h->apply_cap;
   t->apply_lds_kb = h->apply_lds_kb;
+  t->apply_block = h->apply_block;
+  t->apply_path = h->apply_path;
   return LME_OK;
 }
 
@@ -1650,6 +1852,11 @@ extern "C" int lme_set_tuning(lme_handle h, const lme_tuning *t) {
     return fail(LME_EINVAL, "apply_cap must be 0 or in [256, 65536]");
   if (t->apply_lds_kb != 0 && (t->apply_lds_kb < 16 || t->apply_lds_kb > 160))
     return fail(LME_EINVAL, "apply_lds_kb must be 0 or in [16, 160]");
+  if (t->apply_block != 0 && t->apply_block != 256 && t->apply_block != 512 &&
+      t->apply_block != 1024)
+    return fail(LME_EINVAL, "apply_block must be 0, 256, 512 or 1024");
+  if (t->apply_path != 0 && t->apply_path != 1)
+    return fail(LME_EINVAL, "apply_path must be 0 or 1");
   if (t->herm_layout < LME_LAYOUT_AUTO || t->herm_layout > LME_LAYOUT_COLUMN)
     return fail(LME_EINVAL, "unknown layout %d", t->herm_layout);
   if (t->herm_block != 0 && t->herm_block != 256 && t->herm_block != 512 &&
@@ -1659,6 +1866,9 @@ extern "C" int lme_set_tuning(lme_handle h, const lme_tuning *t) {
   h->apply_cap = t->apply_cap ? t->apply_cap : 4096;
   h->tuning.apply_cap = h->apply_cap;
   h->apply_lds_kb = t->apply_lds_kb;
+  h->apply_block = t->apply_block ? t->apply_block : 1024;
+  h->tuning.apply_block = h->apply_block;
+  h->apply_path = t->apply_path;
   return LME_OK;
 }
 
@@ -1751,28 +1961,45 @@ static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_
     h->tuning.rk4_ms_per_step = best / trial;
   }
 
-  // application: pack size (row layout) and LDS budget (column layout)
+  // application: workgroup size and LDS budget (column layout; smaller
+  // budgets put more workgroups on a CU, whose loads then overlap the others'
+  // arithmetic) or pack size (row layout)
+  struct ACand { int path, block, kb, cap; };
+  std::vector<ACand> acs;
+  int wo, nc, nb;
+  if (column_eligible(h, &wo, &nc, &nb)) {
+    acs.push_back({0, h->apply_block, h->apply_lds_kb, h->apply_cap});
+    for (int block : {1024, 512})
+      for (int kb : {0, 80, 40}) acs.push_back({1, block, kb, h->apply_cap});
+  } else {
+    for (int cap : {512, 2048, 8192})
+      acs.push_back({h->apply_path, h->apply_block, h->apply_lds_kb, cap});
+  }
   float best_a = -1.0f;
-  int best_cap = h->apply_cap, best_kb = h->apply_lds_kb;
-  for (int kb : {0, 80, 53, 40})
-    for (int cap : {512, 2048, 8192}) {
-      h->apply_cap = cap;
-      h->apply_lds_kb = kb;
-      float us = 0.0f;
-      rc = time_ms([&]() { return apply_impl(h, LME_FORM_OPERATOR, 0, 0.0, nullptr, rho0_dev,
-                                             out.p, stream); }, 5, &us);
-      if (rc == LME_ENOTSUP) continue;
-      if (rc) return rc;
-      if (best_a < 0.0f || us < best_a) {
-        best_a = us;
-        best_cap = cap;
-        best_kb = kb;
-      }
+  ACand best_c = {h->apply_path, h->apply_block, h->apply_lds_kb, h->apply_cap};
+  for (const ACand &c : acs) {
+    h->apply_path = c.path;
+    h->apply_block = c.block;
+    h->apply_lds_kb = c.kb;
+    h->apply_cap = c.cap;
+    float us = 0.0f;
+    rc = time_ms([&]() { return apply_impl(h, LME_FORM_OPERATOR, 0, 0.0, nullptr, rho0_dev,
+                                           out.p, stream); }, 5, &us);
+    if (rc == LME_ENOTSUP) continue;
+    if (rc) return rc;
+    if (best_a < 0.0f || us < best_a) {
+      best_a = us;
+      best_c = c;
     }
-  h->apply_cap = best_cap;
-  h->apply_lds_kb = best_kb;
-  h->tuning.apply_cap = best_cap;
-  h->tuning.apply_lds_kb = best_kb;
+  }
+  h->apply_path = best_c.path;
+  h->apply_block = best_c.block;
+  h->apply_lds_kb = best_c.kb;
+  h->apply_cap = best_c.cap;
+  h->tuning.apply_path = best_c.path;
+  h->tuning.apply_block = best_c.block;
+  h->tuning.apply_cap = best_c.cap;
+  h->tuning.apply_lds_kb = best_c.kb;
   h->tuning.apply_us = best_a * 1e3;
   if (result) *result = h->tuning;
   return LME_OK;

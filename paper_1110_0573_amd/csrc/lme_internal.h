@@ -299,4 +299,37 @@ struct ApplyArgs {
   double *out;
 };
 
+// Pipelined column application.  A tile is either m whole instances of one
+// signature (r0 = h0 = 0, r1 = span = n) or rows [r0, r1) of one instance
+// together with the rows [h0, h0 + span) its products read (a band around
+// them).  Each buffer of the workgroup's two LDS stages holds the tile's y
+// rows and the row records of all its instances' rows.
+constexpr int kPipeT = 1024;          // threads per workgroup
+constexpr int kPipeStage = 71680;     // bytes per LDS stage (y + records)
+constexpr int kPipeUnits = (kPipeStage / 16 + kPipeT - 1) / kPipeT;  // 16-B loads per thread
+constexpr int kPipeMaxM = 8;          // instances per tile
+constexpr int kPipeMaxTiles = 64;     // tiles per workgroup (descriptors kept in LDS)
+
+struct PTile {
+  int32_t m, n, G;  // instances, dimension, row groups
+  int32_t r0, r1;   // rows computed
+  int32_t h0, span; // rows staged: [h0, h0 + span) of each instance
+  int32_t wb;       // control-term width of the signature
+  int32_t rec_lds;  // byte offset of the records in the stage buffer
+  int32_t pad[3];
+  int64_t yoff[kPipeMaxM];  // state offset of each instance (elements)
+  int64_t roff[kPipeMaxM];  // record offset of each instance (bytes)
+  int32_t id[kPipeMaxM];    // instance index
+};
+
+struct PipeArgs {
+  const PTile *tiles;
+  int32_t n_tiles;
+  const uint8_t *recs;   // row records of every instance (HBM)
+  const double *u;
+  int32_t n_ctrl, n_seg, seg;
+  const double *y;
+  double *out;
+};
+
 }  // namespace lme

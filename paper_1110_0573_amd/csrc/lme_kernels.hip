@@ -1814,8 +1814,18 @@ __global__ __launch_bounds__(T) void apply_col_kernel(ApplyArgs a) {
   double2 *Yb = L.Y + b * n2;
   const double2 *y = reinterpret_cast<const double2 *>(a.y) + L.off[b];
   double2 *out = reinterpret_cast<double2 *>(a.out) + L.off[b];
-  if (active)
-    for (int i = g; i < n; i += G) Yb[i * n + j] = y[i * n + j];
+  if (active) {
+    // eight loads in flight per lane before the LDS writes
+    int i = g;
+    for (; i + 7 * G < n; i += 8 * G) {
+      double2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = y[(i + u * G) * n + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Yb[(i + u * G) * n + j] = t[u];
+    }
+    for (; i < n; i += G) Yb[i * n + j] = y[i * n + j];
+  }
   __syncthreads();
   if (!active) return;
   const uint32_t yb = (uint32_t)(reinterpret_cast<uint8_t *>(Yb) - smem);
@@ -1830,6 +1840,159 @@ __global__ __launch_bounds__(T) void apply_col_kernel(ApplyArgs a) {
   for (int i = g; i < n; i += G)
     out[i * n + j] = lindblad_rec<WO, NC, NB, RE>(smem, recb + i * RL::S, cd, Yb[i * n + j],
                                                   L.u + b * pk.nb, pk.wb);
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined column application (persistent).  One workgroup per CU walks
+// its tiles (blockIdx.x, + gridDim.x, ...) with two LDS stages: while it
+// computes tile t from one stage, each thread already holds in registers its
+// share of tile t + gridDim.x (y rows and row records, 16-byte loads), which
+// it writes into the other stage once its elements of t are done; one
+// barrier per tile.  HBM reads of the next tile thus overlap the arithmetic
+// and the stores of the current one.  Column data come from the staged row
+// records (the record of row j of A holds the column-j entries of A^+ and of
+// the jumps), so a tile needs nothing else from memory.
+// ---------------------------------------------------------------------------
+template <int WO, int NC, int NB>
+__device__ __forceinline__ void load_column_staged(ColPos<WO, NC, NB> &cd, const uint8_t *base,
+                                                   uint32_t rec, int n, uint32_t yb, int j) {
+  using RL = Rec<WO, NC, NB>;
+  int32_t hd[RL::H / 4];
+#pragma unroll
+  for (int t = 0; t < RL::H / 16; ++t) {
+    const int4 q = *reinterpret_cast<const int4 *>(base + rec + 16 * t);
+    hd[4 * t] = q.x;
+    hd[4 * t + 1] = q.y;
+    hd[4 * t + 2] = q.z;
+    hd[4 * t + 3] = q.w;
+  }
+  const double2 *v = reinterpret_cast<const double2 *>(base + rec + RL::H);
+  // header offsets are row offsets c*n*16; the column offset is c*16
+  cd.dj = cconj(v[RL::D]);
+  cd.ybj = yb + 16 * j;
+#pragma unroll
+  for (int w = 0; w < WO; ++w) {
+    cd.yo[w] = yb + (uint32_t)hd[1 + w] / (uint32_t)n;
+    cd.oval[w] = cconj(v[RL::O + w]);
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    cd.yj[k] = yb + (uint32_t)hd[1 + WO + k] / (uint32_t)n;
+    cd.jval[k] = cconj(v[RL::J + k]);
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    cd.dbj[q] = cconj(v[RL::CB + q * RL::CQ]);
+#pragma unroll
+    for (int w = 0; w < kColWB; ++w) {
+      cd.yob[q][w] = yb + (uint32_t)hd[1 + WO + NC + q * kColWB + w] / (uint32_t)n;
+      cd.obval[q][w] = cconj(v[RL::CB + q * RL::CQ + 1 + w]);
+    }
+  }
+}
+
+template <int WO, int NC, int NB, bool RE>
+__global__ __launch_bounds__(kPipeT) void apply_pipe_kernel(PipeArgs a) {
+  using RL = Rec<WO, NC, NB>;
+  constexpr int T = kPipeT, U = kPipeUnits;
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  extern __shared__ __align__(16) uint8_t smem[];
+  PTile *desc = reinterpret_cast<PTile *>(smem + 2 * kPipeStage);
+  const int tid = threadIdx.x;
+  const int nt = a.n_tiles > (int)blockIdx.x
+                     ? (a.n_tiles - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x
+                     : 0;
+  if (nt == 0) return;
+  // this workgroup's tile descriptors (tiles blockIdx.x + k*gridDim.x) into LDS
+  {
+    constexpr int W = sizeof(PTile) / 4;
+    for (int idx = tid; idx < nt * W; idx += T) {
+      const int k = idx / W, w = idx - k * W;
+      reinterpret_cast<int32_t *>(desc + k)[w] = reinterpret_cast<const int32_t *>(
+          a.tiles + blockIdx.x + (int64_t)k * gridDim.x)[w];
+    }
+  }
+
+  // this thread's 16-byte units of a tile: y units first, then records
+  const v4u *__restrict__ yv = reinterpret_cast<const v4u *>(a.y);
+  const uint8_t *__restrict__ recs = a.recs;
+  v4u pf[U];
+  auto fetch = [&](const PTile *tl) {
+    const int n = tl->n, m = tl->m, h0 = tl->h0;
+    const int per = tl->span * n, Ey = m * per;
+    const int ru = n * RL::S / 16, Er = m * ru;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = tid + q * T;
+      const bool isy = e < Ey;
+      const int r = isy ? e : e - Ey, d = isy ? per : ru;
+      const int k = min(r / d, m - 1), rem = r - k * d;
+      // past the tile's units the load repeats the tile's first unit
+      const bool live = e < Ey + Er;
+      const v4u *src = isy    ? yv + tl->yoff[k] + (int64_t)h0 * n + rem
+                       : live ? reinterpret_cast<const v4u *>(recs + tl->roff[k]) + rem
+                              : yv + tl->yoff[0] + (int64_t)h0 * n;
+      pf[q] = __builtin_nontemporal_load(src);
+    }
+  };
+  auto place = [&](const PTile *tl, uint8_t *stage) {
+    const int Ey = tl->m * tl->span * tl->n, Er = tl->m * tl->n * RL::S / 16;
+    const int rec_lds = tl->rec_lds;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int e = tid + q * T;
+      if (e < Ey)
+        reinterpret_cast<v4u *>(stage)[e] = pf[q];
+      else if (e - Ey < Er)
+        reinterpret_cast<v4u *>(stage + rec_lds)[e - Ey] = pf[q];
+    }
+  };
+  // per-thread global data of a tile (read before the next tile's loads are
+  // issued, so that the arithmetic never waits on those)
+  struct Prep {
+    double2 *out;
+    double uq[NB > 0 ? NB : 1];
+  };
+  auto prep = [&](const PTile *tl) {
+    Prep p;
+    const int C = tl->m * tl->n;
+    const int b = tid < C * tl->G ? (tid % C) / tl->n : 0;
+    p.out = reinterpret_cast<double2 *>(a.out) + tl->yoff[b];
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      p.uq[q] = a.seg >= 0 ? a.u[((int64_t)tl->id[b] * a.n_ctrl + q) * a.n_seg + a.seg] : 0.0;
+    return p;
+  };
+  auto compute = [&](const PTile *tl, const uint8_t *stage, const Prep &p) {
+    const int n = tl->n, C = tl->m * n, G = tl->G, r0 = tl->r0, r1 = tl->r1, wb = tl->wb;
+    if (tid >= C * G) return;
+    const int g = tid / C, c = tid - g * C, b = c / n, j = c - b * n;
+    // LDS address of row 0 of instance b (the stage holds rows h0 ..)
+    const uint32_t yb = (uint32_t)(stage - smem) + 16u * (uint32_t)(b * tl->span * n) -
+                        16u * (uint32_t)(tl->h0 * n);
+    const uint32_t rb = (uint32_t)(stage - smem) + tl->rec_lds + b * n * RL::S;
+    ColPos<WO, NC, NB> cd;
+    load_column_staged<WO, NC, NB>(cd, smem, rb + j * RL::S, n, yb, j);
+    for (int i = r0 + g; i < r1; i += G) {
+      const double2 yij = *reinterpret_cast<const double2 *>(smem + yb + 16 * (i * n + j));
+      p.out[i * n + j] = lindblad_rec<WO, NC, NB, RE>(smem, rb + i * RL::S, cd, yij, p.uq, wb);
+    }
+  };
+
+  __syncthreads();
+  fetch(desc);
+  place(desc, smem);
+  int s = 0;
+  for (int k = 0;; ++k) {
+    __syncthreads();  // stage s holds tile k; every thread is done with stage s^1
+    const Prep p = prep(desc + k);
+    const bool more = k + 1 < nt;
+    if (more) fetch(desc + k + 1);
+    compute(desc + k, smem + s * kPipeStage, p);
+    if (!more) break;
+    place(desc + k + 1, smem + (s ^ 1) * kPipeStage);
+    s ^= 1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2515,27 +2678,56 @@ static hipError_t launch_apply_shape_t(const lme::ApplyArgs &a, int n_packs, int
   return hipGetLastError();
 }
 
-template <int WO, int NC, int NB, bool RE>
+template <int T, int WO, int NC, int NB, bool RE>
 static hipError_t launch_apply_col_t(const lme::ApplyArgs &a, int n_packs, int lds,
                                      hipStream_t s) {
-  auto k = lme::apply_col_kernel<1024, WO, NC, NB, RE>;
+  auto k = lme::apply_col_kernel<T, WO, NC, NB, RE>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(n_packs), dim3(1024), lds, s, a);
+  hipLaunchKernelGGL(k, dim3(n_packs), dim3(T), lds, s, a);
   return hipGetLastError();
 }
 
-// Column-owner application, 1024 threads (the column-kernel shapes).
-extern "C" hipError_t lme_internal_launch_apply_col(int wo, int nc, int nb, int re,
+// Column-owner application, T in {256, 512, 1024} threads (the column-kernel
+// shapes).
+extern "C" hipError_t lme_internal_launch_apply_col(int T, int wo, int nc, int nb, int re,
                                                     const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s) {
-#define LME_AC(W, K, B, R) \
-  if (wo == W && nc == K && nb == B && re == R) \
-    return launch_apply_col_t<W, K, B, (R != 0)>(*a, n_packs, lds, s);
-  LME_AC(1, 2, 0, 0) LME_AC(1, 3, 0, 0) LME_AC(2, 2, 0, 0) LME_AC(1, 2, 1, 0) LME_AC(1, 3, 1, 0)
-  LME_AC(1, 2, 0, 1) LME_AC(1, 3, 0, 1) LME_AC(2, 2, 0, 1) LME_AC(1, 2, 1, 1) LME_AC(1, 3, 1, 1)
+#define LME_AC(TT, W, K, B, R) \
+  if (T == TT && wo == W && nc == K && nb == B && re == R) \
+    return launch_apply_col_t<TT, W, K, B, (R != 0)>(*a, n_packs, lds, s);
+#define LME_AC_T(TT)                                                                     \
+  LME_AC(TT, 1, 2, 0, 0) LME_AC(TT, 1, 3, 0, 0) LME_AC(TT, 2, 2, 0, 0)                   \
+  LME_AC(TT, 1, 2, 1, 0) LME_AC(TT, 1, 3, 1, 0) LME_AC(TT, 1, 2, 0, 1)                   \
+  LME_AC(TT, 1, 3, 0, 1) LME_AC(TT, 2, 2, 0, 1) LME_AC(TT, 1, 2, 1, 1) LME_AC(TT, 1, 3, 1, 1)
+  LME_AC_T(256) LME_AC_T(512) LME_AC_T(1024)
+#undef LME_AC_T
 #undef LME_AC
+  return hipErrorInvalidValue;
+}
+
+template <int WO, int NC, int NB, bool RE>
+static hipError_t launch_apply_pipe_t(const lme::PipeArgs &a, int grid, hipStream_t s) {
+  auto k = lme::apply_pipe_kernel<WO, NC, NB, RE>;
+  const int lds = 2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(lme::kPipeT), lds, s, a);
+  return hipGetLastError();
+}
+
+// Pipelined column application (the column-kernel shapes).
+extern "C" hipError_t lme_internal_launch_apply_pipe(int wo, int nc, int nb, int re,
+                                                     const lme::PipeArgs *a, int grid,
+                                                     hipStream_t s) {
+#define LME_AP(W, K, B, R) \
+  if (wo == W && nc == K && nb == B && re == R) \
+    return launch_apply_pipe_t<W, K, B, (R != 0)>(*a, grid, s);
+  LME_AP(1, 2, 0, 0) LME_AP(1, 3, 0, 0) LME_AP(2, 2, 0, 0) LME_AP(1, 2, 1, 0) LME_AP(1, 3, 1, 0)
+  LME_AP(1, 2, 0, 1) LME_AP(1, 3, 0, 1) LME_AP(2, 2, 0, 1) LME_AP(1, 2, 1, 1) LME_AP(1, 3, 1, 1)
+#undef LME_AP
   return hipErrorInvalidValue;
 }
 

@@ -35,7 +35,7 @@ def test_default_options():
     assert o.hermitian == 0
     # the ctypes mirrors have the C layout (fields appended at the end)
     assert C.sizeof(lme.Options) == 72 and lme.Options.hermitian.offset == 64
-    assert C.sizeof(lme.Tuning) == 48 and lme.Tuning.herm_ms_per_step.offset == 40
+    assert C.sizeof(lme.Tuning) == 56 and lme.Tuning.apply_block.offset == 48
 
 
 def _jc():
