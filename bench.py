@@ -324,7 +324,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": None,
-                     "kernel": "rk4_colown_kernel" + (" (Hermitian)" if herm else ""),
+                     "kernel": "rk4_herm_kernel" if herm else "rk4_colown_kernel",
                      "kernel_ms": k_ms, "algorithmic_flops": flops},
         "hbm": {"algorithmic_bytes": hbm_bytes, "GBs": hbm_bytes / (k_ms * 1e-3) / 1e9,
                 "note": "state stays on chip for all steps; HBM moves rho0, rho, outputs"},

@@ -1547,7 +1547,10 @@ static int ensure_pipe(lme_ctx *h, int wo, int nc, int nb) {
     const int n = std::get<0>(gr.first), wb = std::get<2>(gr.first);
     const int yb = 16 * n * n, rb = n * S;
     if (yb + rb <= stage && n <= T) {
-      const int m_max = std::min({stage / (yb + rb), T / n, (int)ids.size(), lme::kPipeMaxM});
+      // at most kPipeEPT rows per thread: m n ceil(n / kPipeEPT) <= T
+      const int m_max = std::min({stage / (yb + rb), T / (n * ((n + lme::kPipeEPT - 1) /
+                                                                lme::kPipeEPT)),
+                                  (int)ids.size(), lme::kPipeMaxM});
       const int cnt = (int)ids.size(), n_t = (cnt + m_max - 1) / m_max;
       int done = 0;
       for (int q = 0; q < n_t; ++q) {
@@ -1569,6 +1572,7 @@ static int ensure_pipe(lme_ctx *h, int wo, int nc, int nb) {
       }
     } else {
       const int max_span = (stage - rb) / (16 * n);
+      const int max_rows = lme::kPipeEPT * (T / n);  // at most kPipeEPT rows per thread
       if (rb > stage / 2 || max_span < 1 || n > T) return LME_ENOTSUP;
       for (int b : ids) {
         int r0 = 0;
@@ -1576,7 +1580,7 @@ static int ensure_pipe(lme_ctx *h, int wo, int nc, int nb) {
           int l = lo[b][r0], u = hi[b][r0];
           if (u - l + 1 > max_span) return LME_ENOTSUP;  // one row's band is too wide
           int r1 = r0 + 1;
-          while (r1 < n) {
+          while (r1 < n && r1 - r0 < max_rows) {
             const int l2 = std::min(l, lo[b][r1]), u2 = std::max(u, hi[b][r1]);
             if (u2 - l2 + 1 > max_span) break;
             l = l2;
@@ -1657,7 +1661,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
     return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
   int wo, nc, nb;
   if (!adjoint && column_eligible(h, &wo, &nc, &nb) && h->apply_path == 0 &&
-      2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile) <= h->lds_limit) {
+      2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile) + 16 <= h->lds_limit) {
     rc = ensure_pipe(h, wo, nc, nb);
     if (rc != LME_OK && rc != LME_ENOTSUP) return rc;
     if (rc == LME_OK) {

@@ -309,6 +309,7 @@ constexpr int kPipeStage = 71680;     // bytes per LDS stage (y + records)
 constexpr int kPipeUnits = (kPipeStage / 16 + kPipeT - 1) / kPipeT;  // 16-B loads per thread
 constexpr int kPipeMaxM = 8;          // instances per tile
 constexpr int kPipeMaxTiles = 64;     // tiles per workgroup (descriptors kept in LDS)
+constexpr int kPipeEPT = 8;           // rows per thread of a tile
 
 struct PTile {
   int32_t m, n, G;  // instances, dimension, row groups

@@ -1845,11 +1845,11 @@ __global__ __launch_bounds__(T) void apply_col_kernel(ApplyArgs a) {
 // ---------------------------------------------------------------------------
 // Pipelined column application (persistent).  One workgroup per CU walks
 // its tiles (blockIdx.x, + gridDim.x, ...) with two LDS stages: while it
-// computes tile t from one stage, each thread already holds in registers its
-// share of tile t + gridDim.x (y rows and row records, 16-byte loads), which
-// it writes into the other stage once its elements of t are done; one
-// barrier per tile.  HBM reads of the next tile thus overlap the arithmetic
-// and the stores of the current one.  Column data come from the staged row
+// computes and stores tile t from one stage, the loads of its share of the
+// next tile (y rows and row records, 16-byte loads into registers) are in
+// flight; once its elements of t are done each thread writes that share into
+// the other stage; one barrier per tile.  HBM reads of the next tile thus
+// overlap the arithmetic and the stores of the current one.  Column data come from the staged row
 // records (the record of row j of A holds the column-j entries of A^+ and of
 // the jumps), so a tile needs nothing else from memory.
 // ---------------------------------------------------------------------------
@@ -1927,7 +1927,8 @@ __global__ __launch_bounds__(kPipeT) void apply_pipe_kernel(PipeArgs a) {
       const bool isy = e < Ey;
       const int r = isy ? e : e - Ey, d = isy ? per : ru;
       const int k = min(r / d, m - 1), rem = r - k * d;
-      // past the tile's units the load repeats the tile's first unit
+      // streaming (non-temporal) loads; past the tile's units the load
+      // repeats the tile's first unit
       const bool live = e < Ey + Er;
       const v4u *src = isy    ? yv + tl->yoff[k] + (int64_t)h0 * n + rem
                        : live ? reinterpret_cast<const v4u *>(recs + tl->roff[k]) + rem
@@ -1935,16 +1936,18 @@ __global__ __launch_bounds__(kPipeT) void apply_pipe_kernel(PipeArgs a) {
       pf[q] = __builtin_nontemporal_load(src);
     }
   };
+  // every unit is written (units past the tile go to a spare 16 bytes past
+  // the descriptor table), so no load is left pending on any path
+  uint8_t *spare = smem + 2 * kPipeStage + kPipeMaxTiles * (int)sizeof(PTile);
   auto place = [&](const PTile *tl, uint8_t *stage) {
     const int Ey = tl->m * tl->span * tl->n, Er = tl->m * tl->n * RL::S / 16;
     const int rec_lds = tl->rec_lds;
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int e = tid + q * T;
-      if (e < Ey)
-        reinterpret_cast<v4u *>(stage)[e] = pf[q];
-      else if (e - Ey < Er)
-        reinterpret_cast<v4u *>(stage + rec_lds)[e - Ey] = pf[q];
+      uint8_t *dst = e < Ey ? stage + 16 * e
+                     : e - Ey < Er ? stage + rec_lds + 16 * (e - Ey) : spare;
+      *reinterpret_cast<v4u *>(dst) = pf[q];
     }
   };
   // per-thread global data of a tile (read before the next tile's loads are
@@ -1986,10 +1989,12 @@ __global__ __launch_bounds__(kPipeT) void apply_pipe_kernel(PipeArgs a) {
   for (int k = 0;; ++k) {
     __syncthreads();  // stage s holds tile k; every thread is done with stage s^1
     const Prep p = prep(desc + k);
-    const bool more = k + 1 < nt;
-    if (more) fetch(desc + k + 1);
+    if (k + 1 >= nt) {
+      compute(desc + k, smem + s * kPipeStage, p);
+      break;
+    }
+    fetch(desc + k + 1);
     compute(desc + k, smem + s * kPipeStage, p);
-    if (!more) break;
     place(desc + k + 1, smem + (s ^ 1) * kPipeStage);
     s ^= 1;
   }
@@ -2710,7 +2715,7 @@ extern "C" hipError_t lme_internal_launch_apply_col(int T, int wo, int nc, int n
 template <int WO, int NC, int NB, bool RE>
 static hipError_t launch_apply_pipe_t(const lme::PipeArgs &a, int grid, hipStream_t s) {
   auto k = lme::apply_pipe_kernel<WO, NC, NB, RE>;
-  const int lds = 2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile);
+  const int lds = 2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile) + 16;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
