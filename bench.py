@@ -26,6 +26,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "instance-RK-steps/sec + HBM GB/s, batched vs plain, at 1e-10 trace distance"
+# HBM bytes per launch of the timed kernels from the FETCH_SIZE / WRITE_SIZE passes
+# (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0), valid only for the kernel
+# source with this SHA-256; any other source reports null.
+TRAFFIC = {"sha256": "c89d20d2006c948c3bde024035eadf66dd010d8704272a12b545f5f0ffa4c5be",
+           "rk4_herm_kernel": 192.3e6 + 178.1e6, "rk4_colown_kernel": 216.5e6 + 232.6e6,
+           "apply_pipe_kernel": 184.5e6 + 158.4e6}
+
+
+def kernel_traffic(name):
+    """Counter-measured bytes per launch of `name`, or None if the kernels changed."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1110_0573_amd", "csrc", "lme_kernels.hip"), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    return TRAFFIC.get(name) if digest == TRAFFIC["sha256"] else None
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMD x 16 lanes x 2 flop/FMA x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
@@ -107,6 +121,9 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
         us = a.elapsed_time(b) * 1e3 / reps
         gbs = nbytes / (us * 1e-6) / 1e9
         res[name] = {"us_per_apply": us, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    res["operator_lds"]["kernel"] = "apply_pipe_kernel" if tuned["apply_path"] == 0 else \
+        "apply_col_kernel"
+    res["operator_lds"]["traffic"] = kernel_traffic(res["operator_lds"]["kernel"])
     # device copy of the same bytes (one state read, one written) for reference
     src = torch.empty_like(y)
     for _ in range(2):
@@ -323,7 +340,7 @@ def main():
                    "tuning": tuning},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": kernel_traffic("rk4_herm_kernel" if herm else "rk4_colown_kernel"),
                      "kernel": "rk4_herm_kernel" if herm else "rk4_colown_kernel",
                      "kernel_ms": k_ms, "algorithmic_flops": flops},
         "hbm": {"algorithmic_bytes": hbm_bytes, "GBs": hbm_bytes / (k_ms * 1e-3) / 1e9,
