@@ -101,7 +101,8 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
     out = torch.empty_like(y)
     nbytes = 32.0 * h.state_elems
     stream = torch.cuda.current_stream()
-    res = {"workload": "jc_sweep batch, 4096 instances (161 MB per state copy)",
+    res = {"workload": f"jc_sweep batch, 4096 instances ({16 * h.state_elems / 1e6:.1f} MB per "
+                       f"state copy)",
            "algorithmic_bytes": nbytes, "apply_lds_kb": tuned["apply_lds_kb"],
            "apply_block": tuned["apply_block"]}
     for name, form in (("operator_lds", lme.LME_FORM_OPERATOR),
