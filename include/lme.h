@@ -142,7 +142,11 @@ typedef struct lme_options {
                               or LME_LAYOUT_COLUMN (monomial collapse
                               operators, at most 2 off-diagonal entries per
                               row of H, at most 3 collapse operators and 1
-                              control term); both give identical results     */
+                              control term); both give identical results.
+                              DOPRI5 has both layouts at 512 threads (column:
+                              at most 16 rows per thread); AUTO takes the
+                              column layout there when 8 rows per thread
+                              suffice                                        */
   double rtol, atol;       /* DOPRI5: per-element tolerance
                               atol + rtol*max(|rho|, |rho_new|)               */
   double h0;               /* DOPRI5: first step; <= 0 selects it

@@ -44,6 +44,9 @@ extern "C" int lme_internal_dp5_epts(int *ept, int cap);
 extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradArgs *a,
                                                int n_packs, int lds, hipStream_t s);
 extern "C" int lme_internal_dp5_extra_lds(int m);
+extern "C" hipError_t lme_internal_launch_dp5_col(int EPT, int wo, int nc, int nb, int re,
+                                                  const lme::Dp5Args *a, int n_packs, int lds,
+                                                  hipStream_t s);
 extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,
                                               int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a, hipStream_t s);
@@ -1092,8 +1095,6 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   if (!std::isfinite(opt->h0) || !(opt->h_min >= 0.0) || !std::isfinite(opt->h_min))
     return fail(LME_EINVAL, "DOPRI5 needs a finite h0 and h_min >= 0");
   if (opt->max_steps < 1) return fail(LME_EINVAL, "DOPRI5 needs max_steps >= 1");
-  if (opt->layout == LME_LAYOUT_COLUMN)
-    return fail(LME_ENOTSUP, "the column layout has no adaptive stepper");
   if (opt->block != 0 && opt->block != 512)
     return fail(LME_EINVAL, "the adaptive stepper runs 512-thread workgroups");
   std::vector<double> stops;
@@ -1111,6 +1112,19 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
     return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the resident adaptive "
                 "workgroup", max_n2);
   bool streamed = opt->path == LME_PATH_STREAMED || !EPT;
+  // column-owner resident kernel: the column-kernel shapes, up to 16 rows per
+  // thread
+  int wo = 0, nc = 0, nb = 0, col_ept = 0;
+  if (opt->layout != LME_LAYOUT_ROW && opt->path != LME_PATH_STREAMED &&
+      column_eligible(h, &wo, &nc, &nb))
+    for (int e : {8, 16})
+      if (!col_ept && column_fits(h, 512, e, false)) col_ept = e;
+  if (opt->layout == LME_LAYOUT_COLUMN && !col_ept)
+    return fail(LME_ENOTSUP, "the batch has no column-owner adaptive kernel (operator shape, "
+                "dimension or path)");
+  // AUTO: the column kernel with 8 rows per thread (the 16-row variant keeps
+  // fewer operands in registers and is not faster than the row kernel)
+  if (opt->layout == LME_LAYOUT_AUTO && col_ept != 8) col_ept = 0;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((rc = ensure_device(h))) return rc;
@@ -1128,7 +1142,10 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
     h->stops_key.swap(key);
   }
   Plan *plan = nullptr;
-  if (!streamed) {
+  if (col_ept) {
+    streamed = false;
+    if ((rc = plan_packs(h, 512, col_ept, 0, 512 * col_ept, 1, 1, &plan))) return rc;
+  } else if (!streamed) {
     rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan);
     if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)
       streamed = true;  // a pack does not fit in LDS
@@ -1183,7 +1200,10 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   if (streamed)
     return evolve_dp5_streamed(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev,
                                rho_out_dev, counts_dev, status_dev, s, a);
-  hipError_t e = lme_internal_launch_dp5(EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
+  hipError_t e = col_ept ? lme_internal_launch_dp5_col(col_ept, wo, nc, nb, real_structure(h), &a,
+                                                       (int)plan->packs.size(), plan->max_lds, s)
+                         : lme_internal_launch_dp5(EPT, &a, (int)plan->packs.size(),
+                                                   plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch resident DOPRI5");
   return LME_OK;
 }

@@ -1105,7 +1105,13 @@ __device__ void dp_outputs(const Dp5Args &a, const PackDesc &pk, const PackLds &
   }
 }
 
-template <int T, int EPT>
+// COL: column-owner layout (the packs of the column kernels: thread owns
+// column j of instance b and rows g, g+G, ...), elements evaluated by
+// lindblad_col() with the column-j operator data in registers; otherwise the
+// row layout (thread owns pack elements f = t + s*T), lindblad_elem().  Both
+// give the same bits; everything but the element evaluation goes through the
+// slot's (instance, row, column).
+template <int T, int EPT, int WO, int NC, int NB, bool RE, bool COL>
 __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const PackDesc pk = a.packs[blockIdx.x];
@@ -1147,19 +1153,46 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
 
   double2 rho[EPT], yn[EPT], y5[EPT];
   uint32_t bij[EPT];
+  uint32_t vmask = 0;  // slots this thread owns
   const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
+  // column layout: this thread's column and its operator data
+  const int C = COL ? m * n : 0, G = COL ? pk.G : 1;
+  const bool cactive = COL && tid < C * G;
+  const int cg = cactive ? tid / C : 0, cc = cactive ? tid - cg * C : 0;
+  const int cb = cc / (COL ? n : 1), cj = cc - cb * n;
+  ColData<WO, NC, NB> cd;
+  uint32_t ridx[COL ? EPT : 1];
+  if constexpr (COL) load_column<WO, NC, NB>(cd, make_view(L.blobs + (size_t)cb * pk.blob_stride, BL), cj);
 #pragma unroll
   for (int s = 0; s < EPT; ++s) {
-    const int f = tid + s * T;
     rho[s] = make_double2(0.0, 0.0);
     bij[s] = 0;
-    if (f < E) {
-      const int b = f / n2, r = f - b * n2;
-      const int i = r / n;
-      bij[s] = pack_bij(b, i, r - i * n);
-      rho[s] = rho0[L.off[b] + r];
+    if constexpr (COL) {
+      const int i = cg + s * G;
+      const OpView op = make_view(L.blobs + (size_t)cb * pk.blob_stride, BL);
+      ridx[s] = row_indices<WO, NC>(op, min(i, n - 1));
+      bij[s] = pack_bij(cb, min(i, n - 1), cj);
+      if (cactive && s < pk.ept && i < n) {
+        vmask |= 1u << s;
+        rho[s] = rho0[L.off[cb] + i * n + cj];
+      }
+    } else {
+      const int f = tid + s * T;
+      if (f < E) {
+        vmask |= 1u << s;
+        const int b = f / n2, r = f - b * n2;
+        const int i = r / n;
+        bij[s] = pack_bij(b, i, r - i * n);
+        rho[s] = rho0[L.off[b] + r];
+      }
     }
   }
+  auto valid = [&](int s) { return ((vmask >> s) & 1u) != 0; };
+  // pack element index of slot s
+  auto flat = [&](int s) {
+    if constexpr (COL) return slot_b(bij[s]) * n2 + slot_i(bij[s]) * n + slot_j(bij[s]);
+    else return tid + s * T;
+  };
   auto goff = [&](uint32_t v) { return L.off[slot_b(v)] + slot_i(v) * n + slot_j(v); };
   auto set_controls = [&](int b, int seg) {
     for (int q = 0; q < pk.nb; ++q)
@@ -1170,8 +1203,8 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
   auto outputs = [&]() {
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
-      const int f = tid + s * T;
-      if (f < E) {
+      if (valid(s)) {
+        const int f = flat(s);
         const int b = slot_b(bij[s]);
         const int k = ctl[b].out_due;
         if (k >= 0) {
@@ -1192,7 +1225,14 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     asm volatile("" : "+v"(v));  // no per-slot addresses hoisted across steps
     const int b = slot_b(v);
     const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
-    return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), y, L.u + b * pk.nb);
+    if constexpr (COL) {
+      uint32_t ri = ridx[s];
+      asm volatile("" : "+v"(ri));
+      return lindblad_col<WO, NC, NB, RE>(op, cd, L.Y + b * n2, slot_i(v), ri, slot_j(v), y,
+                                          L.u + b * pk.nb);
+    } else {
+      return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), y, L.u + b * pk.nb);
+    }
   };
 
   outputs();
@@ -1204,13 +1244,13 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     for (int b = tid; b < m; b += T) set_controls(b, a.n_seg > 0 ? a.stop_seg[0] : -1);
 #pragma unroll
     for (int s = 0; s < EPT; ++s)
-      if (tid + s * T < E) L.Y[tid + s * T] = rho[s];
+      if (valid(s)) L.Y[flat(s)] = rho[s];
     __syncthreads();
     double2 (&f0)[EPT] = y5;  // the stage arrays are idle until the first step
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
       f0[s] = make_double2(0.0, 0.0);
-      if (tid + s * T < E) {
+      if (valid(s)) {
         f0[s] = elem(s, rho[s]);
         K[goff(bij[s])] = f0[s];
       }
@@ -1218,8 +1258,8 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
-      const int f = tid + s * T;
-      if (f < E) {
+      if (valid(s)) {
+        const int f = flat(s);
         const double sc = a.atol + a.rtol * hypot(rho[s].x, rho[s].y);
         const double r0 = hypot(rho[s].x, rho[s].y) / sc, r1 = hypot(f0[s].x, f0[s].y) / sc;
         red[f] = r0 * r0;
@@ -1239,22 +1279,22 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < EPT; ++s)
-      if (tid + s * T < E) {
+      if (valid(s)) {
         const double hs = ctl[slot_b(bij[s])].hs;
-        L.Y[tid + s * T] = caxpy(hs, f0[s], rho[s]);
+        L.Y[flat(s)] = caxpy(hs, f0[s], rho[s]);
       }
     __syncthreads();
     double2 (&f1)[EPT] = yn;
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
       f1[s] = make_double2(0.0, 0.0);
-      if (tid + s * T < E) f1[s] = elem(s, L.Y[tid + s * T]);
+      if (valid(s)) f1[s] = elem(s, L.Y[flat(s)]);
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
-      const int f = tid + s * T;
-      if (f < E) {
+      if (valid(s)) {
+        const int f = flat(s);
         const double sc = a.atol + a.rtol * hypot(rho[s].x, rho[s].y);
         const double r2 = hypot(f1[s].x - f0[s].x, f1[s].y - f0[s].y) / sc;
         red[f] = r2 * r2;
@@ -1306,8 +1346,8 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     for (int st = 0; st < 7; ++st) {
 #pragma unroll
       for (int s = 0; s < EPT; ++s) {
-        const int f = tid + s * T;
-        if (f < E) {
+        if (valid(s)) {
+          const int f = flat(s);
           const DpCtl &c = ctl[slot_b(bij[s])];
           if (c.active) {
             double2 y = rho[s];
@@ -1326,8 +1366,7 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < EPT; ++s) {
-        const int f = tid + s * T;
-        if (f < E) {
+        if (valid(s)) {
           const DpCtl &c = ctl[slot_b(bij[s])];
           if (c.active && (st > 0 || c.need_k1)) K[st * SE + goff(bij[s])] = elem(s, yn[s]);
         }
@@ -1338,8 +1377,8 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     // ---- error norm: RMS over the n^2 moduli of e / (atol + rtol max(|rho|, |y5|))
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
-      const int f = tid + s * T;
-      if (f < E) {
+      if (valid(s)) {
+        const int f = flat(s);
         const DpCtl &c = ctl[slot_b(bij[s])];
         double v = 0.0;
         if (c.active) {
@@ -1395,8 +1434,7 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     // ---- accepted instances move to the fifth-order solution; k7 -> k1
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
-      const int f = tid + s * T;
-      if (f < E && ctl[slot_b(bij[s])].accept) {
+      if (valid(s) && ctl[slot_b(bij[s])].accept) {
         rho[s] = y5[s];
         const int64_t g = goff(bij[s]);
         K[g] = K[6 * SE + g];
@@ -1410,7 +1448,7 @@ finish:
   if (a.rho_out) {
 #pragma unroll
     for (int s = 0; s < EPT; ++s)
-      if (tid + s * T < E) reinterpret_cast<double2 *>(a.rho_out)[goff(bij[s])] = rho[s];
+      if (valid(s)) reinterpret_cast<double2 *>(a.rho_out)[goff(bij[s])] = rho[s];
   }
   for (int b = tid; b < m; b += T) {
     const int id = L.ids[b];
@@ -2605,9 +2643,9 @@ extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb) {
   return (wo == 1 && nc == 2) || (wo == 1 && nc == 3) || (wo == 2 && nc == 2 && nb == 0);
 }
 
-template <int T, int EPT>
+template <int T, int EPT, int WO = 0, int NC = 0, int NB = 0, bool RE = false, bool COL = false>
 static hipError_t launch_dp5_t(const lme::Dp5Args &a, int n_packs, int lds, hipStream_t s) {
-  auto k = lme::dp5_resident_kernel<T, EPT>;
+  auto k = lme::dp5_resident_kernel<T, EPT, WO, NC, NB, RE, COL>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -2625,6 +2663,24 @@ extern "C" int lme_internal_dp5_epts(int *ept, int cap) {
 // LDS beyond the pack proper: per-instance step control and 2 m doubles.
 extern "C" int lme_internal_dp5_extra_lds(int m) {
   return lme::dp_ctl_bytes(m) + lme::align16(16 * m);
+}
+
+// Column-owner resident Dormand-Prince: 512 threads, up to EPT rows per
+// thread, the column-kernel shapes.
+extern "C" hipError_t lme_internal_launch_dp5_col(int EPT, int wo, int nc, int nb, int re,
+                                                  const lme::Dp5Args *a, int n_packs, int lds,
+                                                  hipStream_t s) {
+#define LME_DC(E, W, K, B, R) \
+  if (EPT == E && wo == W && nc == K && nb == B && re == R) \
+    return launch_dp5_t<512, E, W, K, B, (R != 0), true>(*a, n_packs, lds, s);
+#define LME_DC_E(E)                                                                   \
+  LME_DC(E, 1, 2, 0, 0) LME_DC(E, 1, 3, 0, 0) LME_DC(E, 2, 2, 0, 0) LME_DC(E, 1, 2, 1, 0) \
+  LME_DC(E, 1, 3, 1, 0) LME_DC(E, 1, 2, 0, 1) LME_DC(E, 1, 3, 0, 1) LME_DC(E, 2, 2, 0, 1) \
+  LME_DC(E, 1, 2, 1, 1) LME_DC(E, 1, 3, 1, 1)
+  LME_DC_E(8) LME_DC_E(16)
+#undef LME_DC_E
+#undef LME_DC
+  return hipErrorInvalidValue;
 }
 
 extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,

@@ -72,6 +72,28 @@ def test_dp5_batched_ragged_jc_per_instance_control():
     assert len(set(counts[:, 0])) > 1
 
 
+def test_dp5_column_layout_identical_bits():
+    """The column-owner resident kernel evaluates each element with the same
+    arithmetic as the row kernel and reduces the error norm in the same
+    order: identical step sequences and identical bits, on a batched ragged
+    sweep (one rows-per-thread bound) and the Kerr cavity (the other)."""
+    w = S.jc_sweep(n_inst=20, seed=83, t_end=2.0, n_out=5, coherent=True)
+    _, row = run(w.systems, w.tlist, 1e-7, 1e-10, layout=lme.LME_LAYOUT_ROW, want_states=True)
+    _, col = run(w.systems, w.tlist, 1e-7, 1e-10, layout=lme.LME_LAYOUT_COLUMN,
+                 want_states=True)
+    for k in ("expect", "states", "rho", "counts", "status"):
+        assert torch.equal(row[k], col[k]), k
+    ws = S.kerr_single()
+    s = ws.systems[0]
+    tl = np.linspace(0.0, 2.0, 5)
+    _, row = run([s], tl, ws.rtol, ws.atol, layout=lme.LME_LAYOUT_ROW)
+    _, col = run([s], tl, ws.rtol, ws.atol, layout=lme.LME_LAYOUT_COLUMN)
+    for k in ("expect", "rho", "counts", "status"):
+        assert torch.equal(row[k], col[k]), k
+    r = oracle.dopri5(s, s.rho0, tl, ws.rtol, ws.atol)
+    close(col["expect"].cpu().numpy()[0], r["expect"])
+
+
 def test_dp5_controls_stop_on_edges():
     w = S.jc_drive(n_inst=4, N=4, n_seg=6, t_end=1.2, steps_per_seg=1, sigma_u=0.8)
     tl = np.array([0.0, 0.5, 1.2])
