@@ -141,6 +141,55 @@ def streamed_apply_bench(lme, systems, torch, reps=20):
     return res
 
 
+def tfim_apply_bench(lme, systems, torch, reps=10):
+    """HBM roofline of the Liouvillian application on 8-spin chains (n = 256,
+    1 MiB per state): 64 realizations (134 MB per application) and 512 (1.07
+    GB, past the last-level cache).  Algorithmic bytes 32 n^2 per instance.
+    The default form runs the row-block kernel; the plain streamed kernel
+    (every gather from memory) and a device copy of the same bytes are timed
+    beside it."""
+    res = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e3 / reps
+
+    for n_inst in (64, 512):
+        w = systems.tfim(n_inst=n_inst)
+        h = lme.Handle(w.systems)
+        y = h.pack([s.rho0 for s in w.systems], device="cuda:0")
+        y.copy_(torch.randn_like(y))   # every element populated
+        out = torch.empty_like(y)
+        nbytes = 32.0 * h.state_elems
+        r = {"algorithmic_bytes": nbytes}
+        for name, form in (("row_blocks", lme.LME_FORM_OPERATOR),
+                           ("plain_streamed", lme.LME_FORM_OPERATOR_STREAMED)):
+            def go(form=form):
+                rc = lme.load().lme_apply(h._h, form, 0, 0.0, None, lme._ptr(y), lme._ptr(out),
+                                          lme._stream_ptr(stream))
+                assert rc == 0
+            us = timed(go)
+            gbs = nbytes / (us * 1e-6) / 1e9
+            r[name] = {"us_per_apply": us, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        src = torch.empty_like(y)
+        cus = timed(lambda: out.copy_(src))
+        r["row_blocks"]["kernel"] = "apply_rows_kernel"
+        r["device_copy"] = {"us": cus, "GBs": nbytes / (cus * 1e-6) / 1e9}
+        r["row_blocks"]["frac_of_copy"] = cus / r["row_blocks"]["us_per_apply"]
+        res[f"tfim_8spin_x{n_inst}"] = r
+        del h, y, out, src
+        torch.cuda.empty_cache()
+    return res
+
+
 def other_configs(lme, systems, torch):
     """Wall time of each of the other headline configurations, one run after a
     warm-up (HIP events on the launch stream; the adaptive streamed path
@@ -352,6 +401,7 @@ def main():
     if full_path:
         rec["full_path"] = full_path
     rec["streamed_apply"] = streamed_apply_bench(lme, systems, torch)
+    rec["streamed_apply_tfim"] = tfim_apply_bench(lme, systems, torch)
     if not args.no_configs:
         rec["other_configs"] = other_configs(lme, systems, torch)
     if not args.no_cpu:

@@ -50,6 +50,8 @@ extern "C" hipError_t lme_internal_launch_dp5_col(int EPT, int wo, int nc, int n
 extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, int n_packs,
                                               int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_apply_rows(int R, int re, const lme::ApplyGArgs *a,
+                                                    int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
                                               hipStream_t s);
@@ -242,8 +244,11 @@ struct lme_ctx {
   DevBuf d_ckpt;
   // streamed kernels: element tiles (per instance; packed-buffer chunks)
   std::vector<lme::Tile> tiles;
-  DevBuf d_tiles, d_ptiles;
+  DevBuf d_tiles, d_ptiles, d_rtiles;
   int32_t n_ptiles = 0;
+  // row-block application: tiles of rtile_R rows (0: not built, -1: the
+  // batch has an instance outside 128 <= n <= 1024)
+  int32_t n_rtiles = 0, rtile_R = 0, rtile_lds = 0;
   // superoperator form (assembled on first use from the folded operators)
   std::vector<Sparse> A_host;
   std::vector<std::vector<Sparse>> C_host;
@@ -1389,12 +1394,63 @@ static int ensure_packed_tiles(lme_ctx *h) {
   return LME_OK;
 }
 
+// Row blocks for the row-block application: 16 rows when every instance has
+// n <= 256, else 4 (n <= 1024), so a block stages at most 64 KB.  Instances
+// below n = 128 are left to the pack kernels, which serve them better.
+static int ensure_row_tiles(lme_ctx *h) {
+  if (h->rtile_R) return LME_OK;
+  int max_n = 0, min_n = 1 << 30;
+  for (int32_t n : h->dims) {
+    max_n = std::max(max_n, n);
+    min_n = std::min(min_n, n);
+  }
+  if (min_n < 128 || max_n > 1024) {
+    h->rtile_R = -1;
+    return LME_OK;
+  }
+  const int R = max_n <= 256 ? 16 : 4;
+  std::vector<lme::Tile> t;
+  for (int b = 0; b < h->n_inst; ++b)
+    for (int r0 = 0; r0 < h->dims[b]; r0 += R) {
+      lme::Tile x;
+      x.inst = b;
+      x.e0 = r0;
+      x.e1 = std::min(r0 + R, h->dims[b]);
+      x.pad = 0;
+      t.push_back(x);
+    }
+  int rc = h->d_rtiles.upload(t.data(), t.size() * sizeof(lme::Tile), "row tiles");
+  if (rc) return rc;
+  // LDS: R rows of y and the row-side entries of the block's rows (complex
+  // D, Oval, Jval; int Ocol, Jcol) for the widest forward or adjoint operator
+  int wo = 0, ncw = 0;
+  for (auto &d : h->inst)
+    for (const lme::Signature *sg : {&d.fwd, &d.adj}) {
+      wo = std::max(wo, (int)sg->wo);
+      ncw = std::max(ncw, (int)(sg->nc * sg->wc));
+    }
+  const int64_t lds = 16LL * R * max_n + 16LL * R * (1 + wo + ncw) + 4LL * R * (wo + ncw);
+  if (lds > h->lds_limit) {
+    h->rtile_R = -1;
+    return LME_OK;
+  }
+  h->n_rtiles = (int32_t)t.size();
+  h->rtile_R = R;
+  h->rtile_lds = (int32_t)lds;
+  return LME_OK;
+}
+
+// Streamed application (stage input and result in HBM).  rows: allow the
+// row-block kernel (every instance 128 <= n <= 1024); otherwise, and for the
+// explicit streamed form, every element gathers straight from memory.
 static int apply_streamed(lme_ctx *h, int adjoint, double t, const double *u_dev,
-                          const void *y_dev, void *out_dev, hipStream_t s) {
+                          const void *y_dev, void *out_dev, hipStream_t s, bool rows) {
   if (h->state_elems >= (int64_t)1 << 31)
     return fail(LME_ENOTSUP, "the streamed application addresses states below 2^31 elements");
-  int rc = ensure_packed_tiles(h);
+  int rc = rows ? ensure_row_tiles(h) : LME_OK;
   if (rc) return rc;
+  rows = rows && h->rtile_R > 0;
+  if (!rows && (rc = ensure_packed_tiles(h))) return rc;
   lme::ApplyGArgs a;
   std::memset(&a, 0, sizeof a);
   a.tiles = static_cast<const lme::Tile *>(h->d_ptiles.p);
@@ -1408,6 +1464,13 @@ static int apply_streamed(lme_ctx *h, int adjoint, double t, const double *u_dev
   a.seg = segment_at(h, t);
   a.y = static_cast<const double *>(y_dev);
   a.out = static_cast<double *>(out_dev);
+  if (rows) {
+    a.tiles = static_cast<const lme::Tile *>(h->d_rtiles.p);
+    a.n_tiles = h->n_rtiles;
+    hipError_t e = lme_internal_launch_apply_rows(h->rtile_R, adjoint ? 0 : real_structure(h), &a,
+                                                  h->rtile_lds, s);
+    return e == hipSuccess ? LME_OK : hip_fail(e, "launch row-block apply");
+  }
   hipError_t e = lme_internal_launch_apply_global(&a, s);
   return e == hipSuccess ? LME_OK : hip_fail(e, "launch streamed apply");
 }
@@ -1678,7 +1741,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
     return e == hipSuccess ? LME_OK : hip_fail(e, "launch superoperator");
   }
   if (form == LME_FORM_OPERATOR_STREAMED)
-    return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
+    return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s, false);
   int wo, nc, nb;
   if (!adjoint && column_eligible(h, &wo, &nc, &nb) && h->apply_path == 0 &&
       2 * lme::kPipeStage + lme::kPipeMaxTiles * (int)sizeof(lme::PTile) + 16 <= h->lds_limit) {
@@ -1729,7 +1792,7 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   // enough HBM reads in flight
   Plan *plan;
   rc = plan_packs(h, 256, 0, adjoint, h->apply_cap, 0, 0, &plan);
-  if (rc == LME_ENOTSUP) return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s);
+  if (rc == LME_ENOTSUP) return apply_streamed(h, adjoint, t, u_dev, y_dev, out_dev, s, true);
   if (rc) return rc;
   lme::ApplyArgs a;
   std::memset(&a, 0, sizeof a);

@@ -2086,6 +2086,190 @@ __global__ __launch_bounds__(T) void apply_global_kernel(ApplyGArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Row-block streamed application, for instances too large for a resident
+// pack (128 <= n <= 1024).  A workgroup takes rows [r0, r1) (at most R) of
+// one instance and stages them in LDS; thread t owns columns t, t + 256, ...
+// and keeps the R accumulators of its column in registers.  The column side
+// of every product (y A^+), and every left product or jump whose source row
+// lies in the block, reads LDS; the other source rows are read through the
+// caches (the row is the same for the whole workgroup, so each such read is
+// one contiguous row segment).  The row-side operator entries are the same
+// for all lanes (scalar loads).  Every element accumulates its terms in the
+// order of lindblad_elem(), with exactly-zero parts skipped under RE (real
+// jump coefficients, imaginary off-diagonal entries), so the results are
+// those of the other application kernels.
+// ---------------------------------------------------------------------------
+// Word 3 of a buffer resource for plain (untyped, raw) loads on this chip.
+constexpr int kBufferFlags = 0x00020000;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Row-side operator entries are read through the constant address space
+// (the same address in every lane: scalar loads, batched by the compiler).
+template <typename T>
+using cptr = const T __attribute__((address_space(4))) *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
+__device__ __forceinline__ cptr<double> as_const2(const double2 *p) {
+  return (cptr<double>)p;
+}
+// complex element idx of a constant-space complex array
+__device__ __forceinline__ double2 cld(cptr<double> p, int idx) {
+  return make_double2(p[2 * idx], p[2 * idx + 1]);
+}
+
+template <int R, int RT, bool RE>
+__global__ __launch_bounds__(256 * R / RT) void apply_rows_kernel(ApplyGArgs a) {
+  constexpr int NT = 256 * R / RT;  // threads: 256 columns x R / RT row groups
+  extern __shared__ __align__(16) uint8_t smem[];
+  double2 *Ys = reinterpret_cast<double2 *>(smem);
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const Tile tl = a.tiles[tix];
+  const int b = tl.inst, r0 = tl.e0, rows = tl.e1 - tl.e0;
+  const InstDesc &d = a.inst[b];
+  const int n = d.n;
+  const Signature &sg = a.adjoint ? d.adj : d.fwd;
+  const OpView op = make_view(a.ops + (a.adjoint ? d.adj_off : d.ops_off),
+                              blob_layout(n, sg.wo, sg.nb, sg.wb, sg.nc, sg.wc));
+  const int nb = a.seg < 0 ? 0 : op.nb;  // no control amplitude outside all segments
+  const double *uq = a.u + (int64_t)b * a.n_ctrl * a.n_seg + (a.seg < 0 ? 0 : a.seg);
+  const double2 *Yg = reinterpret_cast<const double2 *>(a.y) + d.rho_off;
+  double2 *out = reinterpret_cast<double2 *>(a.out) + d.rho_off;
+  // LDS: the block's rows of y, then the row-side entries of its rows:
+  // D [R] | Oval [wo][R] | Jval [nc wc][R] (complex) | Ocol [wo][R] |
+  // Jcol [nc wc][R] (int)
+  const int ncw = op.nc * op.wc;
+  double2 *Rd = Ys + R * n, *Rov = Rd + R, *Rjv = Rov + op.wo * R;
+  int32_t *Roc = reinterpret_cast<int32_t *>(Rjv + ncw * R), *Rjc = Roc + op.wo * R;
+
+  for (int e = threadIdx.x; e < rows * n; e += NT) Ys[e] = Yg[(int64_t)r0 * n + e];
+  for (int e = threadIdx.x; e < (1 + op.wo + ncw) * R; e += NT) {
+    const int q = e / R, r = e - q * R;
+    if (r >= rows) continue;
+    if (q == 0) {
+      Rd[r] = op.D[r0 + r];
+    } else if (q <= op.wo) {
+      Rov[(q - 1) * R + r] = op.Oval[(q - 1) * n + r0 + r];
+      Roc[(q - 1) * R + r] = op.Ocol[(q - 1) * n + r0 + r];
+    } else {
+      const int k = q - 1 - op.wo;
+      Rjv[k * R + r] = op.Jval[k * n + r0 + r];
+      Rjc[k * R + r] = op.Jcol[k * n + r0 + r];
+    }
+  }
+  __syncthreads();
+  // this thread's rows: rb + r, r < RT (the same for the whole wavefront)
+  const int rb = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 256) * RT);
+  const int jt = threadIdx.x & 255;
+  // element (c, j) of y for a source row c that is the same for all lanes:
+  // LDS inside the block, else a buffer load over this instance's n^2
+  // elements (a load kind of its own, so the two never merge into a flat
+  // access)
+  const __amdgpu_buffer_rsrc_t yrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2 *>(Yg), 0, 16 * n * n, kBufferFlags);
+  auto Yrow = [&](int c, int j) {
+    if (c >= r0 && c < r0 + rows) return Ys[(c - r0) * n + j];
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(yrs, (uint32_t)(c * n + j) * 16u, 0, 0);
+    return __builtin_bit_cast(double2, v);
+  };
+  // acc += v * y and acc += conj(v) * y, exactly-zero parts skipped under RE
+  auto fma_v = [](double2 v, double2 y, double2 acc) {
+    if (RE) return make_double2(fma(-v.y, y.y, acc.x), fma(v.y, y.x, acc.y));
+    return cfma(v, y, acc);
+  };
+  auto fma_cv = [](double2 v, double2 y, double2 acc) {
+    if (RE) return make_double2(fma(v.y, y.y, acc.x), fma(-v.y, y.x, acc.y));
+    return cfma_conj(v, y, acc);
+  };
+
+  for (int j = jt; j < n; j += 256) {
+    double2 acc[RT], yv[RT];
+    const double2 dj = cconj(op.D[j]);
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) acc[r] = cmul(cadd(Rd[rb + r], dj), Ys[(rb + r) * n + j]);
+    // A y: source rows Ocol[w][i]; the R gathers of a term are issued
+    // before its products
+    for (int w = 0; w < op.wo; ++w) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) yv[r] = Yrow(Roc[w * R + rb + r], j);
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) acc[r] = fma_v(Rov[w * R + rb + r], yv[r], acc[r]);
+    }
+    // y A^+: row i, columns Ocol[w][j]
+    for (int w = 0; w < op.wo; ++w) {
+      const int c = op.Ocol[w * n + j];
+      const double2 v = op.Oval[w * n + j];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) acc[r] = fma_cv(v, Ys[(rb + r) * n + c], acc[r]);
+    }
+    // control terms u_q (B_q y + y B_q^+), as a separate sum scaled by u_q
+    for (int q = 0; q < nb; ++q) {
+      const double u = uq[q * a.n_seg];
+      if (u == 0.0) continue;
+      const cptr<double> DBr = as_const2(op.DB + q * n), OBvr = as_const2(op.OBval + q * op.wb * n);
+      const cptr<int32_t> OBcr = as_const(op.OBcol + q * op.wb * n);
+      const double2 *OBv = op.OBval + q * op.wb * n;
+      const int32_t *OBc = op.OBcol + q * op.wb * n;
+      double2 t[RT];
+      const double2 dbj = cconj(op.DB[q * n + j]);
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) t[r] = cmul(cadd(cld(DBr, r0 + rb + r), dbj), Ys[(rb + r) * n + j]);
+      for (int w = 0; w < op.wb; ++w) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (rb + r < rows) yv[r] = Yrow(OBcr[w * n + r0 + rb + r], j);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (rb + r < rows) t[r] = fma_v(cld(OBvr, w * n + r0 + rb + r), yv[r], t[r]);
+      }
+      for (int w = 0; w < op.wb; ++w) {
+        const int c = OBc[w * n + j];
+        const double2 v = OBv[w * n + j];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (rb + r < rows) t[r] = fma_cv(v, Ys[(rb + r) * n + c], t[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) acc[r] = caxpy(u, t[r], acc[r]);
+    }
+    // jumps C_k y C_k^+
+    for (int k = 0; k < op.nc; ++k) {
+      const int kw = k * op.wc * n;
+      for (int w = 0; w < op.wc; ++w)
+        for (int v = 0; v < op.wc; ++v) {
+          const double2 vj = op.Jval[kw + v * n + j];
+          const int cj = op.Jcol[kw + v * n + j];
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            if (rb + r < rows) yv[r] = Yrow(Rjc[(k * op.wc + w) * R + rb + r], cj);
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            if (rb + r < rows) {
+              const double2 vi = Rjv[(k * op.wc + w) * R + rb + r];
+              if (RE) {
+                const double p = vi.x * vj.x;
+                acc[r] = make_double2(fma(p, yv[r].x, acc[r].x), fma(p, yv[r].y, acc[r].y));
+              } else {
+                acc[r] = cfma(cmul(vi, cconj(vj)), yv[r], acc[r]);
+              }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) out[(int64_t)(r0 + rb + r) * n + j] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Superoperator form: out = S y with S the explicit n^2 x n^2 Liouvillian of
 // each instance in slot-major ELL (consecutive rows adjacent per slot, so the
 // column and value reads are coalesced); y read through the caches.
@@ -2720,6 +2904,27 @@ extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a,
   const int grid = 8 * ((a->n_tiles + 7) / 8);
   hipLaunchKernelGGL(lme::apply_global_kernel<256>, dim3(grid), dim3(256), 0, s, *a);
   return hipGetLastError();
+}
+
+// rows per thread of the 16-row kernel
+constexpr int kRowsRT = 4;
+// Row-block streamed application: R = 16 rows per tile (n <= 256) or 4
+// (n <= 1024); lds = R * max n * 16 bytes.
+extern "C" hipError_t lme_internal_launch_apply_rows(int R, int re, const lme::ApplyGArgs *a,
+                                                    int lds, hipStream_t s) {
+  const int grid = 8 * ((a->n_tiles + 7) / 8);
+  auto go = [&](auto k) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(R == 16 ? 256 * 16 / kRowsRT : 256), lds, s, *a);
+    return hipGetLastError();
+  };
+  if (R == 16)
+    return re ? go(lme::apply_rows_kernel<16, kRowsRT, true>)
+              : go(lme::apply_rows_kernel<16, kRowsRT, false>);
+  if (R == 4) return re ? go(lme::apply_rows_kernel<4, 4, true>) : go(lme::apply_rows_kernel<4, 4, false>);
+  return hipErrorInvalidValue;
 }
 
 extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s) {
