@@ -53,6 +53,9 @@ extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a,
 extern "C" hipError_t lme_internal_launch_apply_rows(int R, int re, const lme::ApplyGArgs *a,
                                                     int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_superop(const lme::SuperArgs *a, hipStream_t s);
+extern "C" hipError_t lme_internal_sdp_rows_prepare(int re, int lds);
+extern "C" hipError_t lme_internal_launch_sdp_rows(int s, int re, const lme::StreamArgs *a,
+                                                   int lds, hipStream_t st);
 extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::StreamArgs *a,
                                               hipStream_t s);
 extern "C" hipError_t lme_internal_launch_apply_pipe(int wo, int nc, int nb, int re,
@@ -249,6 +252,9 @@ struct lme_ctx {
   // row-block application: tiles of rtile_R rows (0: not built, -1: the
   // batch has an instance outside 128 <= n <= 1024)
   int32_t n_rtiles = 0, rtile_R = 0, rtile_lds = 0;
+  // streamed steppers: > 0 when their tiles are 16-row blocks (the LDS of
+  // the row-block stage kernel)
+  int32_t srows_lds = 0;
   // superoperator form (assembled on first use from the folded operators)
   std::vector<Sparse> A_host;
   std::vector<std::vector<Sparse>> C_host;
@@ -994,8 +1000,15 @@ static int evolve_dp5_streamed(lme_ctx *h, const lme_options *opt, int32_t n_t,
   a.expect = static_cast<double *>(expect_dev);
   a.counts = counts_dev;
   a.status = status_dev;
+  const int re = real_structure(h);
+  if (h->srows_lds > 0) {
+    hipError_t e = lme_internal_sdp_rows_prepare(re, h->srows_lds);
+    if (e != hipSuccess) return hip_fail(e, "set up the row-block stage kernel");
+  }
   auto L = [&](int which, int arg, hipStream_t st) -> int {
-    hipError_t e = lme_internal_launch_sdp(which, arg, &a, st);
+    hipError_t e = which == 0 && h->srows_lds > 0
+                       ? lme_internal_launch_sdp_rows(arg, re, &a, h->srows_lds, st)
+                       : lme_internal_launch_sdp(which, arg, &a, st);
     return e == hipSuccess ? LME_OK : hip_fail(e, "launch streamed DOPRI5");
   };
   hipError_t e = hipMemcpyAsync(a.rho, rho0_dev, (size_t)h->state_elems * 16,
@@ -1355,14 +1368,26 @@ constexpr int kTileElems = 2048;
 
 static int ensure_tiles(lme_ctx *h) {
   if (h->d_tiles.p) return LME_OK;
+  // every instance 128 <= n <= 256: tiles of 16 whole rows, for the
+  // row-block stage kernel of the adaptive stepper; else kTileElems elements
+  int max_n = 0, min_n = 1 << 30, wo = 0, ncw = 0;
+  for (auto &d : h->inst) {
+    max_n = std::max(max_n, d.n);
+    min_n = std::min(min_n, d.n);
+    wo = std::max(wo, (int)d.fwd.wo);
+    ncw = std::max(ncw, (int)(d.fwd.nc * d.fwd.wc));
+  }
+  const int64_t rows_lds = 16LL * 16 * max_n + 16LL * 16 * (1 + wo + ncw) + 4LL * 16 * (wo + ncw);
+  h->srows_lds = (min_n >= 128 && max_n <= 256 && rows_lds <= h->lds_limit) ? (int)rows_lds : 0;
   std::vector<lme::Tile> t;
   for (int b = 0; b < h->n_inst; ++b) {
-    const int n2 = h->inst[b].n * h->inst[b].n;
-    for (int e0 = 0; e0 < n2; e0 += kTileElems) {
+    const int n = h->inst[b].n, n2 = n * n;
+    const int step = h->srows_lds ? 16 * n : kTileElems;
+    for (int e0 = 0; e0 < n2; e0 += step) {
       lme::Tile x;
       x.inst = b;
       x.e0 = e0;
-      x.e1 = std::min(n2, e0 + kTileElems);
+      x.e1 = std::min(n2, e0 + step);
       x.pad = 0;
       t.push_back(x);
     }

@@ -2099,6 +2099,8 @@ __global__ __launch_bounds__(T) void apply_global_kernel(ApplyGArgs a) {
 // jump coefficients, imaginary off-diagonal entries), so the results are
 // those of the other application kernels.
 // ---------------------------------------------------------------------------
+// rows per thread of the 16-row kernels
+constexpr int kRowsRT = 4;
 // Word 3 of a buffer resource for plain (untyped, raw) loads on this chip.
 constexpr int kBufferFlags = 0x00020000;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -2119,15 +2121,174 @@ __device__ __forceinline__ double2 cld(cptr<double> p, int idx) {
   return make_double2(p[2 * idx], p[2 * idx + 1]);
 }
 
+// LDS of a row block: the block's rows of y, then the row-side entries of
+// its rows: D [R] | Oval [wo][R] | Jval [nc wc][R] (complex) | Ocol [wo][R] |
+// Jcol [nc wc][R] (int).
+template <int R>
+struct RowBlock {
+  double2 *Ys, *Rd, *Rov, *Rjv;
+  int32_t *Roc, *Rjc;
+  int r0, rows;
+};
+
+template <int R>
+__device__ __forceinline__ RowBlock<R> carve_rows(uint8_t *smem, const OpView &op, int r0,
+                                                  int rows) {
+  RowBlock<R> k;
+  const int n = op.n, ncw = op.nc * op.wc;
+  k.Ys = reinterpret_cast<double2 *>(smem);
+  k.Rd = k.Ys + R * n;
+  k.Rov = k.Rd + R;
+  k.Rjv = k.Rov + op.wo * R;
+  k.Roc = reinterpret_cast<int32_t *>(k.Rjv + ncw * R);
+  k.Rjc = k.Roc + op.wo * R;
+  k.r0 = r0;
+  k.rows = rows;
+  return k;
+}
+
+// Stages rows [r0, r0 + rows) of y (n x n, HBM) and their operator entries;
+// all NT threads take part, the caller synchronises.
+template <int R, int NT>
+__device__ __forceinline__ void stage_rows(const RowBlock<R> &k, const OpView &op,
+                                           const double2 *Yg) {
+  const int n = op.n, ncw = op.nc * op.wc, r0 = k.r0, rows = k.rows;
+  for (int e = threadIdx.x; e < rows * n; e += NT) k.Ys[e] = Yg[(int64_t)r0 * n + e];
+  for (int e = threadIdx.x; e < (1 + op.wo + ncw) * R; e += NT) {
+    const int q = e / R, r = e - q * R;
+    if (r >= rows) continue;
+    if (q == 0) {
+      k.Rd[r] = op.D[r0 + r];
+    } else if (q <= op.wo) {
+      k.Rov[(q - 1) * R + r] = op.Oval[(q - 1) * n + r0 + r];
+      k.Roc[(q - 1) * R + r] = op.Ocol[(q - 1) * n + r0 + r];
+    } else {
+      const int kk = q - 1 - op.wo;
+      k.Rjv[kk * R + r] = op.Jval[kk * n + r0 + r];
+      k.Rjc[kk * R + r] = op.Jcol[kk * n + r0 + r];
+    }
+  }
+}
+
+// (L y)_ij for column j and the rows rb + r (r < RT) of a staged block: the
+// terms of lindblad_elem() in its order, exactly-zero parts skipped under RE
+// (real jump coefficients, imaginary off-diagonal entries).  Source rows
+// outside the block are read from Yg (a buffer load over the instance's n^2
+// elements: a load kind of its own, so LDS and HBM reads never merge into a
+// flat access).  uq[q * ustride] are the control amplitudes (nb of them).
+template <int R, int RT, bool RE>
+__device__ __forceinline__ void rows_lindblad(const RowBlock<R> &k, const OpView &op,
+                                              const double2 *Yg, int nb, const double *uq,
+                                              int ustride, int rb, int j, double2 (&acc)[RT]) {
+  const int n = op.n, r0 = k.r0, rows = k.rows;
+  const double2 *Ys = k.Ys;
+  const __amdgpu_buffer_rsrc_t yrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2 *>(Yg), 0, 16 * n * n, kBufferFlags);
+  // element (c, j) of y for a source row c that is the same for all lanes
+  auto Yrow = [&](int c, int jj) {
+    if (c >= r0 && c < r0 + rows) return Ys[(c - r0) * n + jj];
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(yrs, (uint32_t)(c * n + jj) * 16u, 0, 0);
+    return __builtin_bit_cast(double2, v);
+  };
+  // acc += v * y and acc += conj(v) * y
+  auto fma_v = [](double2 v, double2 y, double2 a) {
+    if (RE) return make_double2(fma(-v.y, y.y, a.x), fma(v.y, y.x, a.y));
+    return cfma(v, y, a);
+  };
+  auto fma_cv = [](double2 v, double2 y, double2 a) {
+    if (RE) return make_double2(fma(v.y, y.y, a.x), fma(-v.y, y.x, a.y));
+    return cfma_conj(v, y, a);
+  };
+  double2 yv[RT];
+  const double2 dj = cconj(op.D[j]);
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+    if (rb + r < rows) acc[r] = cmul(cadd(k.Rd[rb + r], dj), Ys[(rb + r) * n + j]);
+  // A y: source rows Ocol[w][i]; the RT gathers of a term are issued before
+  // its products
+  for (int w = 0; w < op.wo; ++w) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) yv[r] = Yrow(k.Roc[w * R + rb + r], j);
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) acc[r] = fma_v(k.Rov[w * R + rb + r], yv[r], acc[r]);
+  }
+  // y A^+: row i, columns Ocol[w][j]
+  for (int w = 0; w < op.wo; ++w) {
+    const int c = op.Ocol[w * n + j];
+    const double2 v = op.Oval[w * n + j];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) acc[r] = fma_cv(v, Ys[(rb + r) * n + c], acc[r]);
+  }
+  // control terms u_q (B_q y + y B_q^+), a separate sum scaled by u_q (row
+  // side read through the constant address space)
+  for (int q = 0; q < nb; ++q) {
+    const double u = uq[q * ustride];
+    if (u == 0.0) continue;
+    const cptr<double> DBr = as_const2(op.DB + q * n), OBvr = as_const2(op.OBval + q * op.wb * n);
+    const cptr<int32_t> OBcr = as_const(op.OBcol + q * op.wb * n);
+    const double2 *OBv = op.OBval + q * op.wb * n;
+    const int32_t *OBc = op.OBcol + q * op.wb * n;
+    double2 t[RT];
+    const double2 dbj = cconj(op.DB[q * n + j]);
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) t[r] = cmul(cadd(cld(DBr, r0 + rb + r), dbj), Ys[(rb + r) * n + j]);
+    for (int w = 0; w < op.wb; ++w) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) yv[r] = Yrow(OBcr[w * n + r0 + rb + r], j);
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) t[r] = fma_v(cld(OBvr, w * n + r0 + rb + r), yv[r], t[r]);
+    }
+    for (int w = 0; w < op.wb; ++w) {
+      const int c = OBc[w * n + j];
+      const double2 v = OBv[w * n + j];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rb + r < rows) t[r] = fma_cv(v, Ys[(rb + r) * n + c], t[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      if (rb + r < rows) acc[r] = caxpy(u, t[r], acc[r]);
+  }
+  // jumps C_k y C_k^+
+  for (int kk = 0; kk < op.nc; ++kk) {
+    const int kw = kk * op.wc * n;
+    for (int w = 0; w < op.wc; ++w)
+      for (int v = 0; v < op.wc; ++v) {
+        const double2 vj = op.Jval[kw + v * n + j];
+        const int cj = op.Jcol[kw + v * n + j];
+        const int slot = (kk * op.wc + w) * R + rb;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (rb + r < rows) yv[r] = Yrow(k.Rjc[slot + r], cj);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (rb + r < rows) {
+            const double2 vi = k.Rjv[slot + r];
+            if (RE) {
+              const double p = vi.x * vj.x;
+              acc[r] = make_double2(fma(p, yv[r].x, acc[r].x), fma(p, yv[r].y, acc[r].y));
+            } else {
+              acc[r] = cfma(cmul(vi, cconj(vj)), yv[r], acc[r]);
+            }
+          }
+      }
+  }
+}
+
 template <int R, int RT, bool RE>
 __global__ __launch_bounds__(256 * R / RT) void apply_rows_kernel(ApplyGArgs a) {
   constexpr int NT = 256 * R / RT;  // threads: 256 columns x R / RT row groups
   extern __shared__ __align__(16) uint8_t smem[];
-  double2 *Ys = reinterpret_cast<double2 *>(smem);
   const int tix = xcd_tile(a.n_tiles);
   if (tix >= a.n_tiles) return;
   const Tile tl = a.tiles[tix];
-  const int b = tl.inst, r0 = tl.e0, rows = tl.e1 - tl.e0;
+  const int b = tl.inst;
   const InstDesc &d = a.inst[b];
   const int n = d.n;
   const Signature &sg = a.adjoint ? d.adj : d.fwd;
@@ -2137,135 +2298,17 @@ __global__ __launch_bounds__(256 * R / RT) void apply_rows_kernel(ApplyGArgs a) 
   const double *uq = a.u + (int64_t)b * a.n_ctrl * a.n_seg + (a.seg < 0 ? 0 : a.seg);
   const double2 *Yg = reinterpret_cast<const double2 *>(a.y) + d.rho_off;
   double2 *out = reinterpret_cast<double2 *>(a.out) + d.rho_off;
-  // LDS: the block's rows of y, then the row-side entries of its rows:
-  // D [R] | Oval [wo][R] | Jval [nc wc][R] (complex) | Ocol [wo][R] |
-  // Jcol [nc wc][R] (int)
-  const int ncw = op.nc * op.wc;
-  double2 *Rd = Ys + R * n, *Rov = Rd + R, *Rjv = Rov + op.wo * R;
-  int32_t *Roc = reinterpret_cast<int32_t *>(Rjv + ncw * R), *Rjc = Roc + op.wo * R;
-
-  for (int e = threadIdx.x; e < rows * n; e += NT) Ys[e] = Yg[(int64_t)r0 * n + e];
-  for (int e = threadIdx.x; e < (1 + op.wo + ncw) * R; e += NT) {
-    const int q = e / R, r = e - q * R;
-    if (r >= rows) continue;
-    if (q == 0) {
-      Rd[r] = op.D[r0 + r];
-    } else if (q <= op.wo) {
-      Rov[(q - 1) * R + r] = op.Oval[(q - 1) * n + r0 + r];
-      Roc[(q - 1) * R + r] = op.Ocol[(q - 1) * n + r0 + r];
-    } else {
-      const int k = q - 1 - op.wo;
-      Rjv[k * R + r] = op.Jval[k * n + r0 + r];
-      Rjc[k * R + r] = op.Jcol[k * n + r0 + r];
-    }
-  }
+  const RowBlock<R> k = carve_rows<R>(smem, op, tl.e0, tl.e1 - tl.e0);
+  stage_rows<R, NT>(k, op, Yg);
   __syncthreads();
-  // this thread's rows: rb + r, r < RT (the same for the whole wavefront)
+  // this thread's rows rb + r, r < RT (the same for the whole wavefront)
   const int rb = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 256) * RT);
-  const int jt = threadIdx.x & 255;
-  // element (c, j) of y for a source row c that is the same for all lanes:
-  // LDS inside the block, else a buffer load over this instance's n^2
-  // elements (a load kind of its own, so the two never merge into a flat
-  // access)
-  const __amdgpu_buffer_rsrc_t yrs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<double2 *>(Yg), 0, 16 * n * n, kBufferFlags);
-  auto Yrow = [&](int c, int j) {
-    if (c >= r0 && c < r0 + rows) return Ys[(c - r0) * n + j];
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(yrs, (uint32_t)(c * n + j) * 16u, 0, 0);
-    return __builtin_bit_cast(double2, v);
-  };
-  // acc += v * y and acc += conj(v) * y, exactly-zero parts skipped under RE
-  auto fma_v = [](double2 v, double2 y, double2 acc) {
-    if (RE) return make_double2(fma(-v.y, y.y, acc.x), fma(v.y, y.x, acc.y));
-    return cfma(v, y, acc);
-  };
-  auto fma_cv = [](double2 v, double2 y, double2 acc) {
-    if (RE) return make_double2(fma(v.y, y.y, acc.x), fma(-v.y, y.x, acc.y));
-    return cfma_conj(v, y, acc);
-  };
-
-  for (int j = jt; j < n; j += 256) {
-    double2 acc[RT], yv[RT];
-    const double2 dj = cconj(op.D[j]);
+  for (int j = (int)(threadIdx.x & 255); j < n; j += 256) {
+    double2 acc[RT];
+    rows_lindblad<R, RT, RE>(k, op, Yg, nb, uq, a.n_seg, rb, j, acc);
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-      if (rb + r < rows) acc[r] = cmul(cadd(Rd[rb + r], dj), Ys[(rb + r) * n + j]);
-    // A y: source rows Ocol[w][i]; the R gathers of a term are issued
-    // before its products
-    for (int w = 0; w < op.wo; ++w) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rb + r < rows) yv[r] = Yrow(Roc[w * R + rb + r], j);
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rb + r < rows) acc[r] = fma_v(Rov[w * R + rb + r], yv[r], acc[r]);
-    }
-    // y A^+: row i, columns Ocol[w][j]
-    for (int w = 0; w < op.wo; ++w) {
-      const int c = op.Ocol[w * n + j];
-      const double2 v = op.Oval[w * n + j];
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rb + r < rows) acc[r] = fma_cv(v, Ys[(rb + r) * n + c], acc[r]);
-    }
-    // control terms u_q (B_q y + y B_q^+), as a separate sum scaled by u_q
-    for (int q = 0; q < nb; ++q) {
-      const double u = uq[q * a.n_seg];
-      if (u == 0.0) continue;
-      const cptr<double> DBr = as_const2(op.DB + q * n), OBvr = as_const2(op.OBval + q * op.wb * n);
-      const cptr<int32_t> OBcr = as_const(op.OBcol + q * op.wb * n);
-      const double2 *OBv = op.OBval + q * op.wb * n;
-      const int32_t *OBc = op.OBcol + q * op.wb * n;
-      double2 t[RT];
-      const double2 dbj = cconj(op.DB[q * n + j]);
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rb + r < rows) t[r] = cmul(cadd(cld(DBr, r0 + rb + r), dbj), Ys[(rb + r) * n + j]);
-      for (int w = 0; w < op.wb; ++w) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          if (rb + r < rows) yv[r] = Yrow(OBcr[w * n + r0 + rb + r], j);
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          if (rb + r < rows) t[r] = fma_v(cld(OBvr, w * n + r0 + rb + r), yv[r], t[r]);
-      }
-      for (int w = 0; w < op.wb; ++w) {
-        const int c = OBc[w * n + j];
-        const double2 v = OBv[w * n + j];
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-          if (rb + r < rows) t[r] = fma_cv(v, Ys[(rb + r) * n + c], t[r]);
-      }
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rb + r < rows) acc[r] = caxpy(u, t[r], acc[r]);
-    }
-    // jumps C_k y C_k^+
-    for (int k = 0; k < op.nc; ++k) {
-      const int kw = k * op.wc * n;
-      for (int w = 0; w < op.wc; ++w)
-        for (int v = 0; v < op.wc; ++v) {
-          const double2 vj = op.Jval[kw + v * n + j];
-          const int cj = op.Jcol[kw + v * n + j];
-#pragma unroll
-          for (int r = 0; r < RT; ++r)
-            if (rb + r < rows) yv[r] = Yrow(Rjc[(k * op.wc + w) * R + rb + r], cj);
-#pragma unroll
-          for (int r = 0; r < RT; ++r)
-            if (rb + r < rows) {
-              const double2 vi = Rjv[(k * op.wc + w) * R + rb + r];
-              if (RE) {
-                const double p = vi.x * vj.x;
-                acc[r] = make_double2(fma(p, yv[r].x, acc[r].x), fma(p, yv[r].y, acc[r].y));
-              } else {
-                acc[r] = cfma(cmul(vi, cconj(vj)), yv[r], acc[r]);
-              }
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-      if (rb + r < rows) out[(int64_t)(r0 + rb + r) * n + j] = acc[r];
+      if (rb + r < k.rows) out[(int64_t)(k.r0 + rb + r) * n + j] = acc[r];
   }
 }
 
@@ -2436,6 +2479,71 @@ __global__ __launch_bounds__(T) void sdp_stage_kernel(StreamArgs a, int s) {
   }
   if (s == 6) {
     const double tot = block_sum<T>(part, sh);
+    if (threadIdx.x == 0) a.tile_part[tix] = tot;
+  }
+}
+
+// The same stage for batches of row-block tiles (every instance
+// 128 <= n <= 256, tiles of at most R whole rows): the stage input's rows
+// and their operator entries are staged in LDS and L(y_s) is evaluated by
+// rows_lindblad(), then every element of the tile continues as above.
+template <int R, int RT, bool RE>
+__global__ __launch_bounds__(256 * R / RT) void sdp_stage_rows_kernel(StreamArgs a, int s) {
+  constexpr int NT = 256 * R / RT;
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ double uq[kMaxWidth];
+  __shared__ double sh[NT / 64];
+  const int tix = xcd_tile(a.n_tiles);
+  if (tix >= a.n_tiles) return;
+  const int b = a.tiles[tix].inst;
+  const DpCtl c = a.ctl[b];
+  if (!c.active) return;
+  const TileCtx t = tile_ctx(a, tix, uq, c.seg);
+  double2 *rho = reinterpret_cast<double2 *>(a.rho) + t.base;
+  double2 *yb[2] = {reinterpret_cast<double2 *>(a.yb0) + t.base,
+                    reinterpret_cast<double2 *>(a.yb1) + t.base};
+  double2 *y5 = reinterpret_cast<double2 *>(a.y5) + t.base;
+  double2 *K = reinterpret_cast<double2 *>(a.K) + t.base;
+  const int64_t SE = a.state_elems;
+  const double2 *Yin = s == 0 ? rho : (s == 6 ? y5 : yb[(s + 1) & 1]);
+  double2 *Yout = s == 5 ? y5 : yb[s & 1];
+  const int n = t.n;
+  const bool need = s > 0 || c.need_k1;
+  const RowBlock<R> k = carve_rows<R>(smem, t.op, t.e0 / n, (t.e1 - t.e0) / n);
+  if (need) stage_rows<R, NT>(k, t.op, Yin);
+  __syncthreads();
+  const int rb = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 256) * RT);
+  double part = 0.0;
+  for (int j = (int)(threadIdx.x & 255); j < n; j += 256) {
+    double2 kv[RT];
+    if (need) rows_lindblad<R, RT, RE>(k, t.op, Yin, t.op.nb, uq, 1, rb, j, kv);
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      if (rb + r >= k.rows) continue;
+      const int e = (k.r0 + rb + r) * n + j;
+      double2 kk;
+      if (need) {
+        kk = kv[r];
+        K[s * SE + e] = kk;
+      } else {
+        kk = K[e];
+      }
+      if (s < 6) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int jj = 0; jj <= s; ++jj) acc = caxpy(kDpA[s + 1][jj], jj == s ? kk : K[jj * SE + e], acc);
+        Yout[e] = caxpy(c.h_try, acc, rho[e]);
+      } else {
+        double2 er = make_double2(0.0, 0.0);
+        for (int jj = 0; jj < 7; ++jj) er = caxpy(kDpE[jj], jj == 6 ? kk : K[jj * SE + e], er);
+        er = make_double2(c.h_try * er.x, c.h_try * er.y);
+        const double sc = a.atol + a.rtol * fmax(hypot(rho[e].x, rho[e].y), hypot(y5[e].x, y5[e].y));
+        const double q = hypot(er.x, er.y) / sc;
+        part += q * q;
+      }
+    }
+  }
+  if (s == 6) {
+    const double tot = block_sum<NT>(part, sh);
     if (threadIdx.x == 0) a.tile_part[tix] = tot;
   }
 }
@@ -2906,8 +3014,6 @@ extern "C" hipError_t lme_internal_launch_apply_global(const lme::ApplyGArgs *a,
   return hipGetLastError();
 }
 
-// rows per thread of the 16-row kernel
-constexpr int kRowsRT = 4;
 // Row-block streamed application: R = 16 rows per tile (n <= 256) or 4
 // (n <= 1024); lds = R * max n * 16 bytes.
 extern "C" hipError_t lme_internal_launch_apply_rows(int R, int re, const lme::ApplyGArgs *a,
@@ -2917,12 +3023,12 @@ extern "C" hipError_t lme_internal_launch_apply_rows(int R, int re, const lme::A
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(R == 16 ? 256 * 16 / kRowsRT : 256), lds, s, *a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(R == 16 ? 256 * 16 / lme::kRowsRT : 256), lds, s, *a);
     return hipGetLastError();
   };
   if (R == 16)
-    return re ? go(lme::apply_rows_kernel<16, kRowsRT, true>)
-              : go(lme::apply_rows_kernel<16, kRowsRT, false>);
+    return re ? go(lme::apply_rows_kernel<16, lme::kRowsRT, true>)
+              : go(lme::apply_rows_kernel<16, lme::kRowsRT, false>);
   if (R == 4) return re ? go(lme::apply_rows_kernel<4, 4, true>) : go(lme::apply_rows_kernel<4, 4, false>);
   return hipErrorInvalidValue;
 }
@@ -3032,6 +3138,29 @@ extern "C" hipError_t lme_internal_launch_sdp(int which, int arg, const lme::Str
     case 22: hipLaunchKernelGGL(srk_tail_kernel, dim3(1), dim3(1), 0, s, *a, arg); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Row-block stage kernel of the streamed adaptive stepper (16-row tiles):
+// prepare sets its dynamic LDS limit (outside any graph capture), launch
+// issues stage s.
+template <bool RE>
+static auto sdp_rows_kernel() {
+  return lme::sdp_stage_rows_kernel<16, lme::kRowsRT, RE>;
+}
+extern "C" hipError_t lme_internal_sdp_rows_prepare(int re, int lds) {
+  const void *k = re ? reinterpret_cast<const void *>(sdp_rows_kernel<true>())
+                     : reinterpret_cast<const void *>(sdp_rows_kernel<false>());
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+extern "C" hipError_t lme_internal_launch_sdp_rows(int s, int re, const lme::StreamArgs *a,
+                                                   int lds, hipStream_t st) {
+  const int grid = 8 * ((a->n_tiles + 7) / 8);
+  const dim3 block(256 * 16 / lme::kRowsRT);
+  if (re)
+    hipLaunchKernelGGL(sdp_rows_kernel<true>(), dim3(grid), block, lds, st, *a, s);
+  else
+    hipLaunchKernelGGL(sdp_rows_kernel<false>(), dim3(grid), block, lds, st, *a, s);
   return hipGetLastError();
 }
 
