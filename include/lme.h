@@ -135,18 +135,19 @@ typedef struct lme_options {
   int32_t nsteps;          /* RK4: equal steps from tlist[0] to tlist[n_t-1];
                               every output time must be on this grid          */
   int32_t block;           /* resident path: threads per workgroup; 0 = tuned
-                              default.  Row layout: 256, 512 or 1024.
-                              Column layout: 512 or 768                       */
+                              default.  RK4 row layout: 256, 512 or 1024;
+                              RK4 column layout: 512 or 768.  DOPRI5: 512, or
+                              1024 in the column layout                       */
   int32_t layout;          /* resident path, thread-to-element layout:
                               LME_LAYOUT_AUTO, LME_LAYOUT_ROW (any operator)
                               or LME_LAYOUT_COLUMN (monomial collapse
                               operators, at most 2 off-diagonal entries per
                               row of H, at most 3 collapse operators and 1
                               control term); both give identical results.
-                              DOPRI5 has both layouts at 512 threads (column:
-                              at most 16 rows per thread); AUTO takes the
-                              column layout there when 8 rows per thread
-                              suffice                                        */
+                              DOPRI5 has the row layout at 512 threads and
+                              the column layout at 1024 threads (4 rows per
+                              thread) or 512 (8 or 16); AUTO takes the column
+                              layout when 4 or 8 rows per thread suffice    */
   double rtol, atol;       /* DOPRI5: per-element tolerance
                               atol + rtol*max(|rho|, |rho_new|)               */
   double h0;               /* DOPRI5: first step; <= 0 selects it

@@ -1113,8 +1113,9 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   if (!std::isfinite(opt->h0) || !(opt->h_min >= 0.0) || !std::isfinite(opt->h_min))
     return fail(LME_EINVAL, "DOPRI5 needs a finite h0 and h_min >= 0");
   if (opt->max_steps < 1) return fail(LME_EINVAL, "DOPRI5 needs max_steps >= 1");
-  if (opt->block != 0 && opt->block != 512)
-    return fail(LME_EINVAL, "the adaptive stepper runs 512-thread workgroups");
+  if (opt->block != 0 && opt->block != 512 && opt->block != 1024)
+    return fail(LME_EINVAL, "the adaptive stepper runs 512-thread workgroups (1024 in the "
+                "column layout)");
   std::vector<double> stops;
   std::vector<int32_t> out_idx, seg;
   int rc = dp5_tables(h, n_t, tlist, &stops, &out_idx, &seg);
@@ -1132,17 +1133,22 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   bool streamed = opt->path == LME_PATH_STREAMED || !EPT;
   // column-owner resident kernel: the column-kernel shapes, up to 16 rows per
   // thread
+  // (1024 threads with 4 rows per thread, else 512 threads)
   int wo = 0, nc = 0, nb = 0, col_ept = 0;
+  auto col_T = [](int e) { return e == 4 ? 1024 : 512; };
   if (opt->layout != LME_LAYOUT_ROW && opt->path != LME_PATH_STREAMED &&
       column_eligible(h, &wo, &nc, &nb))
-    for (int e : {8, 16})
-      if (!col_ept && column_fits(h, 512, e, false)) col_ept = e;
+    for (int e : {4, 8, 16})
+      if (!col_ept && (opt->block == 0 || opt->block == col_T(e)) &&
+          column_fits(h, col_T(e), e, false))
+        col_ept = e;
   if (opt->layout == LME_LAYOUT_COLUMN && !col_ept)
     return fail(LME_ENOTSUP, "the batch has no column-owner adaptive kernel (operator shape, "
                 "dimension or path)");
-  // AUTO: the column kernel with 8 rows per thread (the 16-row variant keeps
-  // fewer operands in registers and is not faster than the row kernel)
-  if (opt->layout == LME_LAYOUT_AUTO && col_ept != 8) col_ept = 0;
+  // AUTO: the column kernel with 4 (1024 threads) or 8 rows per thread; the
+  // 16-row variant keeps fewer operands in registers and is not faster than
+  // the row kernel
+  if (opt->layout == LME_LAYOUT_AUTO && col_ept == 16) col_ept = 0;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((rc = ensure_device(h))) return rc;
@@ -1162,7 +1168,8 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   Plan *plan = nullptr;
   if (col_ept) {
     streamed = false;
-    if ((rc = plan_packs(h, 512, col_ept, 0, 512 * col_ept, 1, 1, &plan))) return rc;
+    if ((rc = plan_packs(h, col_T(col_ept), col_ept, 0, col_T(col_ept) * col_ept, 1, 1, &plan)))
+      return rc;
   } else if (!streamed) {
     rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan);
     if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)

@@ -2957,19 +2957,24 @@ extern "C" int lme_internal_dp5_extra_lds(int m) {
   return lme::dp_ctl_bytes(m) + lme::align16(16 * m);
 }
 
-// Column-owner resident Dormand-Prince: 512 threads, up to EPT rows per
-// thread, the column-kernel shapes.
+// Column-owner resident Dormand-Prince: 512 threads and up to EPT = 8 or 16
+// rows per thread, or 1024 threads and 4 rows (EPT = 4); the column-kernel
+// shapes.
 extern "C" hipError_t lme_internal_launch_dp5_col(int EPT, int wo, int nc, int nb, int re,
                                                   const lme::Dp5Args *a, int n_packs, int lds,
                                                   hipStream_t s) {
-#define LME_DC(E, W, K, B, R) \
-  if (EPT == E && wo == W && nc == K && nb == B && re == R) \
-    return launch_dp5_t<512, E, W, K, B, (R != 0), true>(*a, n_packs, lds, s);
+#define LME_DC(E, W, K, B, R)                                                  \
+  if (EPT == E && wo == W && nc == K && nb == B && re == R) {                  \
+    if constexpr (E == 4)                                                      \
+      return launch_dp5_t<1024, 4, W, K, B, (R != 0), true>(*a, n_packs, lds, s); \
+    else                                                                       \
+      return launch_dp5_t<512, E, W, K, B, (R != 0), true>(*a, n_packs, lds, s); \
+  }
 #define LME_DC_E(E)                                                                   \
   LME_DC(E, 1, 2, 0, 0) LME_DC(E, 1, 3, 0, 0) LME_DC(E, 2, 2, 0, 0) LME_DC(E, 1, 2, 1, 0) \
   LME_DC(E, 1, 3, 1, 0) LME_DC(E, 1, 2, 0, 1) LME_DC(E, 1, 3, 0, 1) LME_DC(E, 2, 2, 0, 1) \
   LME_DC(E, 1, 2, 1, 1) LME_DC(E, 1, 3, 1, 1)
-  LME_DC_E(8) LME_DC_E(16)
+  LME_DC_E(4) LME_DC_E(8) LME_DC_E(16)
 #undef LME_DC_E
 #undef LME_DC
   return hipErrorInvalidValue;
