@@ -29,9 +29,9 @@ METRIC = "instance-RK-steps/sec + HBM GB/s, batched vs plain, at 1e-10 trace dis
 # HBM bytes per launch of the timed kernels from the FETCH_SIZE / WRITE_SIZE passes
 # (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0), valid only for the kernel
 # source with this SHA-256; any other source reports null.
-TRAFFIC = {"sha256": "c89d20d2006c948c3bde024035eadf66dd010d8704272a12b545f5f0ffa4c5be",
-           "rk4_herm_kernel": 192.3e6 + 178.1e6, "rk4_colown_kernel": 216.5e6 + 232.6e6,
-           "apply_pipe_kernel": 184.5e6 + 158.4e6}
+TRAFFIC = {"sha256": "adfe07132281ffe00c470b5093e8a1bc1659f5343a2894d1cde781450b521c78",
+           "rk4_herm_kernel": 192.28e6 + 178.09e6, "rk4_colown_kernel": 216.85e6 + 233.11e6,
+           "apply_pipe_kernel": 184.45e6 + 158.35e6, "apply_rows_kernel": 75.39e6 + 67.11e6}
 
 
 def kernel_traffic(name):
@@ -182,6 +182,8 @@ def tfim_apply_bench(lme, systems, torch, reps=10):
         src = torch.empty_like(y)
         cus = timed(lambda: out.copy_(src))
         r["row_blocks"]["kernel"] = "apply_rows_kernel"
+        if n_inst == 64:
+            r["row_blocks"]["traffic"] = kernel_traffic("apply_rows_kernel")
         r["device_copy"] = {"us": cus, "GBs": nbytes / (cus * 1e-6) / 1e9}
         r["row_blocks"]["frac_of_copy"] = cus / r["row_blocks"]["us_per_apply"]
         res[f"tfim_8spin_x{n_inst}"] = r
@@ -255,12 +257,22 @@ def pmc_pass(lme, systems, torch):
         rc = lme.load().lme_apply(h._h, form, 0, 0.0, None, lme._ptr(rho0), lme._ptr(out),
                                   lme._stream_ptr(None))
         assert rc == 0
+    # the row-block application on 64 8-spin chains
+    wt = systems.tfim(n_inst=64)
+    ht = lme.Handle(wt.systems)
+    yt = ht.pack([s.rho0 for s in wt.systems], device="cuda:0")
+    yt.copy_(torch.randn_like(yt))
+    ot = torch.empty_like(yt)
+    rc = lme.load().lme_apply(ht._h, lme.LME_FORM_OPERATOR, 0, 0.0, None, lme._ptr(yt),
+                              lme._ptr(ot), lme._stream_ptr(None))
+    assert rc == 0
     src = torch.ones(32 * 2**20, dtype=torch.float64, device="cuda:0")   # 256 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"pmc_pass": "done", "copy_bytes_each_way": src.numel() * 8,
-                      "state_bytes": 16 * h.state_elems}), flush=True)
+                      "state_bytes": 16 * h.state_elems,
+                      "tfim_state_bytes": 16 * ht.state_elems}), flush=True)
 
 
 def main():
