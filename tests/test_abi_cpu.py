@@ -148,6 +148,26 @@ def test_evolve_validation_precedes_device_use():
         assert rc == lme.LME_EHIP, msg
 
 
+def test_dopri5_validation_precedes_device_use():
+    """Adaptive-stepper options and the layout/block combinations are checked
+    on the host, before any HIP call."""
+    h, w = _handle()
+    D = lme.LME_DOPRI5
+    tl = [0.0, 1.0]
+    assert _evolve_rc(h, tl, method=D, rtol=0.0)[0] == lme.LME_EINVAL
+    assert _evolve_rc(h, tl, method=D, atol=-1.0)[0] == lme.LME_EINVAL
+    assert _evolve_rc(h, tl, method=D, max_steps=0)[0] == lme.LME_EINVAL
+    assert _evolve_rc(h, tl, method=D, block=768)[0] == lme.LME_EINVAL
+    # a batch outside the column kernels' operator shapes
+    g = lme.Handle([S.random_system(6, n_c=2, density=0.9, seed=1)])
+    rc, msg = _evolve_rc(g, tl, method=D, layout=lme.LME_LAYOUT_COLUMN)
+    assert rc == lme.LME_ENOTSUP, msg
+    rc, msg = _evolve_rc(h, tl, method=D)
+    import torch
+    if not torch.cuda.is_available():
+        assert rc == lme.LME_EHIP, msg
+
+
 def test_evolve_grid_check_for_control_edges():
     w = S.jc_drive(n_inst=2, N=3, n_seg=3, t_end=1.0, steps_per_seg=2)
     h = lme.Handle(w.systems)
