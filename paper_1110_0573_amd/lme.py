@@ -304,6 +304,77 @@ class Handle:
         return out
 
 
+class _Spec:
+    """One system for :func:`evolve` (the attributes Handle reads)."""
+
+    def __init__(self, H0, C, E, H_ctrl=(), edges=None, u=None):
+        self.H0, self.C, self.E = H0, list(C), list(E)
+        self.H_ctrl, self.edges, self.u = list(H_ctrl), edges, u
+
+
+def evolve(H0, c_ops, rho0, tlist, e_ops, controls=None, method="rk4", nsteps=None,
+           rtol=1e-6, atol=None, hermitian=None, device="cuda"):
+    """Master-equation evolution of one system on the GPU, in the calling
+    convention of the paper's solver (Sec. 4: Hamiltonian, initial state, times,
+    collapse and expectation operators; tlist[0] is the initial time and is
+    part of the output).
+
+    H0, c_ops, e_ops: square matrices (NumPy or SciPy sparse).  rho0: a ket
+    (converted to |psi><psi|) or a density matrix.  controls: optional
+    (H_ctrl list, edges[n_seg + 1], u[n_ctrl][n_seg]) for piecewise-constant
+    u_j(t).  method "rk4" takes nsteps equal steps over [tlist[0], tlist[-1]]
+    (every output time on that grid); "dopri5" adapts its steps to rtol/atol
+    (atol defaults to 1e-3 rtol).  hermitian: use the Hermitian RK4 path
+    (default: whenever rho0 is Hermitian).
+
+    Returns expectation values [len(e_ops)][len(tlist)] (real for Hermitian
+    e_ops, complex otherwise); with no e_ops, the states rho(t) instead, as
+    an array [len(tlist)][n][n]."""
+    import torch
+
+    def m(a):
+        return sp.csr_matrix(a, dtype=np.complex128)
+
+    H0 = m(H0)
+    n = H0.shape[0]
+    r = np.asarray(rho0.toarray() if sp.issparse(rho0) else rho0, np.complex128)
+    if r.ndim == 1 or 1 in r.shape:
+        psi = r.reshape(-1)
+        r = np.outer(psi, psi.conj())
+    if r.shape != (n, n):
+        raise LmeError(LME_EINVAL, f"rho0 has shape {r.shape}, expected ({n}, {n})")
+    E = [m(e) for e in e_ops]
+    want_states = len(E) == 0
+    if want_states:  # the batch needs one expectation operator; its values are dropped
+        E = [sp.identity(n, dtype=np.complex128, format="csr")]
+    hc, edges, u = ((), None, None) if controls is None else controls
+    spec = _Spec(H0, [m(c) for c in c_ops], E, [m(x) for x in hc], edges,
+                 None if u is None else np.asarray(u, np.float64))
+    tlist = np.asarray(tlist, np.float64)
+    if method == "rk4" and nsteps is None:
+        raise LmeError(LME_EINVAL, "rk4 needs nsteps")
+    if hermitian is None:
+        hermitian = method == "rk4" and np.array_equal(r, r.conj().T)
+    h = Handle([spec])
+    try:
+        y = h.pack([r], device=device)
+        out = h.evolve(y, tlist, method=method, nsteps=nsteps or 0, rtol=rtol,
+                       atol=1e-3 * rtol if atol is None else atol, hermitian=bool(hermitian),
+                       want_states=want_states)
+        torch.cuda.synchronize()
+        st = int(out["status"].cpu().numpy()[0])
+        if st != 0:
+            raise LmeError(st, f"evolve: instance status {STATUS_NAMES.get(st, st)}")
+        if want_states:
+            return np.stack([h.unpack(out["states"][k])[0] for k in range(len(tlist))])
+        ex = out["expect"].cpu().numpy()[0]
+        herm = [abs(e - e.conj().T).max() == 0 if e.nnz else True for e in E]
+        return np.stack([ex[k].real if herm[k] else ex[k] for k in range(len(E))]) \
+            if all(herm) else ex
+    finally:
+        h.close()
+
+
 def _cost_grad(handle, rho0, O, u, t0, t1, nsteps, ckpt_every, stream=None):
     import torch
     dev = rho0.device
