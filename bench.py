@@ -212,8 +212,10 @@ def other_configs(lme, systems, torch):
     w = systems.jc_single()
     h = lme.Handle(w.systems)
     r0 = h.pack([s.rho0 for s in w.systems])
-    ms, _ = timed(lambda: h.evolve(r0, w.tlist, nsteps=w.nsteps))
-    res["jc_single_N10_rk4_2500"] = {"ms": ms, "instance_steps_per_s": w.nsteps / (ms * 1e-3)}
+    ms, _ = timed(lambda: h.evolve(r0, w.tlist, nsteps=w.nsteps, hermitian=True))
+    ms_full, _ = timed(lambda: h.evolve(r0, w.tlist, nsteps=w.nsteps))
+    res["jc_single_N10_rk4_2500"] = {"ms": ms, "instance_steps_per_s": w.nsteps / (ms * 1e-3),
+                                     "path": "hermitian", "full_path_ms": ms_full}
 
     w = systems.kerr_single()
     h = lme.Handle(w.systems)
