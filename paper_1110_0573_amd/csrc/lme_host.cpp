@@ -41,7 +41,7 @@ extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int herm, int wo, 
                                                      int lds, hipStream_t s);
 extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
 extern "C" int lme_internal_dp5_epts(int *ept, int cap);
-extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradArgs *a,
+extern "C" hipError_t lme_internal_launch_grad(int T, int EPT, int nq, const lme::GradArgs *a,
                                                int n_packs, int lds, hipStream_t s);
 extern "C" int lme_internal_dp5_extra_lds(int m);
 extern "C" hipError_t lme_internal_launch_dp5_col(int EPT, int wo, int nc, int nb, int re,
@@ -1882,9 +1882,15 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
   if (rc) return rc;
   int max_n2 = 0;
   for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
-  int EPT = 0;
-  for (int e : {1, 2, 4, 8})
-    if (!EPT && 512 * e >= max_n2) EPT = e;
+  // 1024 threads (at most 4 elements each: twice the wavefronts of the
+  // 512-thread configuration at the same packing), else 512 x 8
+  int T = 1024, EPT = 0;
+  for (int e : {1, 2, 4})
+    if (!EPT && 1024 * e >= max_n2) EPT = e;
+  if (!EPT && 512 * 8 >= max_n2) {
+    T = 512;
+    EPT = 8;
+  }
   if (!EPT)
     return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the gradient workgroup",
                 max_n2);
@@ -1905,7 +1911,7 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
     h->d_ckpt.bytes = ck_bytes + sb_bytes;
   }
   Plan *plan;
-  if ((rc = plan_packs(h, 512, EPT, 2, 512 * EPT, 0, 2, &plan))) return rc;
+  if ((rc = plan_packs(h, T, EPT, 2, T * EPT, 0, 2, &plan))) return rc;
   lme::GradArgs a;
   std::memset(&a, 0, sizeof a);
   a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
@@ -1927,7 +1933,7 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
   a.stages = reinterpret_cast<double *>(static_cast<uint8_t *>(h->d_ckpt.p) + ck_bytes);
   a.cost = cost_dev;
   a.grad = grad_dev;
-  hipError_t e = lme_internal_launch_grad(EPT, h->n_ctrl, &a, (int)plan->packs.size(),
+  hipError_t e = lme_internal_launch_grad(T, EPT, h->n_ctrl, &a, (int)plan->packs.size(),
                                           plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch gradient");
   return LME_OK;

@@ -3002,13 +3002,16 @@ static hipError_t launch_grad_t(const lme::GradArgs &a, int n_packs, int lds, hi
   return hipGetLastError();
 }
 
-// Gradient kernel: 512 threads, EPT in {1, 2, 4, 8}, 1 or 2 control terms.
-extern "C" hipError_t lme_internal_launch_grad(int EPT, int nq, const lme::GradArgs *a,
+// Gradient kernel: T = 512 threads with EPT in {1, 2, 4, 8}, or T = 1024 with
+// EPT in {1, 2, 4}; 1 or 2 control terms.
+extern "C" hipError_t lme_internal_launch_grad(int T, int EPT, int nq, const lme::GradArgs *a,
                                                int n_packs, int lds, hipStream_t s) {
-#define LME_G(E, Q) \
-  if (EPT == E && nq == Q) return launch_grad_t<512, E, Q>(*a, n_packs, lds, s);
-  LME_G(1, 1) LME_G(2, 1) LME_G(4, 1) LME_G(8, 1)
-  LME_G(1, 2) LME_G(2, 2) LME_G(4, 2) LME_G(8, 2)
+#define LME_G(TT, E, Q) \
+  if (T == TT && EPT == E && nq == Q) return launch_grad_t<TT, E, Q>(*a, n_packs, lds, s);
+  LME_G(512, 1, 1) LME_G(512, 2, 1) LME_G(512, 4, 1) LME_G(512, 8, 1)
+  LME_G(512, 1, 2) LME_G(512, 2, 2) LME_G(512, 4, 2) LME_G(512, 8, 2)
+  LME_G(1024, 1, 1) LME_G(1024, 2, 1) LME_G(1024, 4, 1)
+  LME_G(1024, 1, 2) LME_G(1024, 2, 2) LME_G(1024, 4, 2)
 #undef LME_G
   return hipErrorInvalidValue;
 }
