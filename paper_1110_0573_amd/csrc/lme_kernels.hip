@@ -2281,8 +2281,11 @@ __device__ __forceinline__ void rows_lindblad(const RowBlock<R> &k, const OpView
   }
 }
 
+// Two workgroups per CU (8 wavefronts per SIMD, at most 64 VGPRs): the
+// kernel waits on its remote-row loads, and the extra wavefronts hide that
+// latency better than the registers the cap spills cost.
 template <int R, int RT, bool RE>
-__global__ __launch_bounds__(256 * R / RT) void apply_rows_kernel(ApplyGArgs a) {
+__global__ __launch_bounds__(256 * R / RT, 8) void apply_rows_kernel(ApplyGArgs a) {
   constexpr int NT = 256 * R / RT;  // threads: 256 columns x R / RT row groups
   extern __shared__ __align__(16) uint8_t smem[];
   const int tix = xcd_tile(a.n_tiles);
@@ -2488,7 +2491,7 @@ __global__ __launch_bounds__(T) void sdp_stage_kernel(StreamArgs a, int s) {
 // and their operator entries are staged in LDS and L(y_s) is evaluated by
 // rows_lindblad(), then every element of the tile continues as above.
 template <int R, int RT, bool RE>
-__global__ __launch_bounds__(256 * R / RT) void sdp_stage_rows_kernel(StreamArgs a, int s) {
+__global__ __launch_bounds__(256 * R / RT, 8) void sdp_stage_rows_kernel(StreamArgs a, int s) {
   constexpr int NT = 256 * R / RT;
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ double uq[kMaxWidth];
