@@ -29,9 +29,9 @@ METRIC = "instance-RK-steps/sec + HBM GB/s, batched vs plain, at 1e-10 trace dis
 # HBM bytes per launch of the timed kernels from the FETCH_SIZE / WRITE_SIZE passes
 # (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0), valid only for the kernel
 # source with this SHA-256; any other source reports null.
-TRAFFIC = {"sha256": "d2e79aa19a27e75f3d4fd3358b2732ffd4baf86386af4ca0e5c76b7cc92b6310",
-           "rk4_herm_kernel": 192.39e6 + 178.10e6, "rk4_colown_kernel": 216.92e6 + 232.83e6,
-           "apply_pipe_kernel": 184.47e6 + 158.35e6, "apply_rows_kernel": 75.39e6 + 67.11e6}
+TRAFFIC = {"sha256": "71c744362e636d2966926a52a3682b95e02c8af5c91c6a2710668fd19ec7efed",
+           "rk4_herm_kernel": 192.67e6 + 178.09e6, "rk4_colown_kernel": 216.76e6 + 232.88e6,
+           "apply_pipe_kernel": 184.50e6 + 158.35e6, "apply_rows_kernel": 154.10e6 + 104.86e6}
 
 
 def kernel_traffic(name):
