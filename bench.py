@@ -29,9 +29,9 @@ METRIC = "instance-RK-steps/sec + HBM GB/s, batched vs plain, at 1e-10 trace dis
 # HBM bytes per launch of the timed kernels from the FETCH_SIZE / WRITE_SIZE passes
 # (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0), valid only for the kernel
 # source with this SHA-256; any other source reports null.
-TRAFFIC = {"sha256": "71c744362e636d2966926a52a3682b95e02c8af5c91c6a2710668fd19ec7efed",
-           "rk4_herm_kernel": 192.67e6 + 178.09e6, "rk4_colown_kernel": 216.76e6 + 232.88e6,
-           "apply_pipe_kernel": 184.50e6 + 158.35e6, "apply_rows_kernel": 154.10e6 + 104.86e6}
+TRAFFIC = {"sha256": "987fbade1ff7cd2ae172481d8a87eb7961fc72077c29043a6429fa7497858b26",
+           "rk4_herm_kernel": 192.63e6 + 178.07e6, "rk4_colown_kernel": 217.03e6 + 233.12e6,
+           "apply_pipe_kernel": 184.46e6 + 158.35e6, "apply_rows_kernel": 154.16e6 + 104.86e6}
 
 
 def kernel_traffic(name):

@@ -827,7 +827,11 @@ __global__ __launch_bounds__(T) void rk4_herm_kernel(Rk4Args a) {
   int next_out = 0;
   const double h = a.h;
   for (int st = 0;; ++st) {
+    // an output step leaves rho, the first stage's input, in LDS: without
+    // control terms that stage then needs neither its store nor its barriers
+    bool staged = false;
     while (next_out < a.n_t && a.out_step[next_out] == st) {
+      staged = true;
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < EPT; ++r)
@@ -853,22 +857,24 @@ __global__ __launch_bounds__(T) void rk4_herm_kernel(Rk4Args a) {
     for (int stage = 0; stage < 4; ++stage) {
       const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
       const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
-      __syncthreads();
-      if (stage == 0 && NB > 0) {
-        const int seg = a.seg_of_step[st];
-        for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
-          const int bb = idx / pk.nb, q = idx - bb * pk.nb;
-          L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+      if (!(NB == 0 && stage == 0 && staged)) {
+        __syncthreads();
+        if (stage == 0 && NB > 0) {
+          const int seg = a.seg_of_step[st];
+          for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+            const int bb = idx / pk.nb, q = idx - bb * pk.nb;
+            L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+          }
         }
-      }
 #pragma unroll
-      for (int r = 0; r < EPT; ++r)
-        if (r < nown) {
-          uint32_t p = pos[r];
-          asm volatile("" : "+v"(p));
-          put(p, yn[r]);
-        }
-      __syncthreads();
+        for (int r = 0; r < EPT; ++r)
+          if (r < nown) {
+            uint32_t p = pos[r];
+            asm volatile("" : "+v"(p));
+            put(p, yn[r]);
+          }
+        __syncthreads();
+      }
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
         if (r < ept) {
@@ -951,7 +957,11 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
   int next_out = 0;
   const double h = a.h;
   for (int st = 0;; ++st) {
+    // an output step leaves rho, the first stage's input, in LDS: without
+    // control terms that stage then needs neither its store nor its barriers
+    bool staged = false;
     while (next_out < a.n_t && a.out_step[next_out] == st) {
+      staged = true;
       __syncthreads();
       int gg = g;
       asm volatile("" : "+v"(gg));
@@ -978,20 +988,22 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
     for (int stage = 0; stage < 4; ++stage) {
       const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
       const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
-      __syncthreads();
-      if (stage == 0 && NB > 0) {
-        const int seg = a.seg_of_step[st];
-        for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
-          const int bb = idx / pk.nb, q = idx - bb * pk.nb;
-          L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
-        }
-      }
       int gg = g;
       asm volatile("" : "+v"(gg));
+      if (!(NB == 0 && stage == 0 && staged)) {
+        __syncthreads();
+        if (stage == 0 && NB > 0) {
+          const int seg = a.seg_of_step[st];
+          for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+            const int bb = idx / pk.nb, q = idx - bb * pk.nb;
+            L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+          }
+        }
 #pragma unroll
-      for (int r = 0; r < EPT; ++r)
-        if (owns(gg, r)) Yb[mul24(row_of(gg, r), n) + j] = yn[r];
-      __syncthreads();
+        for (int r = 0; r < EPT; ++r)
+          if (owns(gg, r)) Yb[mul24(row_of(gg, r), n) + j] = yn[r];
+        __syncthreads();
+      }
 #pragma unroll
       for (int r = 0; r < EPT; ++r) {
         if (r < ept) {
