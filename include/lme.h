@@ -89,7 +89,9 @@ typedef enum lme_layout_kind {
 /* Form of the Liouvillian application used by lme_apply. */
 typedef enum lme_form {
   LME_FORM_OPERATOR = 0,   /* sparse H, C_k applied to the dense n x n matrix;
-                              stage input staged in LDS when it fits          */
+                              stage input staged in LDS: whole instances when
+                              they fit a workgroup, else blocks of rows (every
+                              instance 128 <= n <= 1024), else read from HBM */
   LME_FORM_SUPEROP = 1,    /* explicit n^2 x n^2 CSR superoperator SpMV       */
   LME_FORM_OPERATOR_STREAMED = 2  /* operator form read straight from HBM     */
 } lme_form;
