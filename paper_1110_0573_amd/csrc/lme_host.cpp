@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <queue>
 #include <memory>
 #include <new>
 #include <string>
@@ -704,10 +705,72 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
       p->max_lds = std::max(p->max_lds, pk.lds_bytes);
     }
   }
-  // largest work first: the hardware dispatches workgroups roughly in order
-  std::stable_sort(p->packs.begin(), p->packs.end(), [](const PackDesc &a, const PackDesc &b) {
-    return (int64_t)a.m * a.n * a.n > (int64_t)b.m * b.n * b.n;
-  });
+  // longest first (the hardware hands workgroups to free CUs roughly in
+  // order, so this is a longest-processing-time schedule): a column-layout
+  // pack takes time in proportion to its rows per thread, a row-layout pack
+  // to its elements
+  auto longest_first = [&]() {
+    std::stable_sort(p->packs.begin(), p->packs.end(), [](const PackDesc &a, const PackDesc &b) {
+      if (a.ept != b.ept) return a.ept > b.ept;
+      return (int64_t)a.m * a.n * a.n > (int64_t)b.m * b.n * b.n;
+    });
+  };
+  longest_first();
+  // Column layouts, one workgroup per CU: while the pack that finishes last
+  // in that schedule holds several instances and half of them fit more
+  // threads per column (fewer rows per thread), split it in two.  Packing
+  // changes no result bit.
+  int cus = 0;
+  if (column >= 1 && column <= 2 &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+      cus > 0) {
+    for (int iter = 0; iter < 4 * cus; ++iter) {
+      std::priority_queue<std::pair<int64_t, int>, std::vector<std::pair<int64_t, int>>,
+                          std::greater<std::pair<int64_t, int>>> free_at;
+      for (int c = 0; c < cus; ++c) free_at.push({0, c});
+      int64_t makespan = 0;
+      int last = -1;
+      for (int q = 0; q < (int)p->packs.size(); ++q) {
+        auto top = free_at.top();
+        free_at.pop();
+        const int64_t end = top.first + p->packs[q].ept;
+        if (end >= makespan) {
+          makespan = end;
+          last = q;
+        }
+        free_at.push({end, top.second});
+      }
+      if (last < 0) break;
+      PackDesc pk = p->packs[last];
+      if (pk.m < 2) break;
+      const int R = column == 2 ? pk.n / 2 + 1 : pk.n;
+      const int m1 = (pk.m + 1) / 2, m2 = pk.m - m1;
+      const int G1 = std::min(R, T / (m1 * pk.n));
+      const int ept1 = (R + G1 - 1) / G1;
+      if (ept1 >= pk.ept) break;
+      const int G2 = std::min(R, T / (m2 * pk.n));
+      PackDesc a = pk, b = pk;
+      a.m = m1;
+      a.G = G1;
+      a.ept = ept1;
+      a.lds_bytes = pack_lds(pk.n, m1, pk.blob_bytes, pk.nb);
+      b.first = pk.first + m1;
+      b.m = m2;
+      b.G = G2;
+      b.ept = (R + G2 - 1) / G2;
+      b.lds_bytes = pack_lds(pk.n, m2, pk.blob_bytes, pk.nb);
+      p->packs[last] = a;
+      p->packs.push_back(b);
+      longest_first();
+    }
+    for (const PackDesc &q : p->packs) {  // what the column kernels assume
+      const int R = column == 2 ? q.n / 2 + 1 : q.n;
+      if (q.m < 1 || (int64_t)q.m * q.n * q.G > T || q.G > R || q.ept > EPT ||
+          q.ept != (R + q.G - 1) / q.G)
+        return fail(LME_EINVAL, "internal: inconsistent pack (n %d, m %d, G %d, rows %d)", q.n,
+                    q.m, q.G, q.ept);
+    }
+  }
   int rc;
   if ((rc = p->d_packs.upload(p->packs.data(), p->packs.size() * sizeof(PackDesc), "packs"))) return rc;
   if ((rc = p->d_order.upload(p->order.data(), p->order.size() * sizeof(int32_t), "order"))) return rc;
