@@ -30,8 +30,8 @@ METRIC = "instance-RK-steps/sec + HBM GB/s, batched vs plain, at 1e-10 trace dis
 # (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0), valid only for the kernel
 # source with this SHA-256; any other source reports null.
 TRAFFIC = {"sha256": "987fbade1ff7cd2ae172481d8a87eb7961fc72077c29043a6429fa7497858b26",
-           "rk4_herm_kernel": 192.63e6 + 178.07e6, "rk4_colown_kernel": 217.03e6 + 233.12e6,
-           "apply_pipe_kernel": 184.46e6 + 158.35e6, "apply_rows_kernel": 154.16e6 + 104.86e6}
+           "rk4_herm_kernel": 192.59e6 + 178.17e6, "rk4_colown_kernel": 217.17e6 + 233.98e6,
+           "apply_pipe_kernel": 184.46e6 + 158.35e6, "apply_rows_kernel": 154.71e6 + 104.86e6}
 
 
 def kernel_traffic(name):
