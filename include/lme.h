@@ -5,7 +5,7 @@
  *   Sec. 3.1, Eq. (master_equation), hbar = 1:
  *     drho/dt = L(t) rho = -i[H(t), rho]
  *               + sum_k ( C_k rho C_k^+ - 1/2 rho C_k^+ C_k - 1/2 C_k^+ C_k rho )
- *   with H(t) = H0 + sum_j u_j(t) H_j (Sec. 4.6 gives a time-dependent
+ *   with H(t) = H0 + sum_j u_j(t) H_j (Sec. 4.4 gives a time-dependent
  *   Hamiltonian as constant operators times scalar functions of time; here
  *   the u_j are piecewise constant on a fixed set of segment edges).
  *   Sec. 4 (odesolve): the solver returns expectation values Tr(E rho(t)) at
@@ -177,7 +177,10 @@ typedef struct lme_options {
  * rtol 1e-6, atol 1e-9, h0 0, h_min 0, max_steps 10^7, hermitian 0. */
 void lme_default_options(lme_options *opt);
 
-/* Create a handle for a batch of n_inst independent systems.
+/* Create a handle for a batch of n_inst independent systems (Sec. 3.1,
+ * Eq. (master_equation): each system is its Hamiltonian, its collapse
+ * operators C_n = sqrt(gamma_n) A_n and, as in the solver call of Sec. 4,
+ * the operators whose expectation values are returned).
  *   inst[n_inst]: the systems (host, copied);
  *   n_ctrl, n_e: batch-wide counts of control and expectation operators;
  *   seg: control segments (NULL or n_seg == 0 when n_ctrl == 0);
@@ -192,7 +195,10 @@ int lme_create_batch(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
                      int32_t n_e, const lme_segments *seg, const double *u_host,
                      lme_handle *out);
 
-/* Single-instance form of lme_create_batch:
+/* Single-instance form of lme_create_batch (Sec. 3.1, Eq.
+ * (master_equation); the argument order follows the solver call of Sec. 4:
+ * Hamiltonian, its time-dependent terms, collapse operators, expectation
+ * operators):
  *   lme_create(H0, {H_j}, segments + amplitudes, {C_k}, {E_m}). */
 int lme_create(const lme_csr *H0, int32_t n_ctrl, const lme_csr *H_ctrl,
                const lme_segments *seg, const double *u_host, int32_t n_c,

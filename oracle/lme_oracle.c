@@ -12,7 +12,7 @@
  *   Sec. 3.1, Eq. (master_equation): the right-hand side
  *       drho/dt = -i[H(t), rho] + sum_n ( C_n rho C_n^+ - 1/2 rho C_n^+ C_n
  *                                                    - 1/2 C_n^+ C_n rho ).
- *   Sec. 4.6 (Landau-Zener): a time-dependent Hamiltonian given as constant
+ *   Sec. 4.4 (Landau-Zener): a time-dependent Hamiltonian given as constant
  *       operators times scalar functions of time; here H0 + sum_j u_j(t) H_j
  *       with u_j piecewise constant.
  *   Sec. 4 (odesolve): expectation values Tr(E rho) at each output time,

@@ -10,7 +10,7 @@
  * the dynamics of open quantum systems" (arXiv:1110.0573).
  *   - Lindblad equation: Sec. 3.1, Eq. (master_equation), hbar = 1 (Sec. 2,
  *     Eq. (twolevel) convention), C_n = sqrt(gamma_n) A_n.
- *   - Time-dependent Hamiltonian as a sum of terms: Sec. 4.6 (Landau-Zener
+ *   - Time-dependent Hamiltonian as a sum of terms: Sec. 4.4 (Landau-Zener
  *     callback H0 + t*H1), generalised here to H0 + sum_j u_j(t) H_j with
  *     piecewise-constant u_j.
  *   - Expectation values at the output times: Sec. 4 (odesolve with e_ops).

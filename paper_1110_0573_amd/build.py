@@ -1,9 +1,13 @@
 """Builds liblme.so (gfx950) in-tree with hipcc.
 
-Run ``python -m paper_1110_0573_amd.build`` or call :func:`build`.
+Run ``python -m paper_1110_0573_amd.build`` or call :func:`build`.  Every
+source is compiled (in parallel, one hipcc process per file) and linked;
+``--incremental`` (command line only) recompiles just the sources newer than
+their objects, for quick rebuilds while editing.
 """
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
@@ -11,8 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblme.so")
-SOURCES = ["lme_host.cpp", "lme_kernels.hip"]
 ARCH = "gfx950"
 
 # hipcc flags: gfx950 only; packed-FP32 instruction selection switched off.
@@ -23,29 +27,46 @@ HIP_FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra: list[str] | None = None) -> str:
+def sources() -> list[str]:
+    """Every C++ / HIP source of the library."""
+    return sorted(glob.glob(os.path.join(CSRC, "*.cpp")) + glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
+def build(verbose: bool = False, extra: list[str] | None = None,
+          incremental: bool = False) -> str:
     """Compiles every source and links liblme.so; returns its path."""
-    objs = []
+    os.makedirs(OBJDIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
+    procs, objs = [], []
+    for src in sources():
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+        objs.append(obj)
+        if incremental and not _stale(src, obj):
+            continue
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc] + HIP_FLAGS + (extra or []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + HIP_FLAGS + (extra or []) + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        procs.append((src, subprocess.Popen(cmd)))
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    for o in objs:
-        os.remove(o)
     return LIB
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)

@@ -1312,6 +1312,8 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     return fail(LME_EINVAL, "block must be 0, 256, 512, 768 or 1024");
   if (opt->hermitian != 0 && opt->hermitian != 1)
     return fail(LME_EINVAL, "hermitian must be 0 or 1");
+  if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
+    return fail(LME_EINVAL, "unknown layout %d", opt->layout);
   if (opt->method == LME_DOPRI5)
     return evolve_dp5(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
                       counts_dev, status_dev, stream);
@@ -1321,8 +1323,6 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   const double hstep = n_t > 1 ? (tlist[n_t - 1] - tlist[0]) / nsteps : 0.0;
   std::vector<int32_t> tab;
   if ((rc = rk4_tables(h, n_t, tlist, nsteps, hstep, &tab))) return rc;
-  if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
-    return fail(LME_EINVAL, "unknown layout %d", opt->layout);
   lme_options tuned = *opt;  // tuned defaults fill the fields left open
   const bool herm = opt->hermitian == 1;
   const int tl_layout = herm ? h->tuning.herm_layout : h->tuning.rk4_layout;

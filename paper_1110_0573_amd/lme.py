@@ -159,6 +159,28 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _check_tensor(t, dtype, numel, what, optional=False):
+    """Raises LmeError(LME_EINVAL) unless ``t`` is a contiguous device tensor
+    of ``dtype`` with exactly ``numel`` elements: the library cannot see the
+    size of a device buffer, so every buffer is checked here before its
+    pointer crosses the C ABI."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise LmeError(LME_EINVAL, f"{what} is missing")
+    if not isinstance(t, torch.Tensor):
+        raise LmeError(LME_EINVAL, f"{what} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise LmeError(LME_EINVAL, f"{what} has dtype {t.dtype}, expected {dtype}")
+    if t.numel() != numel:
+        raise LmeError(LME_EINVAL, f"{what} has {t.numel()} elements, expected {numel}")
+    if not t.is_contiguous():
+        raise LmeError(LME_EINVAL, f"{what} must be contiguous")
+    if not t.is_cuda:
+        raise LmeError(LME_EINVAL, f"{what} must be a device tensor, got device {t.device}")
+
+
 class Handle:
     """A batch of systems uploaded to the current GPU (lme_create_batch).
 
@@ -224,6 +246,18 @@ class Handle:
         except Exception:
             pass
 
+    # -- argument checks (before any pointer reaches the C ABI) ---------------
+    def _check_state(self, t, what):
+        import torch
+        _check_tensor(t, torch.complex128, self.state_elems, what)
+
+    def _check_u(self, u):
+        import torch
+        if u is not None and self.n_ctrl * self.n_seg == 0:
+            raise LmeError(LME_EINVAL, "u given but the batch has no control segments")
+        _check_tensor(u, torch.float64, self.n_inst * self.n_ctrl * self.n_seg, "u",
+                      optional=True)
+
     # -- packed state helpers (marshalling only) ------------------------------
     def pack(self, mats, device="cuda"):
         import torch
@@ -250,6 +284,8 @@ class Handle:
         hermitian: rho0 is Hermitian (options.hermitian).
         Returns a dict of device tensors (expect, states, rho, counts, status)."""
         import torch
+        self._check_state(rho0, "rho0")
+        self._check_u(u)
         dev = rho0.device
         tl = np.ascontiguousarray(tlist, np.float64)
         n_t = len(tl)
@@ -276,6 +312,7 @@ class Handle:
 
     def autotune(self, rho0, nsteps, hermitian=False, stream=None):
         """lme_autotune: picks the fastest schedule for this batch; returns it."""
+        self._check_state(rho0, "rho0")
         t = Tuning()
         opt = default_options(method=LME_RK4, nsteps=int(nsteps),
                               hermitian=1 if hermitian else 0)
@@ -297,7 +334,9 @@ class Handle:
     def apply(self, y, t=0.0, adjoint=False, form=LME_FORM_OPERATOR, u=None, stream=None):
         """out = L(t) y (or L^+ y) for every instance of the packed batch."""
         import torch
-        out = torch.empty_like(y)
+        self._check_state(y, "y")
+        self._check_u(u)
+        out = torch.empty(self.state_elems, dtype=torch.complex128, device=y.device)
         rc = load().lme_apply(self._h, form, 1 if adjoint else 0, float(t), _ptr(u), _ptr(y),
                               _ptr(out), _stream_ptr(stream))
         _check(rc, "lme_apply")
@@ -377,6 +416,9 @@ def evolve(H0, c_ops, rho0, tlist, e_ops, controls=None, method="rk4", nsteps=No
 
 def _cost_grad(handle, rho0, O, u, t0, t1, nsteps, ckpt_every, stream=None):
     import torch
+    handle._check_state(rho0, "rho0")
+    handle._check_state(O, "O")
+    handle._check_u(u)
     dev = rho0.device
     cost = torch.empty(handle.n_inst, dtype=torch.float64, device=dev)
     grad = torch.empty((handle.n_inst, handle.n_ctrl, handle.n_seg), dtype=torch.float64,
@@ -421,6 +463,9 @@ def _cost_function():
 def expectation_cost(u, handle, rho0, O, t0, t1, nsteps, ckpt_every=10):
     """Differentiable J_b(u) = Re Tr(O_b rho_b(t1)) (torch.autograd.Function).
     u: float64 device tensor [n_inst, n_ctrl, n_seg]; returns [n_inst]."""
+    import torch
+    _check_tensor(u.detach().contiguous() if isinstance(u, torch.Tensor) else u,
+                  torch.float64, handle.n_inst * handle.n_ctrl * handle.n_seg, "u")
     return _cost_function().apply(u, handle, rho0, O, t0, t1, nsteps, ckpt_every)
 
 

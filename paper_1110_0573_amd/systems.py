@@ -291,7 +291,7 @@ def tfim(n_inst=64, seed=5, M=8, t_end=20.0, n_out=201):
 # --------------------------------------------------------------------------
 
 def damped_cavity(N=5, kappa=1.0 / 0.129, n_th=0.0, n0=1):
-    """Cavity H = a^+a with thermal damping (paper Sec. 4.2, Fig. 4 system)."""
+    """Cavity H = a^+a with thermal damping (paper Sec. 3.2 example, Fig. 4)."""
     a = destroy(N)
     ad = dag(a)
     C = [tidy(np.sqrt(kappa * (1 + n_th)) * a)]
@@ -299,23 +299,6 @@ def damped_cavity(N=5, kappa=1.0 / 0.129, n_th=0.0, n0=1):
         C.append(tidy(np.sqrt(kappa * n_th) * ad))
     return System(tidy(ad @ a), C, [tidy(ad @ a)], ket2dm(ket(N, n0)),
                   meta=dict(kappa=kappa, n_th=n_th))
-
-
-def iswap_system(g=TWO_PI, g1=0.75, g2=0.05, n_th=0.75):
-    """Dissipative iSWAP gate (paper Sec. 4.3): H = g (sx sx + sy sy), relaxation,
-    thermal excitation and dephasing on both qubits; psi0 = |e g>.
-    Uses the paper's qubit tensor order (qubit 1 first)."""
-    H = g * (tensor(sigmax(), sigmax()) + tensor(sigmay(), sigmay()))
-    sm1, sz1 = tensor(sigmam(), qeye(2)), tensor(sigmaz(), qeye(2))
-    sm2, sz2 = tensor(qeye(2), sigmam()), tensor(qeye(2), sigmaz())
-    C = []
-    for sm, sz in ((sm1, sz1), (sm2, sz2)):
-        C.append(tidy(np.sqrt(g1 * (1 + n_th)) * sm))
-        C.append(tidy(np.sqrt(g1 * n_th) * dag(sm)))
-        C.append(tidy(np.sqrt(g2) * sz))
-    psi0 = np.kron(ket(2, 1), ket(2, 0))
-    return System(tidy(H), C, [tidy(dag(sm1) @ sm1), tidy(dag(sm2) @ sm2)],
-                  ket2dm(psi0), meta=dict(g=g, g1=g1, g2=g2, n_th=n_th, psi0=psi0))
 
 
 def random_system(n, n_c=2, n_ctrl=0, n_e=2, density=0.4, seed=0, n_seg=0,

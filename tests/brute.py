@@ -99,3 +99,23 @@ def jc_single_excitation(t, wc, wa, g, kappa, gamma):
 
 def fact(k):
     return float(factorial(k))
+
+
+def dopri5_error_map(S, h):
+    """Embedded error estimate of one Dormand-Prince step on a linear constant
+    ODE: y5 - y4 = E(hS) y with E = R - Rhat, where R is the fifth-order
+    stability function above and Rhat that of the embedded fourth-order
+    solution (with the first-same-as-last seventh stage),
+    Rhat(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 + 1097 z^5/120000
+              + 161 z^6/120000 + z^7/24000,
+    both obtained from the published Dormand & Prince (1980) tableau as
+    1 + sum_k z^k b^T A^(k-1) 1.  Written as the difference polynomial
+    E(z) = (-97 z^5 + 39 z^6 - 5 z^7) / 120000 to avoid cancellation."""
+    Z = h * S
+    Z5 = np.linalg.matrix_power(Z, 5)
+    return (-97.0 * Z5 + 39.0 * Z5 @ Z - 5.0 * Z5 @ Z @ Z) / 120000.0
+
+
+def rms_scaled(v, sc):
+    """RMS over the complex moduli of v / sc (the adaptive error norm)."""
+    return float(np.sqrt(np.mean((np.abs(v) / sc) ** 2)))

@@ -184,3 +184,56 @@ def test_null_handle_is_rejected():
                           C.c_void_p(16), None, None, None, None, None, None, None) == lme.LME_EINVAL
     assert lib.lme_apply(None, 0, 0, 0.0, None, C.c_void_p(16), C.c_void_p(32), None) == lme.LME_EINVAL
     assert lib.lme_layout(None, None, None, None, None) == lme.LME_EINVAL
+
+
+def test_dopri5_rejects_unknown_layout_before_device_use():
+    h, w = _handle()
+    for bad in (-1, 3):
+        rc, msg = _evolve_rc(h, [0.0, 1.0], method=lme.LME_DOPRI5, layout=bad)
+        assert rc == lme.LME_EINVAL and "layout" in msg, msg
+
+
+def test_binding_checks_every_buffer_before_the_c_call():
+    """dtype, size and contiguity of every tensor are checked in the binding
+    (the C side cannot see the size of a device buffer); all of these raise
+    LME_EINVAL without any HIP call, so they run on a machine without a GPU."""
+    import torch
+    h, w = _handle()
+    good = torch.zeros(h.state_elems, dtype=torch.complex128)
+    cases = [
+        torch.zeros(h.state_elems, dtype=torch.complex64),          # wrong dtype
+        torch.zeros(h.state_elems - 1, dtype=torch.complex128),     # too short
+        torch.zeros(h.state_elems + 5, dtype=torch.complex128),     # too long
+        torch.zeros(2 * h.state_elems, dtype=torch.complex128)[::2],  # not contiguous
+        np.zeros(h.state_elems, np.complex128),                      # not a tensor
+        good,                                                        # not on the device
+    ]
+    for bad in cases:
+        with pytest.raises(lme.LmeError) as e:
+            h.evolve(bad, np.array([0.0, 1.0]), nsteps=10)
+        assert e.value.code == lme.LME_EINVAL
+        with pytest.raises(lme.LmeError) as e:
+            h.apply(bad)
+        assert e.value.code == lme.LME_EINVAL
+    # control amplitudes: float64, n_inst * n_ctrl * n_seg elements
+    wd = S.jc_drive(n_inst=2, N=3, n_seg=4, t_end=1.0, steps_per_seg=2)
+    hd = lme.Handle(wd.systems)
+    rho = torch.zeros(hd.state_elems, dtype=torch.complex128)
+    for bad_u in (torch.zeros((2, 1, 4), dtype=torch.float32),
+                  torch.zeros((2, 1, 3), dtype=torch.float64)):
+        with pytest.raises(lme.LmeError) as e:
+            hd.evolve(rho, np.array([0.0, 1.0]), nsteps=8, u=bad_u)
+        assert e.value.code == lme.LME_EINVAL and "u" in str(e.value)
+        with pytest.raises(lme.LmeError) as e:
+            lme._cost_grad(hd, rho, rho, bad_u, 0.0, 1.0, 8, 2)
+        assert e.value.code == lme.LME_EINVAL
+        with pytest.raises(lme.LmeError) as e:
+            lme.expectation_cost(bad_u, hd, rho, rho, 0.0, 1.0, 8)
+        assert e.value.code == lme.LME_EINVAL
+    with pytest.raises(lme.LmeError):   # controls given to a batch without segments
+        h.evolve(torch.zeros(h.state_elems, dtype=torch.complex128), np.array([0.0, 1.0]),
+                 nsteps=10, u=torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(lme.LmeError) as e:   # O of the wrong size
+        lme._cost_grad(hd, rho, torch.zeros(hd.state_elems - 1, dtype=torch.complex128),
+                       torch.zeros((2, 1, 4), dtype=torch.float64), 0.0, 1.0, 8, 2)
+    assert e.value.code == lme.LME_EINVAL

@@ -5,6 +5,8 @@ sequences agree up to rounding of the error norm, so the bar is the adaptive
 one: every expectation trace within 1e-6 of the oracle's, relative to the
 trace's largest magnitude.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -22,11 +24,17 @@ from paper_1110_0573_amd import lme  # noqa: E402
 REL = 1e-6
 
 
-def run(systems, tlist, rtol, atol, **kw):
+def run(systems, tlist, rtol, atol, ok=True, **kw):
+    """Adaptive evolution of the batch; with ``ok`` every instance must have
+    finished with status LME_OK (a stopped instance would otherwise show up
+    only as untouched outputs)."""
     h = lme.Handle(systems)
     out = h.evolve(h.pack([s.rho0 for s in systems]), tlist, method="dopri5", rtol=rtol,
                    atol=atol, **kw)
     torch.cuda.synchronize()
+    if ok:
+        st = out["status"].cpu().numpy()
+        assert (st == 0).all(), [lme.STATUS_NAMES.get(int(x), x) for x in st]
     return h, out
 
 
@@ -117,9 +125,9 @@ def test_dp5_given_first_step_and_general_operators():
 def test_dp5_device_status_codes():
     s = S.jc_system(3, g=0.4, kappa=0.3, gamma=0.2)
     tl = np.array([0.0, 3.0])
-    _, o = run([s], tl, 1e-8, 1e-11, max_steps=1)
+    _, o = run([s], tl, 1e-8, 1e-11, ok=False, max_steps=1)
     assert o["status"].cpu().numpy()[0] == lme.LME_EMAXSTEPS
-    _, o = run([s], tl, 1e-8, 1e-11, h_min=1.0)
+    _, o = run([s], tl, 1e-8, 1e-11, ok=False, h_min=1.0)
     assert o["status"].cpu().numpy()[0] == lme.LME_ESTEPUNDERFLOW
     bad = s.rho0.copy()
     bad[0, 0] = np.nan
@@ -173,7 +181,7 @@ def test_dp5_streamed_controls_and_first_step():
 def test_dp5_streamed_status_codes():
     s = S.jc_system(3, g=0.4, kappa=0.3, gamma=0.2)
     tl = np.array([0.0, 3.0])
-    _, o = run([s, s], tl, 1e-8, 1e-11, max_steps=3, path=lme.LME_PATH_STREAMED)
+    _, o = run([s, s], tl, 1e-8, 1e-11, ok=False, max_steps=3, path=lme.LME_PATH_STREAMED)
     assert (o["status"].cpu().numpy() == lme.LME_EMAXSTEPS).all()
     assert (o["counts"].cpu().numpy().sum(axis=1) == 3).all()
 
@@ -188,3 +196,45 @@ def test_dp5_tfim_full_size_routes_to_streamed_short_horizon():
     for b, s in enumerate(w.systems):
         r = oracle.dopri5(s, s.rho0, w.tlist, w.rtol, w.atol)
         close(ex[b], r["expect"])
+
+
+# --------------------------------------------------------------------------
+# the adaptive workloads at full size, exactly as the benchmark runs them,
+# against oracle traces stored by tests/golden/make_adaptive_golden.py
+# --------------------------------------------------------------------------
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _counts_close(gpu, ref):
+    """Step counts within 2 % (both sides run the same controller; rounding of
+    the error norm may move a few accept/reject decisions)."""
+    assert abs(int(gpu[0]) - int(ref[0])) <= 0.02 * ref[0] + 2, (gpu, ref)
+    assert abs(int(gpu[1]) - int(ref[1])) <= 0.02 * ref[0] + 2, (gpu, ref)
+
+
+def test_dp5_kerr_headline_full_horizon_against_golden():
+    """Kerr cavity N = 60, rtol 1e-8, atol 1e-11, t in [0, 50], 101 outputs
+    (37 712 accepted steps on the oracle), default path."""
+    w = S.kerr_single()
+    g = np.load(os.path.join(GOLDEN, "kerr_n60_t50.npz"))
+    assert np.array_equal(g["tlist"], w.tlist) and float(g["rtol"]) == w.rtol
+    h, out = run(w.systems, w.tlist, w.rtol, w.atol)
+    close(out["expect"].cpu().numpy()[0], g["expect"])
+    _counts_close(out["counts"].cpu().numpy()[0], g["counts"])
+
+
+def test_dp5_tfim_headline_64_chains_against_golden_sample():
+    """All 64 eight-spin chains, rtol 1e-7, atol 1e-10, t in [0, 20], 201
+    outputs, default (streamed) path; every instance must finish with status
+    OK, and the seeded sample of realizations stored from the oracle must
+    match on all 8 <sigma_z^i> traces."""
+    w = S.tfim()
+    g = np.load(os.path.join(GOLDEN, "tfim_8spin_t20_sample.npz"))
+    assert np.array_equal(g["tlist"], w.tlist) and float(g["rtol"]) == w.rtol
+    h, out = run(w.systems, w.tlist, w.rtol, w.atol)
+    ex = out["expect"].cpu().numpy()
+    counts = out["counts"].cpu().numpy()
+    for k, b in enumerate(g["index"]):
+        close(ex[b], g["expect"][k])
+        _counts_close(counts[b], g["counts"][k])

@@ -151,7 +151,7 @@ def test_rk4_damped_cavity_exponential_decay_exact_in_truncation():
 
 
 def test_rk4_thermal_cavity_relaxation_loose():
-    """Paper Sec. 4.2 system (N=5, kappa=1/0.129, n_th=0.063, one photon):
+    """Paper Sec. 3.2 example (Fig. 4) (N=5, kappa=1/0.129, n_th=0.063, one photon):
     <n>(t) ~ n_th + (1 - n_th) exp(-kappa t); exact only as N -> infinity."""
     kappa, nth = 1.0 / 0.129, 0.063
     s = S.damped_cavity(N=5, kappa=kappa, n_th=nth, n0=1)
@@ -365,3 +365,121 @@ def test_adjoint_gradient_matches_central_differences_driven_jc():
     # the cost is the final-time expectation computed by plain RK4
     ex, st = oracle.rk4(s, s.rho0, np.array([0.0, 2.0]), w.nsteps, store_states=True)
     assert abs(J - np.real(np.trace(O @ st[-1]))) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# the adaptive step-size controller and the starting step
+# --------------------------------------------------------------------------
+
+RTOL_CONTROLLER = 2e-5
+
+
+def _controller_steps(S, rho0, stops, rtol, atol, h0=0.0, n_accept=12):
+    """Accepted step sizes recomputed from the written rules, with every step
+    map taken from the stability polynomials of the tableau (dense matrices,
+    none of the oracle's stage arithmetic):
+      * start (h0 <= 0): Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4:
+        d0 = ||y0||, d1 = ||f(y0)||, hs = 0.01 d0/d1 (1e-6 if either < 1e-5),
+        d2 = ||f(y0 + hs f(y0)) - f(y0)|| / hs,
+        h1 = (0.01 / max(d1, d2))^(1/5) (max(1e-6, 1e-3 hs) if max <= 1e-15),
+        h = min(100 hs, h1), norms scaled by atol + rtol |y0|;
+      * each attempt: err = ||y5 - y4|| scaled by atol + rtol max(|y|, |y5|);
+        accept if err <= 1, then h <- h_used clip(0.9 err^(-1/5), 0.2, 10),
+        no growth right after a rejection; reject: h <- h max(0.2, 0.9 err^(-1/5));
+      * a step that would pass the next stop point lands on it.
+    Returns (starting step, accepted steps, number of rejections)."""
+    v = brute.vec(rho0)
+    if h0 > 0:
+        h = h0
+        hstart = h0
+    else:
+        f0 = S @ v
+        sc = atol + rtol * np.abs(v)
+        d0, d1 = brute.rms_scaled(v, sc), brute.rms_scaled(f0, sc)
+        hs = 1e-6 if (d0 < 1e-5 or d1 < 1e-5) else 0.01 * d0 / d1
+        f1 = S @ (v + hs * f0)
+        d2 = brute.rms_scaled(f1 - f0, sc) / hs
+        dm = max(d1, d2)
+        h1 = max(1e-6, hs * 1e-3) if dm <= 1e-15 else (0.01 / dm) ** 0.2
+        h = min(100.0 * hs, h1)
+        hstart = (h, hs, h1)
+    t, stop, acc, rej, prev_rej = 0.0, 0, [], 0, False
+    while len(acc) < n_accept and stop < len(stops):
+        h_try, landing = h, False
+        if h_try >= stops[stop] - t:
+            h_try, landing = stops[stop] - t, True
+        y5 = brute.dopri5_map(S, h_try) @ v
+        err = brute.dopri5_error_map(S, h_try) @ v
+        en = brute.rms_scaled(err, atol + rtol * np.maximum(np.abs(v), np.abs(y5)))
+        if en <= 1.0:
+            acc.append(h_try)
+            v = y5
+            fac = 10.0 if en == 0 else min(10.0, max(0.2, 0.9 * en ** -0.2))
+            if prev_rej:
+                fac = min(fac, 1.0)
+            prev_rej = False
+            h = h_try * fac
+            if landing:
+                t = stops[stop]
+                stop += 1
+            else:
+                t += h_try
+        else:
+            rej += 1
+            prev_rej = True
+            h = h_try * max(0.2, 0.9 * en ** -0.2)
+    return hstart, np.array(acc), rej
+
+
+@pytest.mark.parametrize("case", ["jc_cap_binds", "kerr_hnw", "random_stops"])
+def test_dopri5_starting_step_and_controller_follow_written_rules(case):
+    """The oracle's HNW starting step and its first accepted step sizes equal
+    those recomputed from the written controller rules on stability-polynomial
+    maps.  The cases cover both branches of min(100 hs, h1): the cap binding
+    and h1 between 10 hs and 100 hs (so a cap of 10 hs would fail)."""
+    if case == "jc_cap_binds":
+        s = S.jc_system(3, g=0.3, kappa=0.05, gamma=0.02)
+        rtol, atol, tl = 1e-6, 1e-9, np.array([0.0, 0.7, 2.0])
+    elif case == "kerr_hnw":
+        s = S.kerr_system(6, delta=0.4, K=0.2, E=0.3, kappa=0.5)
+        rtol, atol, tl = 1e-10, 1e-13, np.array([0.0, 0.25, 1.0])
+    else:
+        s = S.random_system(3, n_c=2, seed=71)
+        rtol, atol, tl = 1e-7, 1e-10, np.array([0.0, 0.05, 0.3, 0.31])
+    Sm = brute.superop(s.H0, s.C)
+    (h_start, hs, h1), want, _ = _controller_steps(Sm, s.rho0, tl[1:], rtol, atol)
+    r = oracle.dopri5(s, s.rho0, tl, rtol, atol, h_log_cap=len(want), store_states=False)
+    got = r["h_log"][:len(want)]
+    assert len(got) == len(want)
+    # The embedded error estimate is a difference of O(h |f|) stage terms, so
+    # on either side it carries a relative rounding error of about
+    # 1e-16 h|f| / |err| (up to 1e-5 at these tolerances); the step factor
+    # err^(-1/5) passes a fifth of it on.  A wrong exponent (-1/4) changes the
+    # factor by percents, a wrong cap by 10x.
+    np.testing.assert_allclose(got, want, rtol=RTOL_CONTROLLER, atol=0)
+    if case == "jc_cap_binds":
+        assert h1 > 100 * hs            # the 100 hs cap decides the first step
+    if case == "kerr_hnw":
+        assert 10 * hs < h1 < 100 * hs  # h1 decides; a 10 hs cap would not
+    # the first accepted step is the starting step unless it was rejected
+    # or clamped to the first stop point
+    if r["counts"][1] == 0 and h_start < tl[1]:
+        assert abs(got[0] - h_start) <= 1e-13 * h_start
+
+
+def test_dopri5_rejections_and_no_growth_after_reject():
+    """A deliberately large first step is rejected and shrunk by
+    max(0.2, 0.9 err^(-1/5)).  On this Kerr cavity the first step is large
+    enough that the error falls faster than h^5 when the step shrinks, so
+    the accepted step after the rejection has a small error and the rule
+    "no growth right after a rejection" decides the next step size (without
+    it the next step would be 5 % longer)."""
+    s = S.kerr_system(6, delta=0.4, K=0.9, E=0.3, kappa=0.5)
+    rtol, atol, tl = 1e-4, 1e-7, np.array([0.0, 4.0])
+    Sm = brute.superop(s.H0, s.C)
+    _, want, rej = _controller_steps(Sm, s.rho0, tl[1:], rtol, atol, h0=0.55, n_accept=10)
+    assert rej >= 1
+    r = oracle.dopri5(s, s.rho0, tl, rtol, atol, h0=0.55, h_log_cap=10)
+    np.testing.assert_allclose(r["h_log"], want, rtol=RTOL_CONTROLLER, atol=0)
+    # the step after the rejection repeats the accepted one exactly (factor 1)
+    assert r["h_log"][1] == r["h_log"][0]
