@@ -28,9 +28,9 @@ _LIBPATH = os.path.join(_HERE, "liblme_oracle.so")
 _LOCK = threading.Lock()
 _LIB = None
 
-OK, EINVAL, EGRID, EMAXSTEPS, ESTEPUNDERFLOW, ENONFINITE, ENOMEM = range(7)
+OK, EINVAL, EGRID, EMAXSTEPS, ESTEPUNDERFLOW, ENONFINITE, ENOMEM, EDRAWS = range(8)
 CODE_NAMES = {0: "OK", 1: "EINVAL", 2: "EGRID", 3: "EMAXSTEPS",
-              4: "ESTEPUNDERFLOW", 5: "ENONFINITE", 6: "ENOMEM"}
+              4: "ESTEPUNDERFLOW", 5: "ENONFINITE", 6: "ENOMEM", 7: "EDRAWS"}
 
 
 class OracleError(RuntimeError):
@@ -89,6 +89,9 @@ def _lib():
             lib.orc_dopri5_step.argtypes = [P, C.c_double, C.c_double, _PD, _PD, _PD]
             lib.orc_rk4_cost_grad.argtypes = [P, _PD, _PD, C.c_double, C.c_double,
                                               C.c_int32, _PD, _PD]
+            lib.orc_mc.argtypes = [P, _PD, C.c_int32, _PD, C.c_int32, C.c_int32, _PD,
+                                   C.c_int32, _PD, _PD, C.POINTER(C.c_int32), _PD,
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]
             lib.orc_rk4_batch.argtypes = [C.c_int32, P, C.POINTER(_PD), C.c_int32,
                                           _PD, C.c_int32, C.POINTER(_PD), C.c_int32,
                                           C.POINTER(C.c_int32)]
@@ -273,3 +276,38 @@ def rk4_batch(systems, rho0s, tlist, nsteps, n_threads):
                                  int(n_threads), rc.ctypes.data_as(C.POINTER(C.c_int32)))
     _check(worst, "rk4_batch")
     return [e[:m.n_e] for e, m in zip(exs, ms)]
+
+
+def mc(system, psi0, tlist, nsteps, draws, n_threads=1, raise_on_error=True):
+    """Monte-Carlo wave-function trajectories (Sec. 3.2, steps I-IV), one per
+    row of ``draws`` ([n_traj, max_jumps + 1, 2] uniform numbers: the norm
+    threshold r of each waiting period and the number that picks the
+    collapse operator of each jump).  Fixed-step RK4 on the effective
+    Hamiltonian of Eq. (heff); jump times located on the RK4 step of partial
+    length by bisection.  Returns a dict: expect (mean over trajectories,
+    [n_e, n_t]), expect_traj [n_traj, n_e, n_t], n_jumps, jump_t, jump_op
+    ([n_traj, max_jumps]), status [n_traj], rc."""
+    m = _marshal(system)
+    psi0 = np.ascontiguousarray(np.asarray(psi0, np.complex128).reshape(m.n))
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    n_t = len(tl)
+    draws = np.ascontiguousarray(draws, dtype=np.float64)
+    n_traj, mj1 = draws.shape[0], draws.shape[1]
+    assert draws.shape == (n_traj, mj1, 2)
+    max_jumps = mj1 - 1
+    ne = max(1, m.n_e)
+    avg = np.zeros((ne, n_t), np.complex128)
+    per = np.zeros((n_traj, ne, n_t), np.complex128)
+    nj = np.zeros(n_traj, np.int32)
+    jt = np.zeros((n_traj, max(1, max_jumps)), np.float64)
+    jo = np.full((n_traj, max(1, max_jumps)), -1, np.int32)
+    st = np.zeros(n_traj, np.int32)
+    PI = C.POINTER(C.c_int32)
+    rc = _lib().orc_mc(C.byref(m.s), _dptr(psi0.view(np.float64)), n_t, _dptr(tl), int(nsteps),
+                       n_traj, _dptr(draws), max_jumps, _dptr(avg.view(np.float64)),
+                       _dptr(per.view(np.float64)), nj.ctypes.data_as(PI), _dptr(jt),
+                       jo.ctypes.data_as(PI), st.ctypes.data_as(PI), int(n_threads))
+    if raise_on_error:
+        _check(rc, "mc")
+    return {"expect": avg[:m.n_e], "expect_traj": per[:, :m.n_e], "n_jumps": nj,
+            "jump_t": jt[:, :max_jumps], "jump_op": jo[:, :max_jumps], "status": st, "rc": rc}

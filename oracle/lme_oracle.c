@@ -767,6 +767,299 @@ int orc_rk4_cost_grad(const orc_system *s, const double *rho0, const double *O,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Monte-Carlo wave-function trajectories (Sec. 3.2)                           */
+/* ------------------------------------------------------------------------- */
+
+/* out += alpha * M x */
+static void csr_vec(int n, const orc_csr *M, const cplx *x, cplx alpha, cplx *out) {
+  const cplx *mv = cval(M);
+  for (int i = 0; i < n; ++i)
+    for (int p = M->row_ptr[i]; p < M->row_ptr[i + 1]; ++p) out[i] += alpha * mv[p] * x[M->col[p]];
+}
+
+/* out += alpha * M^+ x,  (M^+ x)_i = sum_l conj(M_li) x_l */
+static void csrdag_vec(int n, const orc_csr *M, const cplx *x, cplx alpha, cplx *out) {
+  const cplx *mv = cval(M);
+  for (int l = 0; l < n; ++l)
+    for (int p = M->row_ptr[l]; p < M->row_ptr[l + 1]; ++p)
+      out[M->col[p]] += alpha * conj(mv[p]) * x[l];
+}
+
+static double norm2_vec(int n, const cplx *x) {
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+  return acc;
+}
+
+/* out = -i H_eff psi with H_eff = H0 - (i/2) sum_n C_n^+ C_n (Eq. (heff), hbar = 1),
+ * i.e. out = -i H0 psi - 1/2 sum_n C_n^+ (C_n psi). */
+static void heff_rhs(const orc_system *s, const cplx *psi, cplx *out, cplx *tmp) {
+  const int n = s->n;
+  memset(out, 0, (size_t)n * sizeof(cplx));
+  csr_vec(n, &s->H0, psi, -I, out);
+  for (int k = 0; k < s->n_c; ++k) {
+    memset(tmp, 0, (size_t)n * sizeof(cplx));
+    csr_vec(n, &s->C[k], psi, 1.0, tmp);
+    csrdag_vec(n, &s->C[k], tmp, -0.5, out);
+  }
+}
+
+typedef struct {
+  cplx *k, *y, *acc, *tmp;
+} mc_work;
+
+/* out = the classic RK4 step of length h of d psi/dt = -i H_eff psi from psi. */
+static void rk4_vec(const orc_system *s, double h, const cplx *psi, cplx *out, mc_work *w) {
+  const int n = s->n;
+  heff_rhs(s, psi, w->k, w->tmp); /* k1 */
+  for (int i = 0; i < n; ++i) {
+    w->acc[i] = w->k[i];
+    w->y[i] = psi[i] + (0.5 * h) * w->k[i];
+  }
+  heff_rhs(s, w->y, w->k, w->tmp); /* k2 */
+  for (int i = 0; i < n; ++i) {
+    w->acc[i] += 2.0 * w->k[i];
+    w->y[i] = psi[i] + (0.5 * h) * w->k[i];
+  }
+  heff_rhs(s, w->y, w->k, w->tmp); /* k3 */
+  for (int i = 0; i < n; ++i) {
+    w->acc[i] += 2.0 * w->k[i];
+    w->y[i] = psi[i] + h * w->k[i];
+  }
+  heff_rhs(s, w->y, w->k, w->tmp); /* k4 */
+  for (int i = 0; i < n; ++i) {
+    w->acc[i] += w->k[i];
+    out[i] = psi[i] + (h / 6.0) * w->acc[i];
+  }
+}
+
+/* <psi|E psi> / <psi|psi> for every expectation operator into ex[m] (complex). */
+static void mc_record(const orc_system *s, const cplx *psi, cplx *tmp, cplx *ex) {
+  const int n = s->n;
+  const double nn = norm2_vec(n, psi);
+  for (int m = 0; m < s->n_e; ++m) {
+    memset(tmp, 0, (size_t)n * sizeof(cplx));
+    csr_vec(n, &s->E[m], psi, 1.0, tmp);
+    cplx acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += conj(psi[i]) * tmp[i];
+    ex[m] = acc / nn;
+  }
+}
+
+/* One trajectory: steps I-IV of Sec. 3.2.  ex: [n_e][n_t] complex. */
+static int mc_trajectory(const orc_system *s, const cplx *psi0, int32_t n_t, const double *tlist,
+                         int32_t nsteps, const long *out_step, const double *draws,
+                         int32_t max_jumps, cplx *ex, int32_t *n_jumps, double *jump_t,
+                         int32_t *jump_op) {
+  const int n = s->n;
+  const double t0 = tlist[0];
+  const double h = n_t > 1 ? (tlist[n_t - 1] - t0) / nsteps : 0.0;
+  cplx *buf = (cplx *)malloc(7 * (size_t)n * sizeof(cplx));
+  cplx *exk = (cplx *)malloc(((size_t)s->n_e + 1) * sizeof(cplx));
+  if (!buf || !exk) {
+    free(buf);
+    free(exk);
+    return ORC_ENOMEM;
+  }
+  mc_work w = {buf, buf + n, buf + 2 * (size_t)n, buf + 3 * (size_t)n};
+  cplx *psi = buf + 4 * (size_t)n, *trial = buf + 5 * (size_t)n, *cpsi = buf + 6 * (size_t)n;
+  int rc = ORC_OK;
+  int jumps = 0;
+  /* the initial state, normalised */
+  const double nn0 = norm2_vec(n, psi0);
+  if (!(nn0 > 0.0) || !isfinite(nn0)) {
+    rc = ORC_EINVAL;
+    goto done;
+  }
+  for (int i = 0; i < n; ++i) psi[i] = psi0[i] / sqrt(nn0);
+  mc_record(s, psi, w.tmp, exk);
+  for (int m = 0; m < s->n_e; ++m) ex[(size_t)m * n_t] = exk[m];
+
+  double r = draws[0]; /* step I: the first waiting period's threshold */
+  int next = 1;
+  for (long st = 0; st < (n_t > 1 ? nsteps : 0); ++st) {
+    double t = t0 + (double)st * h; /* time of the current state */
+    double left = h;                  /* the rest of this grid step */
+    while (left > 0.0) {
+      /* step II: integrate; does the norm reach r within the rest of the step? */
+      rk4_vec(s, left, psi, trial, &w);
+      const double nt = norm2_vec(n, trial);
+      if (!isfinite(nt)) {
+        rc = ORC_ENONFINITE;
+        goto done;
+      }
+      if (nt > r) {
+        memcpy(psi, trial, (size_t)n * sizeof(cplx));
+        break;
+      }
+      /* the jump time: tau in (0, left] with |RK4(psi, tau)|^2 = r, by bisection
+         (the norm is above r at 0 and at most r at `left`) */
+      double lo = 0.0, hi = left;
+      for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        rk4_vec(s, mid, psi, trial, &w);
+        if (norm2_vec(n, trial) <= r)
+          hi = mid;
+        else
+          lo = mid;
+      }
+      const double tau = hi;
+      rk4_vec(s, tau, psi, trial, &w);
+      /* step III: probabilities P_i = <psi|C_i^+ C_i|psi> / sum (Eq. (pcn)) and
+         the smallest n with P_1 + ... + P_n >= r' (Eq. (mc3)) */
+      if (jumps >= max_jumps) {
+        rc = ORC_EDRAWS;
+        goto done;
+      }
+      const double r2 = draws[2 * (size_t)jumps + 1];
+      double total = 0.0;
+      for (int k = 0; k < s->n_c; ++k) {
+        memset(cpsi, 0, (size_t)n * sizeof(cplx));
+        csr_vec(n, &s->C[k], trial, 1.0, cpsi);
+        total += norm2_vec(n, cpsi);
+      }
+      if (!(total > 0.0) || !isfinite(total)) {
+        rc = ORC_ENONFINITE;
+        goto done;
+      }
+      int chosen = -1, last_nonzero = -1;
+      double cum = 0.0, w_chosen = 0.0;
+      for (int k = 0; k < s->n_c && chosen < 0; ++k) {
+        memset(cpsi, 0, (size_t)n * sizeof(cplx));
+        csr_vec(n, &s->C[k], trial, 1.0, cpsi);
+        const double wk = norm2_vec(n, cpsi);
+        if (wk > 0.0) last_nonzero = k;
+        cum += wk / total;
+        if (cum >= r2 && wk > 0.0) {
+          chosen = k;
+          w_chosen = wk;
+        }
+      }
+      if (chosen < 0) { /* r' above the rounded cumulative sum: the last channel */
+        chosen = last_nonzero;
+        memset(cpsi, 0, (size_t)n * sizeof(cplx));
+        csr_vec(n, &s->C[chosen], trial, 1.0, cpsi);
+        w_chosen = norm2_vec(n, cpsi);
+      }
+      /* the projected, renormalised state (Eq. (project)) */
+      memset(cpsi, 0, (size_t)n * sizeof(cplx));
+      csr_vec(n, &s->C[chosen], trial, 1.0, cpsi);
+      for (int i = 0; i < n; ++i) psi[i] = cpsi[i] / sqrt(w_chosen);
+      t += tau;
+      if (jump_t) jump_t[jumps] = t;
+      if (jump_op) jump_op[jumps] = chosen;
+      ++jumps;
+      /* step IV: a new random number; continue from the jump time with the
+         rest of the grid step */
+      r = draws[2 * (size_t)jumps];
+      left -= tau;
+    }
+    while (next < n_t && out_step[next] == st + 1) {
+      mc_record(s, psi, w.tmp, exk);
+      for (int m = 0; m < s->n_e; ++m) ex[(size_t)m * n_t + next] = exk[m];
+      ++next;
+    }
+  }
+done:
+  if (n_jumps) *n_jumps = jumps;
+  free(buf);
+  free(exk);
+  return rc;
+}
+
+typedef struct {
+  const orc_system *s;
+  const cplx *psi0;
+  int32_t n_t;
+  const double *tlist;
+  int32_t nsteps;
+  const long *out_step;
+  const double *draws;
+  int32_t max_jumps;
+  cplx *ex_all; /* [n_traj][n_e][n_t] */
+  int32_t *n_jumps;
+  double *jump_t;
+  int32_t *jump_op;
+  int32_t *status;
+  int32_t n_traj;
+  int next;
+} mc_job;
+
+static void *mc_worker(void *arg) {
+  mc_job *j = (mc_job *)arg;
+  const size_t per = (size_t)j->s->n_e * j->n_t;
+  for (;;) {
+    const int b = __atomic_fetch_add(&j->next, 1, __ATOMIC_RELAXED);
+    if (b >= j->n_traj) break;
+    int32_t nj = 0;
+    j->status[b] = mc_trajectory(
+        j->s, j->psi0, j->n_t, j->tlist, j->nsteps, j->out_step,
+        j->draws + 2 * (size_t)b * ((size_t)j->max_jumps + 1), j->max_jumps, j->ex_all + per * b,
+        &nj, j->jump_t ? j->jump_t + (size_t)b * j->max_jumps : NULL,
+        j->jump_op ? j->jump_op + (size_t)b * j->max_jumps : NULL);
+    if (j->n_jumps) j->n_jumps[b] = nj;
+  }
+  return NULL;
+}
+
+int orc_mc(const orc_system *s, const double *psi0, int32_t n_t, const double *tlist,
+           int32_t nsteps, int32_t n_traj, const double *draws, int32_t max_jumps,
+           double *expect_avg, double *expect_traj, int32_t *n_jumps, double *jump_t,
+           int32_t *jump_op, int32_t *status, int32_t n_threads) {
+  int rc = check_system(s);
+  if (rc) return rc;
+  if (s->n_ctrl != 0 || !psi0 || !tlist || n_t < 1 || n_traj < 1 || !draws || max_jumps < 0 ||
+      n_threads < 1)
+    return ORC_EINVAL;
+  if (n_t > 1 && nsteps < 1) return ORC_EINVAL;
+  const double h = n_t > 1 ? (tlist[n_t - 1] - tlist[0]) / nsteps : 0.0;
+  long *out_step = (long *)malloc(sizeof(long) * (size_t)n_t);
+  const size_t per = (size_t)s->n_e * n_t;
+  cplx *ex_all = (cplx *)calloc(per * n_traj + 1, sizeof(cplx));
+  int32_t *st = (int32_t *)calloc((size_t)n_traj, sizeof(int32_t));
+  if (!out_step || !ex_all || !st) {
+    free(out_step);
+    free(ex_all);
+    free(st);
+    return ORC_ENOMEM;
+  }
+  if (n_t > 1) rc = rk4_grid(s, n_t, tlist, nsteps, h, out_step);
+  else out_step[0] = 0;
+  if (rc) goto done;
+  {
+    mc_job job = {s, (const cplx *)psi0, n_t, tlist, nsteps, out_step, draws, max_jumps, ex_all,
+                  n_jumps, jump_t, jump_op, st, n_traj, 0};
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    int started = 0;
+    if (th)
+      for (int i = 0; i < n_threads; ++i)
+        if (pthread_create(&th[i], NULL, mc_worker, &job) == 0) ++started;
+    if (started == 0) mc_worker(&job);
+    for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
+    free(th);
+  }
+  for (int b = 0; b < n_traj; ++b)
+    if (st[b] != ORC_OK) rc = st[b];
+  if (status) memcpy(status, st, sizeof(int32_t) * (size_t)n_traj);
+  if (expect_traj) memcpy(expect_traj, ex_all, per * n_traj * sizeof(cplx));
+  if (expect_avg) {
+    /* mean over trajectories, in trajectory order */
+    cplx *avg = (cplx *)expect_avg;
+    for (size_t e = 0; e < per; ++e) {
+      cplx acc = 0.0;
+      for (int b = 0; b < n_traj; ++b) acc += ex_all[per * b + e];
+      avg[e] = acc / (double)n_traj;
+    }
+  }
+done:
+  free(out_step);
+  free(ex_all);
+  free(st);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Many instances on host threads                                             */
 /* ------------------------------------------------------------------------- */
 

@@ -38,7 +38,8 @@ enum {
   ORC_EMAXSTEPS = 3,       /* adaptive: step budget exhausted                  */
   ORC_ESTEPUNDERFLOW = 4,  /* adaptive: step size fell below h_min             */
   ORC_ENONFINITE = 5,      /* NaN/Inf met in the state or the error norm       */
-  ORC_ENOMEM = 6
+  ORC_ENOMEM = 6,
+  ORC_EDRAWS = 7           /* Monte-Carlo: a trajectory used up its draws      */
 };
 
 typedef struct {
@@ -90,6 +91,26 @@ int orc_dopri5_step(const orc_system *s, double t, double h, const double *y,
 int orc_rk4_cost_grad(const orc_system *s, const double *rho0, const double *O,
                       double t0, double t1, int32_t nsteps, double *cost,
                       double *grad);
+
+/* Monte-Carlo wave-function trajectories (Sec. 3.2, steps I-IV).
+ * Each trajectory starts from psi0 (normalised here) at tlist[0] and evolves
+ * under the non-Hermitian effective Hamiltonian of Eq. (heff),
+ *   d psi/dt = -i H_eff psi,   H_eff = H0 - (i/2) sum_n C_n^+ C_n,
+ * with classic RK4 on the grid tlist[0] + m h, h = (tlist[n_t-1] - tlist[0])
+ * / nsteps (every output time on the grid).  Between grid points the
+ * solution is the RK4 step of the partial length.  Random numbers are an
+ * input: draws[(traj*(max_jumps+1) + j)*2 + 0] is the number r of step I for
+ * the j-th waiting period, draws[... + 1] the number that chooses the
+ * collapse operator of the j-th jump (step III).  A trajectory that would
+ * need more than max_jumps jumps stops with ORC_EDRAWS.
+ * Outputs (each may be NULL): expect_avg [n_e][n_t] complex, the mean over
+ * trajectories of <psi|E|psi>/<psi|psi>; expect_traj [n_traj][n_e][n_t]
+ * complex; n_jumps [n_traj]; jump_t, jump_op [n_traj][max_jumps] (time and
+ * collapse-operator index of every jump); status [n_traj]. */
+int orc_mc(const orc_system *s, const double *psi0, int32_t n_t, const double *tlist,
+           int32_t nsteps, int32_t n_traj, const double *draws, int32_t max_jumps,
+           double *expect_avg, double *expect_traj, int32_t *n_jumps, double *jump_t,
+           int32_t *jump_op, int32_t *status, int32_t n_threads);
 
 /* RK4 over many independent instances on n_threads host threads (dynamic
  * scheduling); used for timing the oracle on the host. rc[b] per instance. */

@@ -21,7 +21,10 @@ Workloads (all sizes are those of the headline configurations):
   * ``jc_drive``    256 driven qubit x cavity instances (N=20), piecewise
                     constant drive on 100 segments, RK4 with 1000 steps;
   * ``tfim``        dissipative transverse-field Ising chain, 8 spins, 64
-                    disorder realizations, Dormand-Prince rtol 1e-7.
+                    disorder realizations, Dormand-Prince rtol 1e-7;
+  * ``trilinear``   three coupled modes of 17 states (dim 4913) for the
+                    Monte-Carlo solver, with ``mc_draws`` supplying the
+                    random numbers of every trajectory.
 """
 from __future__ import annotations
 
@@ -299,6 +302,45 @@ def damped_cavity(N=5, kappa=1.0 / 0.129, n_th=0.0, n0=1):
         C.append(tidy(np.sqrt(kappa * n_th) * ad))
     return System(tidy(ad @ a), C, [tidy(ad @ a)], ket2dm(ket(N, n0)),
                   meta=dict(kappa=kappa, n_th=n_th))
+
+
+# --------------------------------------------------------------------------
+# Monte-Carlo workloads (Sec. 3.2 and Sec. 4.3)
+# --------------------------------------------------------------------------
+
+def mc_draws(n_traj, max_jumps, seed):
+    """Uniform numbers in [0, 1) for the Monte-Carlo trajectories, shape
+    [n_traj, max_jumps + 1, 2]: per waiting period j the norm threshold r of
+    step I and the number that picks the collapse operator of the j-th jump
+    (step III).  Drawn once here and handed to both the GPU and the oracle."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n_traj, max_jumps + 1, 2))
+
+
+def thermal_cavity_mc(N=5, kappa=1.0 / 0.129, n_th=0.063):
+    """Single-photon cavity decay in a thermal environment (Sec. 3.2 example,
+    Fig. 4): H = a^+a, C_1 = sqrt((1 + n_th) kappa) a, C_2 = sqrt(n_th kappa) a^+,
+    psi0 = |1>, <a^+a> at 100 times on [0, 0.6]."""
+    s = damped_cavity(N=N, kappa=kappa, n_th=n_th, n0=1)
+    s.meta["psi0"] = ket(N, 1)
+    return s
+
+
+def trilinear(N=17, alpha=np.sqrt(10.0), g=(0.1, 0.4, 0.1)):
+    """Trilinear Hamiltonian (Sec. 4.3, Eq. (trilinear), K = 1, hbar = 1):
+    H = i (a b^+ c^+ - a^+ b c) on three modes of N states each (pump a,
+    signal b, idler c, in that tensor order), C_k = sqrt(2 g_k) a_k,
+    psi0 = |alpha> |0> |0> (coherent pump), E-ops the three number operators."""
+    a0 = tensor(destroy(N), qeye(N), qeye(N))
+    a1 = tensor(qeye(N), destroy(N), qeye(N))
+    a2 = tensor(qeye(N), qeye(N), destroy(N))
+    H = tidy(1j * (a0 @ dag(a1) @ dag(a2) - dag(a0) @ a1 @ a2))
+    C = [tidy(np.sqrt(2.0 * gk) * ak) for gk, ak in zip(g, (a0, a1, a2))]
+    E = [tidy(dag(ak) @ ak) for ak in (a0, a1, a2)]
+    psi0 = np.kron(np.kron(coherent_ket(N, alpha), ket(N, 0)), ket(N, 0))
+    s = System(H, C, E, None, meta=dict(N=N, alpha=alpha, g=g))
+    s.meta["psi0"] = psi0
+    return s
 
 
 def random_system(n, n_c=2, n_ctrl=0, n_e=2, density=0.4, seed=0, n_seg=0,

@@ -119,3 +119,18 @@ def dopri5_error_map(S, h):
 def rms_scaled(v, sc):
     """RMS over the complex moduli of v / sc (the adaptive error norm)."""
     return float(np.sqrt(np.mean((np.abs(v) / sc) ** 2)))
+
+
+def heff(H, C):
+    """Dense effective Hamiltonian H - (i/2) sum_n C_n^+ C_n (the non-Hermitian
+    generator of the no-jump evolution)."""
+    Hd = dense(H).astype(np.complex128)
+    for c in C:
+        c = dense(c)
+        Hd = Hd - 0.5j * (c.conj().T @ c)
+    return Hd
+
+
+def nojump_state(H, C, psi0, t):
+    """exp(-i H_eff t) psi0 (unnormalised)."""
+    return sl.expm(-1j * heff(H, C) * t) @ np.asarray(psi0, np.complex128)

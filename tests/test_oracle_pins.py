@@ -483,3 +483,131 @@ def test_dopri5_rejections_and_no_growth_after_reject():
     np.testing.assert_allclose(r["h_log"], want, rtol=RTOL_CONTROLLER, atol=0)
     # the step after the rejection repeats the accepted one exactly (factor 1)
     assert r["h_log"][1] == r["h_log"][0]
+
+
+# --------------------------------------------------------------------------
+# Monte-Carlo wave-function trajectories (Sec. 3.2)
+# --------------------------------------------------------------------------
+
+def _mc_system(seed=91, n=4, n_c=2):
+    s = S.random_system(n, n_c=n_c, n_e=2, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    psi = rng.normal(size=n) + 1j * rng.normal(size=n)
+    return s, psi / np.linalg.norm(psi)
+
+
+def test_mc_without_jumps_follows_the_effective_hamiltonian():
+    """With r = 0 no jump happens: each output is <psi|E|psi>/<psi|psi> of
+    psi(t) = exp(-i H_eff t) psi0, H_eff = H - i/2 sum C^+C (Eq. (heff)),
+    within the RK4 error at h = 1e-3."""
+    s, psi0 = _mc_system()
+    tl = np.linspace(0.0, 2.0, 11)
+    draws = np.zeros((2, 3, 2))
+    r = oracle.mc(s, psi0, tl, 2000, draws)
+    assert (r["n_jumps"] == 0).all()
+    for k, t in enumerate(tl):
+        p = brute.nojump_state(s.H0, s.C, psi0, t)
+        for m, E in enumerate(s.E):
+            want = np.vdot(p, brute.dense(E) @ p) / np.vdot(p, p)
+            assert abs(r["expect_traj"][0, m, k] - want) < 1e-10
+    assert np.array_equal(r["expect"], r["expect_traj"][0])
+
+
+def test_mc_without_collapse_operators_is_the_schrodinger_equation():
+    """No collapse operators: the trajectory is the closed-system evolution
+    exp(-i H t) psi0 whatever the draws (Sec. 4.3 remark)."""
+    s, psi0 = _mc_system(seed=93, n=5, n_c=0)
+    tl = np.linspace(0.0, 1.5, 4)
+    r = oracle.mc(s, psi0, tl, 1500, S.mc_draws(3, 2, 5))
+    for k, t in enumerate(tl):
+        p = sl.expm(-1j * brute.dense(s.H0) * t) @ psi0
+        want = np.vdot(p, brute.dense(s.E[0]) @ p)
+        assert np.max(np.abs(r["expect_traj"][:, 0, k] - want)) < 1e-10
+
+
+def test_mc_jump_times_solve_the_norm_equation_and_channels_the_cumulative_rule():
+    """Step II: the first jump time tau of each trajectory satisfies
+    |exp(-i H_eff tau) psi0|^2 = r_0.  Step III: the chosen collapse operator
+    is the smallest n with P_1 + ... + P_n >= r'_0, P_i from the exact state
+    at tau (Eq. (pcn), (mc3)).  Every draw is checked against the exact
+    no-jump evolution, not against the oracle's own integrator."""
+    s, psi0 = _mc_system(seed=95, n=4, n_c=3)
+    tl = np.array([0.0, 2.0])
+    draws = S.mc_draws(40, 60, 7)
+    draws[:, :, 0] = 0.35 + 0.6 * draws[:, :, 0]   # thresholds the decay reaches early
+    r = oracle.mc(s, psi0, tl, 2000, draws)
+    checked = 0
+    for b in range(len(draws)):
+        if r["n_jumps"][b] == 0:
+            p = brute.nojump_state(s.H0, s.C, psi0, tl[-1])
+            assert np.vdot(p, p).real > draws[b, 0, 0]   # the norm never reached r
+            continue
+        tau = r["jump_t"][b, 0]
+        p = brute.nojump_state(s.H0, s.C, psi0, tau)
+        assert abs(np.vdot(p, p).real - draws[b, 0, 0]) < 1e-9
+        w = np.array([np.linalg.norm(brute.dense(c) @ p) ** 2 for c in s.C])
+        cum = np.cumsum(w / w.sum())
+        if np.min(np.abs(cum - draws[b, 0, 1])) < 1e-8:
+            continue                                  # too close to call
+        assert r["jump_op"][b, 0] == int(np.argmax(cum >= draws[b, 0, 1]))
+        checked += 1
+    assert checked >= 30 and len(set(r["jump_op"][r["n_jumps"] > 0, 0])) == 3
+
+
+def test_mc_first_jump_of_a_decaying_photon_closed_form():
+    """Zero-temperature cavity from |1>: |psi(t)|^2 = exp(-kappa t), so the
+    jump time is -ln(r)/kappa and the jump lands in |0> (no further jumps)."""
+    kappa = 1.0 / 0.129
+    s = S.thermal_cavity_mc(N=4, kappa=kappa, n_th=0.0)
+    tl = np.linspace(0.0, 0.6, 7)
+    draws = S.mc_draws(30, 3, 11)
+    r = oracle.mc(s, s.meta["psi0"], tl, 6000, draws)
+    for b in range(30):
+        tau = -np.log(draws[b, 0, 0]) / kappa
+        if tau < 0.6:
+            assert r["n_jumps"][b] == 1
+            assert abs(r["jump_t"][b, 0] - tau) < 1e-10
+            assert r["jump_op"][b, 0] == 0
+            after = tl > tau + 1e-12
+            np.testing.assert_allclose(r["expect_traj"][b, 0, after].real, 0.0, atol=1e-14)
+        else:
+            assert r["n_jumps"][b] == 0
+            np.testing.assert_allclose(r["expect_traj"][b, 0].real, 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("which", ["thermal_cavity", "jc_three_channels"])
+def test_mc_ensemble_average_converges_to_master_equation(which):
+    """Averaged over m trajectories the Monte-Carlo expectation values approach
+    the master-equation solution (Sec. 3.2): at every output time the mean
+    lies within 5 standard errors (sample std / sqrt(m)) of the master
+    equation's value, and the mean absolute deviation over the time grid
+    shrinks like m^(-1/2) (the statistical error of an average; the paper's
+    Fig. 5 fits 1/m to a related measure) when m grows 16-fold."""
+    if which == "thermal_cavity":
+        s = S.thermal_cavity_mc()                # paper Fig. 4 parameters, N = 5
+        tl, nsteps = np.linspace(0.0, 0.6, 61), 1200
+    else:
+        s = S.jc_system(3, g=0.5, kappa=0.4, gamma=0.3, n_th=0.2, psi0=(1, 1))
+        s.meta["psi0"] = S.ket(6, 3)
+        tl, nsteps = np.linspace(0.0, 4.0, 41), 2000
+    m_big, m_small = 3200, 200
+    r = oracle.mc(s, s.meta["psi0"], tl, nsteps, S.mc_draws(m_big, 40, 21), n_threads=8)
+    me, _ = oracle.rk4(s, S.ket2dm(s.meta["psi0"]), tl, nsteps)
+    for mi in range(len(s.E)):
+        x = r["expect_traj"][:, mi].real
+        se = x.std(axis=0) / np.sqrt(m_big) + 1e-12
+        assert np.all(np.abs(x.mean(axis=0) - me[mi].real) <= 5 * se + 1e-10)
+        # error of 16 independent small ensembles vs the big one: ~ 4x larger
+        small = x.reshape(16, m_small, -1).mean(axis=1)
+        err_small = np.mean(np.abs(small - me[mi].real))
+        err_big = np.mean(np.abs(x.mean(axis=0) - me[mi].real))
+        assert 1.5 < err_small / max(err_big, 1e-12) < 12
+    np.testing.assert_allclose(r["expect"], r["expect_traj"].mean(axis=0), atol=1e-13)
+
+
+def test_mc_runs_out_of_draws():
+    s = S.thermal_cavity_mc()
+    d = S.mc_draws(4, 0, 3)
+    d[:, :, 0] = 0.999                       # every trajectory jumps almost at once
+    r = oracle.mc(s, s.meta["psi0"], np.array([0.0, 0.6]), 600, d, raise_on_error=False)
+    assert r["rc"] == oracle.EDRAWS and (r["status"] == oracle.EDRAWS).all()
