@@ -188,7 +188,8 @@ void lme_default_options(lme_options *opt);
  *           (NULL = all zero); lme_evolve may override them per call.
  * Builds the operator tables (A = -iH0 - 1/2 sum_k C_k^+ C_k, the control
  * terms -iH_j, the jump tables and their adjoints) and uploads them to the
- * current HIP device.  *out receives the handle (NULL on failure).
+ * current HIP device (on a machine without a device, at the handle's first
+ * device call instead).  *out receives the handle (NULL on failure).
  * Errors: LME_EINVAL, LME_ENOTSUP (an operator row with more than 64
  * non-zeros, or n > 4096), LME_ENOMEM, LME_EHIP. */
 int lme_create_batch(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
@@ -239,6 +240,27 @@ int lme_evolve(lme_handle h, const lme_options *opt, int32_t n_t,
                const double *tlist, const void *rho0_dev, const double *u_dev,
                void *expect_dev, void *states_dev, void *rho_out_dev,
                int64_t *counts_dev, int32_t *status_dev, void *stream);
+
+/* lme_evolve without any device allocation, for callers that cannot
+ * allocate device memory during a call: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * and errors as lme_evolve (bit for bit: the same kernels run), restricted
+ * to the resident kernels (LME_ENOTSUP for path = LME_PATH_STREAMED or a
+ * batch the automatic path would stream).  The step or stop tables, the pack
+ * tables and, with LME_DOPRI5, the stage derivatives (112 bytes per state
+ * element) live in one library-owned device array of 64 MiB per GPU instead
+ * of handle-owned buffers; a call that needs more returns LME_ENOTSUP before
+ * any device work.  The tables are copied into the array with
+ * hipMemcpyAsync on `stream` from a host image the handle keeps until its
+ * next such call.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or host threads) race; calls queued
+ * on one stream are ordered.  The handle must have been created while a
+ * device was present (its operators are uploaded at create then);
+ * LME_EINVAL otherwise. */
+int lme_evolve_noalloc(lme_handle h, const lme_options *opt, int32_t n_t,
+                       const double *tlist, const void *rho0_dev, const double *u_dev,
+                       void *expect_dev, void *states_dev, void *rho_out_dev,
+                       int64_t *counts_dev, int32_t *status_dev, void *stream);
 
 /* One application of the Liouvillian (Eq. (master_equation)) or, with
  * adjoint != 0, of its adjoint under the Hilbert-Schmidt inner product

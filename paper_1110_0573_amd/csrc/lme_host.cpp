@@ -68,6 +68,7 @@ extern "C" hipError_t lme_internal_launch_apply_col(int T, int wo, int nc, int n
 extern "C" hipError_t lme_internal_launch_apply_shape(int wo, int nc, int nb, int re,
                                                       const lme::ApplyArgs *a, int n_packs,
                                                       int lds, hipStream_t s);
+extern "C" hipError_t lme_internal_noalloc_scratch(void **ptr, size_t *bytes);
 extern "C" hipError_t lme_internal_launch_apply_lds(const lme::ApplyArgs *a, int n_packs,
                                                     int lds, hipStream_t s);
 
@@ -216,6 +217,7 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 struct Plan {
   int T = 0, EPT = 0, adjoint = 0, cap = 0, column = 0, dp = 0, lds_budget = 0;
+  bool uploaded = false;   // d_packs / d_order hold the tables
   std::vector<PackDesc> packs;
   std::vector<int32_t> order;
   int max_lds = 0;
@@ -276,6 +278,9 @@ struct lme_ctx {
   hipGraphExec_t gexec = nullptr;
   std::vector<uint8_t> gkey;
   lme_tuning tuning = {0, 0, 0, 0, 0.0, 0.0};
+  // lme_evolve_noalloc: host image of the tables it copies into the scratch
+  // array (kept until the next such call on this handle)
+  std::vector<uint8_t> na_host;
   ~lme_ctx() {
     for (Plan *p : plans) delete p;
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -372,6 +377,8 @@ extern "C" void lme_default_options(lme_options *opt) {
 }
 
 extern "C" const char *lme_last_error(void) { return g_err.c_str(); }
+
+static int ensure_device(lme_ctx *h);
 
 static int create_impl(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl, int32_t n_e,
                        const lme_segments *seg, const double *u_host, lme_handle *out) {
@@ -512,6 +519,15 @@ static int create_impl(int32_t n_inst, const lme_instance *inst, int32_t n_ctrl,
     h->u_default.assign((size_t)n_inst * n_ctrl * n_seg, 0.0);
     if (u_host) std::memcpy(h->u_default.data(), u_host, h->u_default.size() * sizeof(double));
   }
+  // With a device present, bind it and upload the operator tables now (a
+  // machine without one defers this to the first device call).
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) == hipSuccess && n_dev > 0) {
+    const int rc = ensure_device(h);
+    if (rc) return rc;
+  } else {
+    (void)hipGetLastError();
+  }
   *out = guard.release();
   return LME_OK;
 }
@@ -594,11 +610,25 @@ static int ensure_device(lme_ctx *h) {
 // row data lives in registers).
 static int real_structure(const lme_ctx *h);
 
+static int upload_plan(Plan *p) {
+  int rc;
+  if ((rc = p->d_packs.upload(p->packs.data(), p->packs.size() * sizeof(PackDesc), "packs"))) return rc;
+  if ((rc = p->d_order.upload(p->order.data(), p->order.size() * sizeof(int32_t), "order"))) return rc;
+  p->uploaded = true;
+  return LME_OK;
+}
+
+// upload = false: the host tables only (lme_evolve_noalloc copies them into
+// its scratch array); a later call with upload = true uploads a cached plan.
 static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int column, int dp,
-                      Plan **out, int lds_budget = 0) {
+                      Plan **out, int lds_budget = 0, bool upload = true) {
   for (Plan *p : h->plans)
     if (p->T == T && p->EPT == EPT && p->adjoint == adjoint && p->cap == cap &&
         p->column == column && p->dp == dp && p->lds_budget == lds_budget) {
+      if (upload && !p->uploaded) {
+        const int rc = upload_plan(p);
+        if (rc) return rc;
+      }
       *out = p;
       return LME_OK;
     }
@@ -771,11 +801,54 @@ static int plan_packs(lme_ctx *h, int T, int EPT, int adjoint, int cap, int colu
                     q.m, q.G, q.ept);
     }
   }
-  int rc;
-  if ((rc = p->d_packs.upload(p->packs.data(), p->packs.size() * sizeof(PackDesc), "packs"))) return rc;
-  if ((rc = p->d_order.upload(p->order.data(), p->order.size() * sizeof(int32_t), "order"))) return rc;
+  if (upload) {
+    const int rc = upload_plan(p.get());
+    if (rc) return rc;
+  }
   *out = p.get();
   h->plans.push_back(p.release());
+  return LME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lme_evolve_noalloc: tables and stage derivatives in the scratch array
+// ---------------------------------------------------------------------------
+// Scratch layout: [tables | packs | order | stage derivatives], each part
+// 256-byte aligned.  The host part is assembled in h->na_host and copied with
+// one hipMemcpyAsync on the caller's stream.
+struct NoAlloc {
+  uint8_t *base = nullptr;
+  size_t cap = 0;
+  size_t packs_off = 0, order_off = 0, kbuf_off = 0, total = 0;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int noalloc_stage(lme_ctx *h, const void *tab, size_t tab_bytes, const Plan *plan,
+                         size_t kbuf_bytes, hipStream_t s, NoAlloc *na) {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipError_t e = lme_internal_noalloc_scratch(&p, &cap);
+  if (e != hipSuccess) return hip_fail(e, "scratch array address");
+  na->base = static_cast<uint8_t *>(p);
+  na->cap = cap;
+  na->packs_off = align256(tab_bytes);
+  na->order_off = align256(na->packs_off + plan->packs.size() * sizeof(PackDesc));
+  const size_t host_end = na->order_off + plan->order.size() * sizeof(int32_t);
+  na->kbuf_off = align256(host_end);
+  na->total = na->kbuf_off + kbuf_bytes;
+  if (na->total > cap)
+    return fail(LME_ENOTSUP, "lme_evolve_noalloc needs %zu bytes of scratch; its array holds %zu "
+                "(the adaptive stepper's stage derivatives take 112 bytes per state element)",
+                na->total, cap);
+  h->na_host.assign(host_end, 0);
+  std::memcpy(h->na_host.data(), tab, tab_bytes);
+  std::memcpy(h->na_host.data() + na->packs_off, plan->packs.data(),
+              plan->packs.size() * sizeof(PackDesc));
+  std::memcpy(h->na_host.data() + na->order_off, plan->order.data(),
+              plan->order.size() * sizeof(int32_t));
+  e = hipMemcpyAsync(na->base, h->na_host.data(), host_end, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "copy tables into the scratch array");
   return LME_OK;
 }
 
@@ -1169,7 +1242,7 @@ static int evolve_rk4_streamed(lme_ctx *h, int32_t n_t, int32_t nsteps, double h
 static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
                       const void *rho0_dev, const double *u_dev, void *expect_dev,
                       void *states_dev, void *rho_out_dev, int64_t *counts_dev,
-                      int32_t *status_dev, void *stream) {
+                      int32_t *status_dev, void *stream, bool noalloc) {
   if (!(opt->rtol > 0.0) || !std::isfinite(opt->rtol) || !(opt->atol >= 0.0) ||
       !std::isfinite(opt->atol))
     return fail(LME_EINVAL, "DOPRI5 needs rtol > 0 and atol >= 0, finite");
@@ -1212,36 +1285,55 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   // 16-row variant keeps fewer operands in registers and is not faster than
   // the row kernel
   if (opt->layout == LME_LAYOUT_AUTO && col_ept == 16) col_ept = 0;
+  if (noalloc && streamed && !col_ept)
+    return fail(LME_ENOTSUP, "lme_evolve_noalloc runs the resident kernels only; this batch "
+                "needs the streamed adaptive path");
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (noalloc && !h->on_device)
+    return fail(LME_EINVAL, "the handle was created without a device: its operators are not on "
+                "a GPU");
   if ((rc = ensure_device(h))) return rc;
   // tables: [stops | out_idx | seg], content-cached
-  std::vector<double> key(stops);
-  key.push_back((double)n_t);
-  for (int k = 0; k < n_t; ++k) key.push_back(tlist[k]);
   const size_t ns = stops.size();
-  if (key != h->stops_key || !h->d_stops.p) {
-    std::vector<uint8_t> buf(ns * 8 + 2 * ns * 4 + 16, 0);
-    std::memcpy(buf.data(), stops.data(), ns * 8);
-    std::memcpy(buf.data() + ns * 8, out_idx.data(), ns * 4);
-    std::memcpy(buf.data() + ns * 12, seg.data(), ns * 4);
-    if ((rc = h->d_stops.upload(buf.data(), buf.size(), "stop tables"))) return rc;
-    h->stops_key.swap(key);
+  std::vector<uint8_t> buf(ns * 8 + 2 * ns * 4 + 16, 0);
+  std::memcpy(buf.data(), stops.data(), ns * 8);
+  std::memcpy(buf.data() + ns * 8, out_idx.data(), ns * 4);
+  std::memcpy(buf.data() + ns * 12, seg.data(), ns * 4);
+  if (!noalloc) {
+    std::vector<double> key(stops);
+    key.push_back((double)n_t);
+    for (int k = 0; k < n_t; ++k) key.push_back(tlist[k]);
+    if (key != h->stops_key || !h->d_stops.p) {
+      if ((rc = h->d_stops.upload(buf.data(), buf.size(), "stop tables"))) return rc;
+      h->stops_key.swap(key);
+    }
   }
   Plan *plan = nullptr;
   if (col_ept) {
     streamed = false;
-    if ((rc = plan_packs(h, col_T(col_ept), col_ept, 0, col_T(col_ept) * col_ept, 1, 1, &plan)))
+    if ((rc = plan_packs(h, col_T(col_ept), col_ept, 0, col_T(col_ept) * col_ept, 1, 1, &plan, 0,
+                         !noalloc)))
       return rc;
   } else if (!streamed) {
-    rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan);
-    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)
+    rc = plan_packs(h, 512, EPT, 0, 512 * EPT, 0, 1, &plan, 0, !noalloc);
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !noalloc)
       streamed = true;  // a pack does not fit in LDS
     else if (rc)
       return rc;
   }
+  NoAlloc na;
+  const uint8_t *tb = static_cast<const uint8_t *>(h->d_stops.p);
+  double *kbuf = static_cast<double *>(h->d_kbuf.p);
+  if (noalloc) {
+    if ((rc = noalloc_stage(h, buf.data(), buf.size(), plan, (size_t)7 * h->state_elems * 16, s,
+                            &na)))
+      return rc;
+    tb = na.base;
+    kbuf = reinterpret_cast<double *>(na.base + na.kbuf_off);
+  }
 
-  if (!streamed) {
+  if (!streamed && !noalloc) {
     const size_t kbytes = (size_t)7 * h->state_elems * 16;
     if (h->d_kbuf.bytes < kbytes) {
       h->d_kbuf.release();
@@ -1252,12 +1344,17 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
       }
       h->d_kbuf.bytes = kbytes;
     }
+    kbuf = static_cast<double *>(h->d_kbuf.p);
   }
 
   lme::Dp5Args a;
   std::memset(&a, 0, sizeof a);
   a.packs = plan ? static_cast<const PackDesc *>(plan->d_packs.p) : nullptr;
   a.order = plan ? static_cast<const int32_t *>(plan->d_order.p) : nullptr;
+  if (noalloc) {
+    a.packs = reinterpret_cast<const PackDesc *>(na.base + na.packs_off);
+    a.order = reinterpret_cast<const int32_t *>(na.base + na.order_off);
+  }
   a.inst = static_cast<const InstDesc *>(h->d_inst.p);
   a.ops = static_cast<const uint8_t *>(h->d_ops.p);
   a.eops = static_cast<const uint8_t *>(h->d_eops.p);
@@ -1266,7 +1363,6 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   a.n_seg = h->n_seg;
   a.n_e = h->n_e;
   a.n_t = n_t;
-  const uint8_t *tb = static_cast<const uint8_t *>(h->d_stops.p);
   a.stops = reinterpret_cast<const double *>(tb);
   a.stop_out = reinterpret_cast<const int32_t *>(tb + ns * 8);
   a.stop_seg = reinterpret_cast<const int32_t *>(tb + ns * 12);
@@ -1278,7 +1374,7 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   a.h_min = opt->h_min;
   a.max_steps = opt->max_steps;
   a.state_elems = h->state_elems;
-  a.kbuf = static_cast<double *>(h->d_kbuf.p);
+  a.kbuf = kbuf;
   a.rho0 = static_cast<const double *>(rho0_dev);
   a.rho_out = static_cast<double *>(rho_out_dev);
   a.states = static_cast<double *>(states_dev);
@@ -1299,7 +1395,7 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
 static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
                        const void *rho0_dev, const double *u_dev, void *expect_dev,
                        void *states_dev, void *rho_out_dev, int64_t *counts_dev,
-                       int32_t *status_dev, void *stream) {
+                       int32_t *status_dev, void *stream, bool noalloc) {
   if (!h) return fail(LME_EINVAL, "handle is NULL");
   if (!opt) return fail(LME_EINVAL, "options are NULL");
   if (!rho0_dev) return fail(LME_EINVAL, "rho0 is NULL");
@@ -1316,7 +1412,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     return fail(LME_EINVAL, "unknown layout %d", opt->layout);
   if (opt->method == LME_DOPRI5)
     return evolve_dp5(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
-                      counts_dev, status_dev, stream);
+                      counts_dev, status_dev, stream, noalloc);
   if (opt->method != LME_RK4) return fail(LME_EINVAL, "unknown method %d", opt->method);
   if (n_t > 1 && opt->nsteps < 1) return fail(LME_EINVAL, "RK4 needs nsteps >= 1");
   const int32_t nsteps = n_t > 1 ? opt->nsteps : 0;
@@ -1356,21 +1452,26 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     if (opt->block == 768) return fail(LME_EINVAL, "block 768 exists only in the column layout");
     // the row layout has no Hermitian variant: it computes every element
     rc = pick_rk4_config(h, opt->block, &T, &EPT);
-    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO)
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !noalloc)
       streamed = true;  // an instance is too large for a resident workgroup
     else if (rc)
       return rc;
   }
+  if (noalloc && streamed)
+    return fail(LME_ENOTSUP, "lme_evolve_noalloc runs the resident kernels only");
+  if (noalloc && !h->on_device)
+    return fail(LME_EINVAL, "the handle was created without a device: its operators are not on "
+                "a GPU");
 
   // validation done: from here on the device is used
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((rc = ensure_device(h))) return rc;
-  if ((rc = upload_tables(h, tab, s))) return rc;
+  if (!noalloc && (rc = upload_tables(h, tab, s))) return rc;
   hipError_t e;
   Plan *plan = nullptr;
   if (!streamed) {
-    rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan);
-    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !column)
+    rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan, 0, !noalloc);
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !column && !noalloc)
       streamed = true;
     else if (rc)
       return rc;
@@ -1378,6 +1479,10 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   if (streamed)
     return evolve_rk4_streamed(h, n_t, nsteps, hstep, u_dev, rho0_dev, expect_dev, states_dev,
                                rho_out_dev, counts_dev, status_dev, s);
+  NoAlloc na;
+  if (noalloc &&
+      (rc = noalloc_stage(h, tab.data(), tab.size() * sizeof(int32_t), plan, 0, s, &na)))
+    return rc;
 
   lme::Rk4Args a;
   std::memset(&a, 0, sizeof a);
@@ -1394,6 +1499,12 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   a.n_t = n_t;
   a.seg_of_step = static_cast<const int32_t *>(h->d_steps.p);
   a.out_step = static_cast<const int32_t *>(h->d_steps.p) + nsteps;
+  if (noalloc) {
+    a.packs = reinterpret_cast<const PackDesc *>(na.base + na.packs_off);
+    a.order = reinterpret_cast<const int32_t *>(na.base + na.order_off);
+    a.seg_of_step = reinterpret_cast<const int32_t *>(na.base);
+    a.out_step = reinterpret_cast<const int32_t *>(na.base) + nsteps;
+  }
   a.nsteps = nsteps;
   a.h = hstep;
   a.state_elems = h->state_elems;
@@ -1418,7 +1529,21 @@ extern "C" int lme_evolve(lme_handle h, const lme_options *opt, int32_t n_t, con
                           int32_t *status_dev, void *stream) {
   try {
     return evolve_impl(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
-                       counts_dev, status_dev, stream);
+                       counts_dev, status_dev, stream, false);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+extern "C" int lme_evolve_noalloc(lme_handle h, const lme_options *opt, int32_t n_t,
+                                  const double *tlist, const void *rho0_dev, const double *u_dev,
+                                  void *expect_dev, void *states_dev, void *rho_out_dev,
+                                  int64_t *counts_dev, int32_t *status_dev, void *stream) {
+  try {
+    return evolve_impl(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
+                       counts_dev, status_dev, stream, true);
   } catch (const std::bad_alloc &) {
     return fail(LME_ENOMEM, "out of host memory");
   } catch (...) {
@@ -2122,7 +2247,7 @@ static int autotune_impl(lme_handle h, const lme_options *opt, const void *rho0_
     o.block = c.block;
     float ms = 0.0f;
     rc = time_ms([&]() { return evolve_impl(h, &o, 2, tl, rho0_dev, nullptr, nullptr, nullptr,
-                                            out.p, nullptr, nullptr, stream); }, 2, &ms);
+                                            out.p, nullptr, nullptr, stream, false); }, 2, &ms);
     if (rc == LME_ENOTSUP || rc == LME_EINVAL || rc == LME_EGRID) continue;  // not eligible
     if (rc) {
       h->tuning = saved;

@@ -28,8 +28,8 @@ LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
-           "lme_last_error", "lme_layout", "lme_evolve", "lme_apply", "lme_cost_grad",
-           "lme_get_tuning", "lme_set_tuning", "lme_autotune"]
+           "lme_last_error", "lme_layout", "lme_evolve", "lme_evolve_noalloc", "lme_apply",
+           "lme_cost_grad", "lme_get_tuning", "lme_set_tuning", "lme_autotune"]
 
 
 class LmeError(RuntimeError):
@@ -89,6 +89,7 @@ def load():
         lib.lme_evolve.argtypes = [H, C.POINTER(Options), C.c_int32, _PD, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.lme_evolve_noalloc.argtypes = lib.lme_evolve.argtypes
         lib.lme_apply.argtypes = [H, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p]
         lib.lme_cost_grad.argtypes = [H, C.c_int32, C.c_int32, C.c_double, C.c_double,
@@ -279,9 +280,10 @@ class Handle:
     def evolve(self, rho0, tlist, method="rk4", nsteps=0, rtol=1e-6, atol=1e-9, h0=0.0,
                h_min=0.0, max_steps=10**7, path=LME_PATH_AUTO, block=0, layout=0, u=None,
                want_expect=True, want_states=False, want_rho=True, hermitian=False,
-               stream=None):
-        """Runs lme_evolve.  rho0: complex128 device tensor [state_elems].
-        hermitian: rho0 is Hermitian (options.hermitian).
+               stream=None, noalloc=False):
+        """Runs lme_evolve (lme_evolve_noalloc with ``noalloc``).  rho0:
+        complex128 device tensor [state_elems].  hermitian: rho0 is Hermitian
+        (options.hermitian).
         Returns a dict of device tensors (expect, states, rho, counts, status)."""
         import torch
         self._check_state(rho0, "rho0")
@@ -303,11 +305,12 @@ class Handle:
                       if want_rho else None)
         out["counts"] = torch.zeros((self.n_inst, 2), dtype=torch.int64, device=dev)
         out["status"] = torch.full((self.n_inst,), -1, dtype=torch.int32, device=dev)
-        rc = load().lme_evolve(self._h, C.byref(opt), n_t, tl.ctypes.data_as(_PD),
-                               _ptr(rho0), _ptr(u), _ptr(out["expect"]), _ptr(out["states"]),
-                               _ptr(out["rho"]), _ptr(out["counts"]), _ptr(out["status"]),
-                               _stream_ptr(stream))
-        _check(rc, "lme_evolve")
+        fn = load().lme_evolve_noalloc if noalloc else load().lme_evolve
+        rc = fn(self._h, C.byref(opt), n_t, tl.ctypes.data_as(_PD),
+                _ptr(rho0), _ptr(u), _ptr(out["expect"]), _ptr(out["states"]),
+                _ptr(out["rho"]), _ptr(out["counts"]), _ptr(out["status"]),
+                _stream_ptr(stream))
+        _check(rc, "lme_evolve_noalloc" if noalloc else "lme_evolve")
         return out
 
     def autotune(self, rho0, nsteps, hermitian=False, stream=None):
