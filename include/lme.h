@@ -62,8 +62,10 @@ typedef enum lme_status {
   LME_ENOMEM = 6,          /* host or device allocation failed                */
   LME_EHIP = 7,            /* a HIP runtime call failed (no device, launch)   */
   LME_ENOTSUP = 8,         /* valid input outside what this build supports    */
-  LME_ENOTHERM = 9         /* hermitian option with a non-Hermitian rho0 of
+  LME_ENOTHERM = 9,        /* hermitian option with a non-Hermitian rho0 of
                               that instance (device, per instance)            */
+  LME_EDRAWS = 10          /* Monte-Carlo: a trajectory needed more jumps than
+                              its random draws cover (device, per trajectory)*/
 } lme_status;
 
 typedef struct lme_ctx *lme_handle;
@@ -338,6 +340,64 @@ int lme_set_tuning(lme_handle h, const lme_tuning *t);
  * Errors as lme_evolve. */
 int lme_autotune(lme_handle h, const lme_options *opt, const void *rho0_dev, void *stream,
                  lme_tuning *result);
+
+/* ---------------------------------------------------------------------------
+ * Monte-Carlo wave-function trajectories (Sec. 3.2, steps I-IV).
+ *
+ * Each trajectory evolves a ket under the non-Hermitian effective Hamiltonian
+ * of Eq. (heff), d psi/dt = -i H_eff psi with H_eff = H - (i/2) sum_n C_n^+ C_n,
+ * until its squared norm falls to the drawn number r (step II); it then jumps
+ * with the collapse operator C_k for the smallest k with
+ * P_1 + ... + P_k >= r' (Eqs. (pcn), (mc3); r' is a second, independent
+ * draw), P_i = <psi|C_i^+ C_i|psi> / sum_j <psi|C_j^+ C_j|psi>, is
+ * renormalised (Eq. (project)) and continues with the next draw (step IV).
+ * The paper names no integrator: classic RK4 on the uniform grid
+ * h = (tlist[n_t-1] - tlist[0]) / nsteps (every output time on the grid,
+ * LME_EGRID otherwise); between grid points the state is the RK4 step of the
+ * partial length, and the jump time solves |psi(tau)|^2 = r on it.
+ * --------------------------------------------------------------------------- */
+typedef struct lme_mc_ctx *lme_mc_handle;
+
+/* One system for Monte-Carlo trajectories: Hamiltonian H (n x n, n <= 8192),
+ * n_c <= 16 collapse operators C[n_c] and n_e expectation operators E[n_e]
+ * (host CSR, copied; Sec. 4.3 passes the same arguments as the master
+ * equation solver).  Builds -i H_eff as diagonal + ELL tables, the collapse
+ * and expectation operators as ELL tables, and uploads them to the current
+ * device (at the first device call on a machine without one).
+ * Errors: LME_EINVAL, LME_ENOTSUP (n, row widths > 64, n_c), LME_ENOMEM,
+ * LME_EHIP. */
+int lme_mc_create(const lme_csr *H, int32_t n_c, const lme_csr *C, int32_t n_e,
+                  const lme_csr *E, lme_mc_handle *out);
+
+/* Releases the handle and its device buffers.  NULL is a no-op. */
+void lme_mc_destroy(lme_mc_handle h);
+
+/* n_traj trajectories from psi0 (device complex128 [n], normalised by the
+ * call) over tlist (host, strictly increasing, n_t >= 1, tlist[0] the
+ * initial time) in nsteps RK4 steps.
+ *   draws_dev: device double [n_traj][max_jumps + 1][2], uniform numbers in
+ *              [0, 1): entry [b][j][0] is the threshold r of trajectory b's
+ *              j-th waiting period, [b][j][1] the number r' that chooses the
+ *              collapse operator of its j-th jump.  A trajectory that needs
+ *              more than max_jumps jumps stops with status LME_EDRAWS.
+ * outputs (device; each may be NULL):
+ *   expect_dev:      complex128 [n_e][n_t], the mean over trajectories of
+ *                    <psi|E_m|psi> / <psi|psi> (summed in trajectory order);
+ *   expect_traj_dev: complex128 [n_traj][n_e][n_t], each trajectory's values
+ *                    (a stopped trajectory's later values are 0);
+ *   n_jumps_dev:     int32 [n_traj];
+ *   jump_t_dev, jump_op_dev: double / int32 [n_traj][max_jumps], time and
+ *                    collapse-operator index of every jump;
+ *   status_dev:      int32 [n_traj], LME_OK, LME_EDRAWS or LME_ENONFINITE.
+ * The handle owns a scratch of 64 n bytes per trajectory slot in flight (the
+ * Taylor vectors of a step with a jump) and, when expect_traj_dev is NULL,
+ * the per-trajectory outputs.  Asynchronous on `stream`.
+ * Host-side errors: LME_EINVAL, LME_EGRID, LME_ENOTSUP, LME_ENOMEM, LME_EHIP. */
+int lme_mc_evolve(lme_mc_handle h, int32_t n_t, const double *tlist, int32_t nsteps,
+                  const void *psi0_dev, int32_t n_traj, const double *draws_dev,
+                  int32_t max_jumps, void *expect_dev, void *expect_traj_dev,
+                  int32_t *n_jumps_dev, double *jump_t_dev, int32_t *jump_op_dev,
+                  int32_t *status_dev, void *stream);
 
 #ifdef __cplusplus
 }

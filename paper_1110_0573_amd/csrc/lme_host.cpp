@@ -2328,3 +2328,273 @@ extern "C" int lme_autotune(lme_handle h, const lme_options *opt, const void *rh
     return fail(LME_EINVAL, "unexpected host exception");
   }
 }
+
+// ---------------------------------------------------------------------------
+// Monte-Carlo wave-function trajectories (Sec. 3.2)
+// ---------------------------------------------------------------------------
+extern "C" int lme_internal_mc_rows(int *rows, int *max_threads, int cap);
+extern "C" int lme_internal_mc_lds_bytes(int T, int P, int n);
+extern "C" hipError_t lme_internal_launch_mc(int R, const lme::McArgs *a, int grid, int lds,
+                                             hipStream_t s);
+extern "C" hipError_t lme_internal_launch_mc_average(const double *ex_traj, double *expect,
+                                                     int n_traj, int per, hipStream_t s);
+
+struct lme_mc_ctx {
+  int n = 0, wo = 0, nc = 0, wc = 0, ne = 0, we = 0;
+  lme::McLayout L;
+  std::vector<uint8_t> tabs;   // operator tables (layout lme::mc_layout), host image
+  int device = 0, lds_limit = 0, n_cu = 0;
+  bool on_device = false;
+  DevBuf d_tabs, d_out, d_ex, d_vbuf;
+  std::vector<int32_t> out_key;
+};
+
+static int mc_ensure_device(lme_mc_ctx *h) {
+  hipError_t e;
+  if (h->on_device) {
+    e = hipSetDevice(h->device);
+    return e == hipSuccess ? LME_OK : hip_fail(e, "hipSetDevice");
+  }
+  if ((e = hipGetDevice(&h->device)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if ((e = hipDeviceGetAttribute(&h->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                 h->device)) != hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute(LDS)");
+  if ((e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device)) !=
+      hipSuccess)
+    return hip_fail(e, "hipDeviceGetAttribute(CUs)");
+  int rc = h->d_tabs.upload(h->tabs.data(), h->tabs.size(), "Monte-Carlo operator tables");
+  if (rc) return rc;
+  h->on_device = true;
+  return LME_OK;
+}
+
+static int mc_create_impl(const lme_csr *H, int32_t n_c, const lme_csr *C, int32_t n_e,
+                          const lme_csr *E, lme_mc_handle *out) {
+  if (!out) return fail(LME_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!H) return fail(LME_EINVAL, "H is NULL");
+  const int n = H->n;
+  if (n < 1) return fail(LME_EINVAL, "n must be >= 1");
+  if (n > lme::kMcMaxDim) return fail(LME_ENOTSUP, "n=%d exceeds %d", n, lme::kMcMaxDim);
+  if (n_c < 0 || (n_c > 0 && !C)) return fail(LME_EINVAL, "bad collapse-operator list");
+  if (n_c > lme::kMcMaxNC) return fail(LME_ENOTSUP, "at most %d collapse operators", lme::kMcMaxNC);
+  if (n_e < 0 || (n_e > 0 && !E)) return fail(LME_EINVAL, "bad expectation-operator list");
+  Sparse Hs;
+  int rc = check_csr(H, n, "H", 0, &Hs);
+  if (rc) return rc;
+  std::vector<Sparse> Cs(n_c), Es(n_e);
+  for (int k = 0; k < n_c; ++k)
+    if ((rc = check_csr(&C[k], n, "C", 0, &Cs[k]))) return rc;
+  for (int m = 0; m < n_e; ++m)
+    if ((rc = check_csr(&E[m], n, "E", 0, &Es[m]))) return rc;
+  // A = -i H_eff = -i H - 1/2 sum_k C_k^+ C_k  (Eq. (heff), hbar = 1)
+  Sparse A(n);
+  A.axpy(cd(0.0, -1.0), Hs);
+  for (auto &c : Cs) A.axpy(cd(-0.5, 0.0), dag_times_self(c));
+  A.finalize();
+  std::unique_ptr<lme_mc_ctx> h(new (std::nothrow) lme_mc_ctx);
+  if (!h) return fail(LME_ENOMEM, "out of host memory");
+  h->n = n;
+  h->wo = A.width_offdiag();
+  h->nc = n_c;
+  h->ne = n_e;
+  for (auto &c : Cs) h->wc = std::max(h->wc, c.width());
+  for (auto &m : Es) h->we = std::max(h->we, m.width());
+  if (h->wo > lme::kMaxWidth || h->wc > lme::kMaxWidth || h->we > lme::kMaxWidth)
+    return fail(LME_ENOTSUP, "an operator row has more than %d non-zeros", lme::kMaxWidth);
+  h->L = lme::mc_layout(n, h->wo, h->nc, h->wc, h->ne, h->we);
+  if (h->L.bytes > (int64_t)1 << 31) return fail(LME_ENOTSUP, "operator tables exceed 2 GiB");
+  h->tabs.assign((size_t)h->L.bytes, 0);
+  auto put_c = [&](int64_t off, const std::vector<cd> &v) {
+    std::memcpy(h->tabs.data() + off, v.data(), v.size() * sizeof(cd));
+  };
+  auto put_i = [&](int64_t off, const std::vector<int32_t> &v) {
+    std::memcpy(h->tabs.data() + off, v.data(), v.size() * sizeof(int32_t));
+  };
+  put_c(h->L.offD, diag_of(A));
+  Ell o = to_ell(A, h->wo, true);
+  put_c(h->L.offOval, o.val);
+  put_i(h->L.offOcol, o.col);
+  for (int k = 0; k < n_c; ++k) {
+    Ell e = to_ell(Cs[k], h->wc, false);
+    put_c(h->L.offJval + 16LL * k * h->wc * n, e.val);
+    put_i(h->L.offJcol + 4LL * k * h->wc * n, e.col);
+  }
+  for (int m = 0; m < n_e; ++m) {
+    Ell e = to_ell(Es[m], h->we, false);
+    put_c(h->L.offEval + 16LL * m * h->we * n, e.val);
+    put_i(h->L.offEcol + 4LL * m * h->we * n, e.col);
+  }
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) == hipSuccess && n_dev > 0) {
+    if ((rc = mc_ensure_device(h.get()))) return rc;
+  } else {
+    (void)hipGetLastError();
+  }
+  *out = h.release();
+  return LME_OK;
+}
+
+extern "C" int lme_mc_create(const lme_csr *H, int32_t n_c, const lme_csr *C, int32_t n_e,
+                             const lme_csr *E, lme_mc_handle *out) {
+  try {
+    return mc_create_impl(H, n_c, C, n_e, E, out);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+extern "C" void lme_mc_destroy(lme_mc_handle h) { delete h; }
+
+// Work decomposition: G threads (a power of two) per trajectory with R rows
+// each (R a compiled row count, G * P within the kernel's largest workgroup),
+// about five rows per thread; P trajectories per workgroup, bounded by LDS,
+// enough workgroups for every CU when the trajectories allow it.
+static int mc_plan(const lme_mc_ctx *h, int n_traj, int *R, int *G, int *P) {
+  int rows[32], maxT[32];
+  const int nr = lme_internal_mc_rows(rows, maxT, 32);
+  const int n = h->n;
+  *R = 0;
+  for (int i = 0; i < nr && !*R; ++i) {
+    if (rows[i] < std::min(n, 5)) continue;
+    int g = 1;
+    while (g * rows[i] < n) g <<= 1;
+    // the smallest power of two covering n with rows[i] rows per thread
+    if (g <= maxT[i]) {
+      *R = rows[i];
+      *G = g;
+      int Pmax = maxT[i] / g;
+      while (Pmax > 0 && lme_internal_mc_lds_bytes(Pmax * g, Pmax, n) > h->lds_limit) --Pmax;
+      if (Pmax < 1) {
+        *R = 0;
+        continue;
+      }
+      const int want = std::max((64 + g - 1) / g, (n_traj + 2 * h->n_cu - 1) / (2 * h->n_cu));
+      *P = std::max(1, std::min({Pmax, want, n_traj}));
+    }
+  }
+  if (!*R)
+    return fail(LME_ENOTSUP, "dimension %d does not fit the Monte-Carlo workgroup (%d B LDS)", n,
+                h->lds_limit);
+  return LME_OK;
+}
+
+static int mc_evolve_impl(lme_mc_handle h, int32_t n_t, const double *tlist, int32_t nsteps,
+                          const void *psi0_dev, int32_t n_traj, const double *draws_dev,
+                          int32_t max_jumps, void *expect_dev, void *expect_traj_dev,
+                          int32_t *n_jumps_dev, double *jump_t_dev, int32_t *jump_op_dev,
+                          int32_t *status_dev, void *stream) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  int rc = check_times(n_t, tlist);
+  if (rc) return rc;
+  if (!psi0_dev || !draws_dev) return fail(LME_EINVAL, "psi0 and draws are required");
+  if (n_traj < 1) return fail(LME_EINVAL, "n_traj must be >= 1");
+  if (max_jumps < 0) return fail(LME_EINVAL, "max_jumps must be >= 0");
+  if ((int64_t)n_traj * (max_jumps + 1) * 2 > ((int64_t)1 << 31))
+    return fail(LME_ENOTSUP, "the draws table exceeds 2^31 numbers");
+  if (n_t > 1 && nsteps < 1) return fail(LME_EINVAL, "need nsteps >= 1");
+  const int32_t ns = n_t > 1 ? nsteps : 0;
+  const double hstep = n_t > 1 ? (tlist[n_t - 1] - tlist[0]) / nsteps : 0.0;
+  std::vector<int32_t> out_step(n_t, 0);
+  for (int k = 1; k < n_t; ++k) {
+    const long m = grid_index(tlist[k], tlist[0], hstep);
+    if (m < 0 || m > ns)
+      return fail(LME_EGRID, "output time %.17g is not on the RK4 grid (h = %.17g)", tlist[k],
+                  hstep);
+    out_step[k] = (int32_t)m;
+  }
+  if (n_t > 1 && out_step[n_t - 1] != ns)
+    return fail(LME_EGRID, "last output time is not the end of the grid");
+  // validation done: from here on the device is used
+  if ((rc = mc_ensure_device(h))) return rc;
+  int R = 0, G = 0, P = 0;
+  if ((rc = mc_plan(h, n_traj, &R, &G, &P))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (out_step != h->out_key || !h->d_out.p) {
+    if ((rc = h->d_out.upload(out_step.data(), out_step.size() * sizeof(int32_t), "output steps")))
+      return rc;
+    h->out_key = out_step;
+  }
+  const int n_packs = (n_traj + P - 1) / P;
+  const int grid = std::min(n_packs, 8 * std::max(1, h->n_cu));
+  const size_t per = (size_t)h->ne * n_t;
+  auto ensure = [&](DevBuf &b, size_t bytes, const char *what) -> int {
+    if (b.bytes >= bytes && b.p) return LME_OK;
+    b.release();
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      return fail(LME_ENOMEM, "hipMalloc(%s, %zu B) failed", what, bytes);
+    }
+    b.bytes = bytes;
+    return LME_OK;
+  };
+  double *ex_traj = static_cast<double *>(expect_traj_dev);
+  if (!ex_traj && per > 0) {
+    if ((rc = ensure(h->d_ex, std::max<size_t>(16, 16 * per * n_traj), "trajectory outputs")))
+      return rc;
+    ex_traj = static_cast<double *>(h->d_ex.p);
+  }
+  if ((rc = ensure(h->d_vbuf, (size_t)grid * 64 * P * h->n, "jump scratch"))) return rc;
+
+  const uint8_t *tb = static_cast<const uint8_t *>(h->d_tabs.p);
+  lme::McArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.n = h->n;
+  a.wo = h->wo;
+  a.nc = h->nc;
+  a.wc = h->wc;
+  a.ne = h->ne;
+  a.we = h->we;
+  a.G = G;
+  a.P = P;
+  a.n_traj = n_traj;
+  a.n_t = n_t;
+  a.nsteps = ns;
+  a.max_jumps = max_jumps;
+  a.t0 = tlist[0];
+  a.h = hstep;
+  a.D = reinterpret_cast<const double *>(tb + h->L.offD);
+  a.Oval = reinterpret_cast<const double *>(tb + h->L.offOval);
+  a.Ocol = reinterpret_cast<const int32_t *>(tb + h->L.offOcol);
+  a.Jval = reinterpret_cast<const double *>(tb + h->L.offJval);
+  a.Jcol = reinterpret_cast<const int32_t *>(tb + h->L.offJcol);
+  a.Eval = reinterpret_cast<const double *>(tb + h->L.offEval);
+  a.Ecol = reinterpret_cast<const int32_t *>(tb + h->L.offEcol);
+  a.out_step = static_cast<const int32_t *>(h->d_out.p);
+  a.psi0 = static_cast<const double *>(psi0_dev);
+  a.draws = draws_dev;
+  a.ex_traj = ex_traj;
+  a.n_jumps = n_jumps_dev;
+  a.jump_t = jump_t_dev;
+  a.jump_op = jump_op_dev;
+  a.status = status_dev;
+  a.vbuf = static_cast<double *>(h->d_vbuf.p);
+  const int lds = lme_internal_mc_lds_bytes(P * G, P, h->n);
+  hipError_t e = lme_internal_launch_mc(R, &a, grid, lds, s);
+  if (e != hipSuccess) return hip_fail(e, "launch Monte-Carlo kernel");
+  if (expect_dev && per > 0) {
+    e = lme_internal_launch_mc_average(ex_traj, static_cast<double *>(expect_dev), n_traj,
+                                       (int)per, s);
+    if (e != hipSuccess) return hip_fail(e, "launch trajectory average");
+  }
+  return LME_OK;
+}
+
+extern "C" int lme_mc_evolve(lme_mc_handle h, int32_t n_t, const double *tlist, int32_t nsteps,
+                             const void *psi0_dev, int32_t n_traj, const double *draws_dev,
+                             int32_t max_jumps, void *expect_dev, void *expect_traj_dev,
+                             int32_t *n_jumps_dev, double *jump_t_dev, int32_t *jump_op_dev,
+                             int32_t *status_dev, void *stream) {
+  try {
+    return mc_evolve_impl(h, n_t, tlist, nsteps, psi0_dev, n_traj, draws_dev, max_jumps,
+                          expect_dev, expect_traj_dev, n_jumps_dev, jump_t_dev, jump_op_dev,
+                          status_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}

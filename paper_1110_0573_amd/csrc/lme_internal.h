@@ -158,6 +158,51 @@ struct Rk4Args {
   int32_t *status;          // [n_inst]
 };
 
+// Monte-Carlo wave-function kernel (lme_mc.hip).  Operators of one system:
+// A = -i H - 1/2 sum_n C_n^+ C_n as diagonal D[n] plus ELL off-diagonal
+// Oval/Ocol[wo][n]; collapse operators Jval/Jcol[nc][wc][n]; expectation
+// operators Eval/Ecol[ne][we][n] (ELL padding: value 0, column = row).
+constexpr int kMcMaxNC = 16;     // collapse operators
+constexpr int kMcMaxDim = 8192;  // largest dimension (the kernel's row capacity)
+
+struct McLayout {
+  int64_t offD, offOval, offOcol, offJval, offJcol, offEval, offEcol, bytes;
+};
+
+LME_HD inline McLayout mc_layout(int32_t n, int32_t wo, int32_t nc, int32_t wc, int32_t ne,
+                                 int32_t we) {
+  McLayout L;
+  int64_t o = 0;
+  auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
+  L.offD = o;    o = al(o + 16LL * n);
+  L.offOval = o; o = al(o + 16LL * wo * n);
+  L.offOcol = o; o = al(o + 4LL * wo * n);
+  L.offJval = o; o = al(o + 16LL * nc * wc * n);
+  L.offJcol = o; o = al(o + 4LL * nc * wc * n);
+  L.offEval = o; o = al(o + 16LL * ne * we * n);
+  L.offEcol = o; o = al(o + 4LL * ne * we * n);
+  L.bytes = o;
+  return L;
+}
+
+struct McArgs {
+  int32_t n, wo, nc, wc, ne, we;
+  int32_t G, P;                 // threads per trajectory (2^k), trajectories per workgroup
+  int32_t n_traj, n_t, nsteps, max_jumps;
+  double t0, h;
+  const double *D, *Oval, *Jval, *Eval;   // complex128
+  const int32_t *Ocol, *Jcol, *Ecol;
+  const int32_t *out_step;      // [n_t]: grid step after which output k is due
+  const double *psi0;           // complex128 [n]
+  const double *draws;          // [n_traj][max_jumps + 1][2]
+  double *ex_traj;              // complex128 [n_traj][ne][n_t]
+  int32_t *n_jumps;             // [n_traj] or null
+  double *jump_t;               // [n_traj][max_jumps] or null
+  int32_t *jump_op;             // [n_traj][max_jumps] or null
+  int32_t *status;              // [n_traj] or null
+  double *vbuf;                 // complex128 [gridDim][4][P][n]: Taylor vectors of a jump
+};
+
 // Per-call arguments of the resident Dormand-Prince kernel.
 struct Dp5Args {
   const PackDesc *packs;

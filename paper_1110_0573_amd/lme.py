@@ -8,6 +8,7 @@ raise.
 from __future__ import annotations
 
 import ctypes as C
+import ctypes as C_
 import os
 
 import numpy as np
@@ -17,10 +18,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "liblme.so")
 
 LME_OK, LME_EINVAL, LME_EGRID, LME_EMAXSTEPS, LME_ESTEPUNDERFLOW, LME_ENONFINITE, \
-    LME_ENOMEM, LME_EHIP, LME_ENOTSUP, LME_ENOTHERM = range(10)
+    LME_ENOMEM, LME_EHIP, LME_ENOTSUP, LME_ENOTHERM, LME_EDRAWS = range(11)
 STATUS_NAMES = {0: "LME_OK", 1: "LME_EINVAL", 2: "LME_EGRID", 3: "LME_EMAXSTEPS",
                 4: "LME_ESTEPUNDERFLOW", 5: "LME_ENONFINITE", 6: "LME_ENOMEM",
-                7: "LME_EHIP", 8: "LME_ENOTSUP", 9: "LME_ENOTHERM"}
+                7: "LME_EHIP", 8: "LME_ENOTSUP", 9: "LME_ENOTHERM", 10: "LME_EDRAWS"}
 LME_RK4, LME_DOPRI5 = 0, 1
 LME_PATH_AUTO, LME_PATH_RESIDENT, LME_PATH_STREAMED = 0, 1, 2
 LME_FORM_OPERATOR, LME_FORM_SUPEROP, LME_FORM_OPERATOR_STREAMED = 0, 1, 2
@@ -29,7 +30,8 @@ LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
            "lme_last_error", "lme_layout", "lme_evolve", "lme_evolve_noalloc", "lme_apply",
-           "lme_cost_grad", "lme_get_tuning", "lme_set_tuning", "lme_autotune"]
+           "lme_cost_grad", "lme_get_tuning", "lme_set_tuning", "lme_autotune",
+           "lme_mc_create", "lme_mc_destroy", "lme_mc_evolve"]
 
 
 class LmeError(RuntimeError):
@@ -99,6 +101,13 @@ def load():
         lib.lme_set_tuning.argtypes = [H, C.POINTER(Tuning)]
         lib.lme_autotune.argtypes = [H, C.POINTER(Options), C.c_void_p, C.c_void_p,
                                      C.POINTER(Tuning)]
+        lib.lme_mc_create.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(Csr), C.c_int32,
+                                      C.POINTER(Csr), C.POINTER(H)]
+        lib.lme_mc_destroy.argtypes = [H]
+        lib.lme_mc_destroy.restype = None
+        lib.lme_mc_evolve.argtypes = [H, C.c_int32, _PD, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _LIB = lib
     return _LIB
 
@@ -492,3 +501,97 @@ def raw_create_batch(systems, n_ctrl=None, n_e=None):
     if rc == LME_OK:
         lib.lme_destroy(h)
     return rc, msg
+
+
+# ---------------------------------------------------------------------------
+# Monte-Carlo wave-function trajectories (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+class McHandle:
+    """One system for Monte-Carlo trajectories (lme_mc_create): Hamiltonian H,
+    collapse operators C, expectation operators E (square matrices)."""
+
+    def __init__(self, H, C, E):
+        lib = load()
+        keep = _CsrKeep()
+        Hc = keep.array([H])
+        Cs = keep.array(list(C))
+        Es = keep.array(list(E))
+        h = C_.c_void_p()
+        rc = lib.lme_mc_create(C_.cast(Hc, C_.POINTER(Csr)), len(C), C_.cast(Cs, C_.POINTER(Csr)),
+                               len(E), C_.cast(Es, C_.POINTER(Csr)), C_.byref(h))
+        _check(rc, "lme_mc_create")
+        self._h = h
+        self.n = sp.csr_matrix(H).shape[0]
+        self.n_c, self.n_e = len(C), len(E)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lme_mc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def evolve(self, psi0, tlist, nsteps, draws, want_traj=True, want_jumps=True, stream=None):
+        """lme_mc_evolve.  psi0: complex128 device tensor [n]; draws: float64
+        device tensor [n_traj, max_jumps + 1, 2].  Returns a dict of device
+        tensors: expect [n_e, n_t] (mean), expect_traj [n_traj, n_e, n_t],
+        n_jumps, jump_t, jump_op [n_traj, max_jumps], status [n_traj]."""
+        import torch
+        _check_tensor(psi0, torch.complex128, self.n, "psi0")
+        if not isinstance(draws, torch.Tensor) or draws.dim() != 3 or draws.shape[2] != 2:
+            raise LmeError(LME_EINVAL, "draws must be a tensor [n_traj, max_jumps + 1, 2]")
+        n_traj, mj = int(draws.shape[0]), int(draws.shape[1]) - 1
+        _check_tensor(draws, torch.float64, n_traj * (mj + 1) * 2, "draws")
+        tl = np.ascontiguousarray(tlist, np.float64)
+        n_t = len(tl)
+        dev = psi0.device
+        out = {"expect": torch.zeros((self.n_e, n_t), dtype=torch.complex128, device=dev),
+               "expect_traj": (torch.zeros((n_traj, self.n_e, n_t), dtype=torch.complex128,
+                                           device=dev) if want_traj else None),
+               "status": torch.full((n_traj,), -1, dtype=torch.int32, device=dev)}
+        if want_jumps:
+            out["n_jumps"] = torch.zeros(n_traj, dtype=torch.int32, device=dev)
+            out["jump_t"] = torch.zeros((n_traj, max(mj, 1)), dtype=torch.float64, device=dev)
+            out["jump_op"] = torch.full((n_traj, max(mj, 1)), -1, dtype=torch.int32, device=dev)
+        g = out.get
+        rc = load().lme_mc_evolve(self._h, n_t, tl.ctypes.data_as(_PD), int(nsteps), _ptr(psi0),
+                                  n_traj, _ptr(draws), mj, _ptr(g("expect")),
+                                  _ptr(g("expect_traj")), _ptr(g("n_jumps")), _ptr(g("jump_t")),
+                                  _ptr(g("jump_op")), _ptr(g("status")), _stream_ptr(stream))
+        _check(rc, "lme_mc_evolve")
+        return out
+
+
+def mcsolve(H, psi0, tlist, ntraj, c_ops, e_ops, nsteps, seed=0, max_jumps=64, device="cuda",
+            draws=None):
+    """Monte-Carlo solver in the calling convention of the paper (Sec. 4.3:
+    Hamiltonian, initial ket, times, number of trajectories, collapse and
+    expectation operators).  The random numbers of every trajectory are drawn
+    once from ``numpy.random.default_rng(seed)`` (or given as ``draws``,
+    [ntraj, max_jumps + 1, 2]).  Returns the trajectory-averaged expectation
+    values [len(e_ops)][len(tlist)] (real for Hermitian e_ops)."""
+    import torch
+    from . import systems
+    E = [sp.csr_matrix(e, dtype=np.complex128) for e in e_ops]
+    h = McHandle(H, [sp.csr_matrix(c, dtype=np.complex128) for c in c_ops], E)
+    try:
+        psi = torch.from_numpy(np.ascontiguousarray(np.asarray(psi0, np.complex128).reshape(-1)))
+        d = systems.mc_draws(ntraj, max_jumps, seed) if draws is None else np.asarray(draws)
+        out = h.evolve(psi.to(device), tlist, nsteps, torch.from_numpy(np.ascontiguousarray(d)).to(device),
+                       want_traj=False, want_jumps=False)
+        torch.cuda.synchronize()
+        st = out["status"].cpu().numpy()
+        if (st != 0).any():
+            bad = int(st[st != 0][0])
+            raise LmeError(bad, f"mcsolve: {int((st != 0).sum())} trajectories stopped "
+                                f"({STATUS_NAMES.get(bad, bad)})")
+        ex = out["expect"].cpu().numpy()
+        herm = [abs(e - e.conj().T).max() == 0 if e.nnz else True for e in E]
+        return np.stack([ex[k].real if herm[k] else ex[k] for k in range(len(E))]) if E else ex
+    finally:
+        h.close()

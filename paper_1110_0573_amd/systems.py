@@ -343,6 +343,15 @@ def trilinear(N=17, alpha=np.sqrt(10.0), g=(0.1, 0.4, 0.1)):
     return s
 
 
+def trilinear_mc_workload(n_traj=1000, seed=6, max_jumps=128):
+    """Sec. 4.3 trilinear Hamiltonian (N = 17, dim 4913), 1000 trajectories,
+    201 outputs on [0, 4], RK4 with h = 0.004 (1000 steps; the no-jump
+    propagator is reproduced to 1e-9 at this step), draws seeded."""
+    s = trilinear()
+    return Workload(f"trilinear_mc_{n_traj}", [s], np.linspace(0.0, 4.0, 201), "mc",
+                    nsteps=1000, extra=dict(draws=mc_draws(n_traj, max_jumps, seed)))
+
+
 def random_system(n, n_c=2, n_ctrl=0, n_e=2, density=0.4, seed=0, n_seg=0,
                   t_end=1.0, hermitian_rho=True):
     """Random sparse Hermitian H, general sparse C_k, random controls and a

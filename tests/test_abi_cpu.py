@@ -237,3 +237,40 @@ def test_binding_checks_every_buffer_before_the_c_call():
         lme._cost_grad(hd, rho, torch.zeros(hd.state_elems - 1, dtype=torch.complex128),
                        torch.zeros((2, 1, 4), dtype=torch.float64), 0.0, 1.0, 8, 2)
     assert e.value.code == lme.LME_EINVAL
+
+
+def test_mc_create_and_evolve_validation_before_device_use():
+    """Monte-Carlo entry points: operator validation at create, time grid and
+    argument checks before any HIP call."""
+    lib = lme.load()
+    s = S.thermal_cavity_mc()
+    with pytest.raises(lme.LmeError) as e:      # collapse operator of the wrong dimension
+        lme.McHandle(s.H0, [sp.identity(3, dtype=np.complex128, format="csr")], s.E)
+    assert e.value.code == lme.LME_EINVAL
+    with pytest.raises(lme.LmeError) as e:      # too many collapse operators
+        lme.McHandle(s.H0, [s.C[0]] * 17, s.E)
+    assert e.value.code == lme.LME_ENOTSUP
+    h = lme.McHandle(s.H0, s.C, s.E)
+
+    def rc_of(tl, nsteps, n_traj=4, max_jumps=2, psi=16, draws=32):
+        tl = np.ascontiguousarray(tl, np.float64)
+        return lib.lme_mc_evolve(h._h, len(tl), tl.ctypes.data_as(C.POINTER(C.c_double)), nsteps,
+                                 C.c_void_p(psi), n_traj, C.c_void_p(draws), max_jumps, None,
+                                 None, None, None, None, None, None)
+    assert rc_of([0.0, 0.5, 0.4], 10) == lme.LME_EINVAL           # not increasing
+    assert rc_of([0.0, 0.33, 1.0], 10) == lme.LME_EGRID           # off the grid
+    assert rc_of([0.0, 1.0], 0) == lme.LME_EINVAL                 # no steps
+    assert rc_of([0.0, 1.0], 10, n_traj=0) == lme.LME_EINVAL
+    assert rc_of([0.0, 1.0], 10, max_jumps=-1) == lme.LME_EINVAL
+    assert rc_of([0.0, 1.0], 10, psi=0) == lme.LME_EINVAL
+    assert lib.lme_mc_evolve(None, 1, None, 0, None, 1, None, 0, None, None, None, None, None,
+                             None, None) == lme.LME_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        assert rc_of([0.0, 1.0], 10) == lme.LME_EHIP
+        with pytest.raises(lme.LmeError) as e:    # the binding checks tensors first
+            h.evolve(torch.zeros(4, dtype=torch.complex128), [0.0, 1.0], 10,
+                     torch.zeros((2, 3, 2), dtype=torch.float64))
+        assert e.value.code == lme.LME_EINVAL
+    lib.lme_mc_destroy(None)
+    h.close()
