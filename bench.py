@@ -61,6 +61,59 @@ def apply_flops(s):
     return 8.0 * (2 * n * off + n * n + jumps)
 
 
+def survey_apply_flops(s):
+    """The scope table's count of one application, operator form:
+    8 n nnz(A) + 2 n^2 + 8 n^2 K (A = -iH - 1/2 sum C^+C with its diagonal,
+    K collapse operators)."""
+    import scipy.sparse as sp
+    n = s.n
+    A = sp.csr_matrix(-1j * s.H0)
+    for c in s.C:
+        A = A - 0.5 * (c.conj().T @ c)
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    return 8.0 * n * A.nnz + 2.0 * n * n + 8.0 * n * n * len(s.C)
+
+
+def herm_lds_bytes_per_element_stage(s):
+    """LDS bytes one element-stage of the Hermitian resident kernel moves
+    (row data in registers): the y gathers of A y, y A^+ (one per
+    off-diagonal entry of A on each side) and C_k y C_k^+ (one per monomial
+    collapse operator), 16 bytes each, plus the stage input stored twice
+    (the element and its conjugate mirror)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(-1j * s.H0)
+    for c in s.C:
+        A = A - 0.5 * (c.conj().T @ c)
+    A = sp.csr_matrix(A)
+    A.setdiag(0)
+    A.eliminate_zeros()
+    wo = int(np.max(np.diff(A.indptr))) if A.nnz else 0
+    return 16.0 * (2 * wo + len(s.C)) + 32.0
+
+
+def lds_peak_tbs(lme, torch, reps=5):
+    """Measured LDS read bandwidth of the chip (TB/s): the probe kernel,
+    two 1024-thread workgroups per CU, ds_read_b128 without bank conflicts."""
+    import ctypes as C
+    lib = lme.load()
+    lib.lme_internal_probe_lds.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    grid, iters = 2 * n_cu, 8192
+    sink = torch.zeros(grid, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        assert lib.lme_internal_probe_lds(grid, iters, lme._ptr(sink), lme._stream_ptr(stream)) == 0
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lib.lme_internal_probe_lds(grid, iters, lme._ptr(sink), lme._stream_ptr(stream))
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    return grid * 1024.0 * iters * 16.0 / sec / 1e12
+
+
 def rk4_step_flops(s):
     """One RK4 step: four applications plus the stage combinations
     (2 complex-by-real axpys per stage and the final update: 36 flops/element)."""
@@ -73,21 +126,149 @@ def rk4_step_flops_hermitian(s):
     return rk4_step_flops(s) * (s.n + 1) / (2.0 * s.n)
 
 
-def cpu_baseline(w, sample, nsteps_full):
-    """The oracle (plain C, -O3) on a bounded sample of the same workload,
-    one instance per host thread."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, sample, nsteps_full, systems, with_configs=True):
+    """The oracle (plain C, gcc -O3 -march=native, built here on the host it
+    is timed on) on bounded samples: the headline sweep (one instance per
+    host thread, median of 3 runs) and, single-threaded or one instance per
+    thread, the other configurations and the Monte-Carlo workload."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
+    try:
+        oracle.use_native_build(tempfile.mkdtemp(prefix="oracle_native_"))
+        build = "gcc -O3 -march=native"
+    except Exception as e:  # pragma: no cover - no compiler on the host
+        build = f"gcc -O3 (generic; native build failed: {e})"
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     rng = np.random.default_rng(123)
     idx = rng.choice(len(w.systems), sample, replace=False)
-    systems = [w.systems[i] for i in idx]
-    cores = os.cpu_count() or 1
+    sub = [w.systems[i] for i in idx]
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.rk4_batch(sub, [s.rho0 for s in sub], w.tlist, nsteps_full, cores)
+        runs.append(time.perf_counter() - t0)
+    dt = float(np.median(runs))
+    rec = {"value": sample * nsteps_full / dt, "unit": "instance-RK-steps/s", "cores": cores,
+           "kind": "oracle", "cpu": cpu_model(), "build": build,
+           "sample": f"{sample} random instances of the 4096-instance sweep, full 1000 RK4 "
+                     f"steps each, one instance per thread on {cores} host threads; median of "
+                     f"3 runs ({', '.join(f'{r:.2f}' for r in runs)} s)"}
+    if not with_configs:
+        return rec
+    cfg = {}
+    ws = systems.jc_single()
+    s = ws.systems[0]
     t0 = time.perf_counter()
-    oracle.rk4_batch(systems, [s.rho0 for s in systems], w.tlist, nsteps_full, cores)
-    dt = time.perf_counter() - t0
-    return {"value": sample * nsteps_full / dt, "unit": "instance-RK-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{sample} random instances of the 4096-instance sweep, full 1000 RK4 "
-                      f"steps each, {dt:.1f} s on {cores} host threads"}
+    oracle.rk4(s, s.rho0, ws.tlist, ws.nsteps)
+    d = time.perf_counter() - t0
+    cfg["jc_single_N10_rk4_2500"] = {"steps_per_s": ws.nsteps / d, "threads": 1,
+                                     "sample": "the full run", "s": d}
+    wk = systems.kerr_single()
+    s = wk.systems[0]
+    tl = np.linspace(0.0, 5.0, 11)
+    t0 = time.perf_counter()
+    r = oracle.dopri5(s, s.rho0, tl, wk.rtol, wk.atol)
+    d = time.perf_counter() - t0
+    cfg["kerr_N60_dopri5"] = {"accepted_steps_per_s": float(r["counts"][0]) / d, "threads": 1,
+                              "sample": f"t in [0, 5] ({int(r['counts'][0])} accepted steps) of "
+                                        "the t in [0, 50] run", "s": d}
+    wd = systems.jc_drive()
+    nd = min(cores, 16)
+    O = wd.extra["target"]
+
+    def grad_one(b):
+        sy = wd.systems[b]
+        return oracle.rk4_cost_grad(sy, sy.rho0, O, 0.0, 10.0, wd.nsteps)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nd) as ex:
+        list(ex.map(grad_one, range(nd)))
+    d = time.perf_counter() - t0
+    cfg["jc_drive_cost_grad"] = {"forward_instance_steps_per_s": nd * wd.nsteps / d,
+                                 "threads": nd, "sample": f"{nd} of the 256 instances, full "
+                                 "1000-step cost and gradient each", "s": d}
+    wt = systems.tfim()
+    nt = min(cores, 8)
+    tlt = np.linspace(0.0, 1.0, 11)
+
+    def tfim_one(b):
+        sy = wt.systems[b]
+        return oracle.dopri5(sy, sy.rho0, tlt, wt.rtol, wt.atol)["counts"][0]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nt) as ex:
+        acc = sum(ex.map(tfim_one, range(nt)))
+    d = time.perf_counter() - t0
+    cfg["tfim_8spin_dopri5"] = {"accepted_instance_steps_per_s": float(acc) / d, "threads": nt,
+                                "sample": f"{nt} of the 64 realizations on t in [0, 1] "
+                                          "(of [0, 20])", "s": d}
+    wm = systems.trilinear_mc_workload()
+    sm = wm.systems[0]
+    nm = 2 * cores
+    t0 = time.perf_counter()
+    oracle.mc(sm, sm.meta["psi0"], wm.tlist, wm.nsteps, wm.extra["draws"][:nm], n_threads=cores)
+    d = time.perf_counter() - t0
+    cfg["trilinear_mc"] = {"trajectory_steps_per_s": nm * wm.nsteps / d, "threads": cores,
+                           "sample": f"{nm} of the 1000 trajectories, full 1000 steps each",
+                           "s": d}
+    rec["configs"] = cfg
+    return rec
+
+
+def mc_trilinear_bench(lme, systems, torch, reps=3):
+    """Monte-Carlo trajectories of the trilinear Hamiltonian (Sec. 4.3): 1000
+    trajectories of dimension 4913, 1000 RK4 steps, 201 outputs.  Kernel
+    time with HIP events on the launch stream (median of the timed runs)."""
+    import scipy.sparse as sp
+    w = systems.trilinear_mc_workload()
+    s = w.systems[0]
+    h = lme.McHandle(s.H0, s.C, s.E)
+    psi0 = torch.from_numpy(s.meta["psi0"]).cuda()
+    draws = torch.from_numpy(w.extra["draws"]).cuda()
+    stream = torch.cuda.current_stream()
+    out = h.evolve(psi0, w.tlist, w.nsteps, draws, want_traj=False)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out = h.evolve(psi0, w.tlist, w.nsteps, draws, want_traj=False)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    st = out["status"].cpu().numpy()
+    jumps = out["n_jumps"].cpu().numpy()
+    n_traj = len(w.extra["draws"])
+    kms = float(np.median(ms))
+    # algorithmic flops per trajectory-step: four sparse products with A
+    # (8 per complex multiply-add over nnz(A)), the 1/k scalings and the
+    # running-sum updates (2 + 4 per element each) and the squared norm
+    A = sp.csr_matrix(-1j * s.H0)
+    for c in s.C:
+        A = A - 0.5 * (c.conj().T @ c)
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    n = s.n
+    f_step = 4 * (8.0 * A.nnz + 6.0 * n) + 4.0 * n
+    flops = f_step * n_traj * w.nsteps
+    return {"workload": "trilinear Hamiltonian, 3 modes x 17 states (dim 4913), 1000 "
+                        "trajectories, 1000 RK4 steps on [0, 4], 201 outputs",
+            "ms": kms, "ms_runs": ms, "trajectory_steps_per_s": n_traj * w.nsteps / (kms * 1e-3),
+            "jumps_mean": float(jumps.mean()), "status_ok": bool((st == 0).all()),
+            "algorithmic_flops": flops, "achieved_tflops": flops / (kms * 1e-3) / 1e12,
+            "frac_fp64_peak": flops / (kms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "kernel": "mc_kernel"}
 
 
 def streamed_apply_bench(lme, systems, torch, reps=20):
@@ -268,6 +449,25 @@ def pmc_pass(lme, systems, torch):
     rc = lme.load().lme_apply(ht._h, lme.LME_FORM_OPERATOR, 0, 0.0, None, lme._ptr(yt),
                               lme._ptr(ot), lme._stream_ptr(None))
     assert rc == 0
+    # the other configurations' kernels, on short horizons
+    wk = systems.kerr_single()
+    hk = lme.Handle(wk.systems)
+    hk.evolve(hk.pack([s.rho0 for s in wk.systems]), np.linspace(0.0, 5.0, 11), method="dopri5",
+              rtol=wk.rtol, atol=wk.atol)
+    wt5 = systems.tfim()
+    ht5 = lme.Handle(wt5.systems)
+    ht5.evolve(ht5.pack([s.rho0 for s in wt5.systems]), np.linspace(0.0, 1.0, 11),
+               method="dopri5", rtol=wt5.rtol, atol=wt5.atol)
+    wd = systems.jc_drive()
+    hd = lme.Handle(wd.systems)
+    lme._cost_grad(hd, hd.pack([s.rho0 for s in wd.systems]),
+                   hd.pack([wd.extra["target"]] * len(wd.systems)),
+                   torch.from_numpy(wd.extra["u"]).cuda(), 0.0, 10.0, wd.nsteps, 10)
+    wm = systems.trilinear_mc_workload()
+    sm = wm.systems[0]
+    hm = lme.McHandle(sm.H0, sm.C, sm.E)
+    hm.evolve(torch.from_numpy(sm.meta["psi0"]).cuda(), wm.tlist, wm.nsteps,
+              torch.from_numpy(wm.extra["draws"]).cuda(), want_traj=False)
     src = torch.ones(32 * 2**20, dtype=torch.float64, device="cuda:0")   # 256 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -361,8 +561,18 @@ def main():
 
     step_flops = rk4_step_flops_hermitian if herm else rk4_step_flops
     flops = sum(step_flops(s) for s in w.systems) * w.nsteps
+    survey_flops = sum(4.0 * survey_apply_flops(s) for s in w.systems) * w.nsteps
     k_ms = float(np.mean(kern_ms))
     achieved = flops / (k_ms * 1e-3) / 1e12
+    survey_tflops = survey_flops / (k_ms * 1e-3) / 1e12
+    # LDS: the resident kernel's own bound (its state never leaves the chip)
+    if herm:
+        elem_stages = [4.0 * w.nsteps * s.n * (s.n + 1) / 2 for s in w.systems]
+        lds_bytes = sum(e * herm_lds_bytes_per_element_stage(s)
+                        for e, s in zip(elem_stages, w.systems))
+    else:
+        lds_bytes = None
+    lds_peak = lds_peak_tbs(lme, torch)
     # HBM bytes the path must move: rho0 in, final rho out, expectations out
     hbm_bytes = 2 * 16 * h.state_elems + 16 * n_inst * 2 * len(w.tlist)
 
@@ -402,11 +612,26 @@ def main():
                    "hermitian": herm,
                    "block": args.block or "tuned", "layout": args.layout or "tuned",
                    "tuning": tuning},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+        "roofline": ({"bound": "lds", "achieved": lds_bytes / (k_ms * 1e-3) / 1e12,
+                      "peak": lds_peak, "unit": "TB/s",
+                      "frac": lds_bytes / (k_ms * 1e-3) / 1e12 / lds_peak,
+                      "algorithmic_lds_bytes": lds_bytes,
+                      "lds_bytes_per_element_stage": herm_lds_bytes_per_element_stage(w.systems[0]),
+                      "peak_source": "measured: LDS read probe (ds_read_b128, no bank conflicts)"}
+                     if herm else
+                     {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS}) | {
                      "traffic": kernel_traffic("rk4_herm_kernel" if herm else "rk4_colown_kernel"),
                      "kernel": "rk4_herm_kernel" if herm else "rk4_colown_kernel",
-                     "kernel_ms": k_ms, "algorithmic_flops": flops},
+                     "kernel_ms": k_ms,
+                     "flops": {"scope_table_count": survey_flops,
+                               "achieved_tflops": survey_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                               "frac": survey_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                               "path_count": flops, "path_achieved_tflops": achieved,
+                               "path_frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                               "note": "scope_table_count: 4 x (8 n nnz(A) + 2 n^2 + 8 n^2 K) "
+                                       "per step; path_count: the elements this path computes "
+                                       "(n(n+1)/2 per instance on the Hermitian path)"}},
         "hbm": {"algorithmic_bytes": hbm_bytes, "GBs": hbm_bytes / (k_ms * 1e-3) / 1e9,
                 "note": "state stays on chip for all steps; HBM moves rho0, rho, outputs"},
         "batched_vs_plain": {"plain_value": plain_rate, "speedup": value / plain_rate,
@@ -415,11 +640,13 @@ def main():
     if full_path:
         rec["full_path"] = full_path
     rec["streamed_apply"] = streamed_apply_bench(lme, systems, torch)
+    rec["mc_trilinear"] = mc_trilinear_bench(lme, systems, torch)
     rec["streamed_apply_tfim"] = tfim_apply_bench(lme, systems, torch)
     if not args.no_configs:
         rec["other_configs"] = other_configs(lme, systems, torch)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, w.nsteps)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, w.nsteps, systems,
+                                           with_configs=not args.no_configs)
     print(json.dumps(rec), flush=True)
 
 

@@ -39,16 +39,33 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def build(force: bool = True) -> str:
-    """Compile lme_oracle.c into liblme_oracle.so (gcc, -O3, host ISA)."""
-    if not force and os.path.exists(_LIBPATH):
-        return _LIBPATH
-    tmp = _LIBPATH + f".tmp{os.getpid()}"
-    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-shared", "-fPIC",
-           "-o", tmp, _SRC, "-lm", "-lpthread"]
+def build(force: bool = True, path: str | None = None, native: bool = False) -> str:
+    """Compile lme_oracle.c into liblme_oracle.so (gcc -O3).  The in-tree copy
+    uses the generic x86-64 ISA, because it is built on one machine and loaded
+    on another (the GPU host); ``native=True`` adds -march=native for a copy
+    built and timed on the same host (``path``)."""
+    path = path or _LIBPATH
+    if not force and os.path.exists(path):
+        return path
+    tmp = path + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-shared", "-fPIC"] + \
+        (["-march=native"] if native else []) + ["-o", tmp, _SRC, "-lm", "-lpthread"]
     subprocess.run(cmd, check=True, cwd=_HERE)
-    os.replace(tmp, _LIBPATH)
-    return _LIBPATH
+    os.replace(tmp, path)
+    return path
+
+
+def use_native_build(workdir: str) -> str:
+    """Builds an -O3 -march=native copy of the oracle in ``workdir`` and makes
+    every following call use it (for timing the oracle on the host it runs
+    on).  Returns its path."""
+    global _LIB, _LIBPATH
+    path = build(path=os.path.join(workdir, "liblme_oracle_native.so"), native=True)
+    with _LOCK:
+        _LIB = None
+        _LIBPATH = path
+    _lib()
+    return path
 
 
 class _Csr(C.Structure):
@@ -76,7 +93,7 @@ def _lib():
         if _LIB is None:
             if not os.path.exists(_LIBPATH) or (
                     os.path.getmtime(_LIBPATH) < os.path.getmtime(_SRC)):
-                build()
+                build(path=_LIBPATH)
             lib = C.CDLL(_LIBPATH)
             P = C.POINTER(_System)
             lib.orc_apply_L.argtypes = [P, C.c_double, _PD, _PD]

@@ -21,7 +21,8 @@
 // Work decomposition: a workgroup holds P trajectories; G = 2^g threads own
 // one trajectory, thread g its rows g, g + G, ... (R rows).  The current
 // Taylor vector of every trajectory is staged in LDS (16 n bytes each) so the
-// sparse products gather from LDS; psi and the running sum stay in
+// sparse products gather from LDS; the state psi sits in LDS too (read and
+// written only by the thread that owns the row) and the running sum in
 // registers.  Per-trajectory scalars (threshold, time left, jump count,
 // status) are identical in every thread of a group: reductions end with the
 // same bits in every lane (xor butterflies, then a fixed-order sum of the
@@ -36,7 +37,7 @@ namespace {
 
 using lme::McArgs;
 
-struct cplx {
+struct __attribute__((aligned(16))) cplx {
   double x, y;
 };
 
@@ -136,7 +137,7 @@ __device__ inline cplx row_eop(const Tabs &t, int n, int we, const cplx *x, int 
 constexpr int kMaxNC = lme::kMcMaxNC;
 
 // Largest workgroup of the kernel with R rows per thread.
-constexpr int mc_max_threads(int R) { return R <= 6 ? 1024 : 512; }
+constexpr int mc_max_threads(int) { return 512; }
 
 template <int R>
 __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
@@ -148,7 +149,8 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
   cplx *V = reinterpret_cast<cplx *>(lds + ((nwaves * 9 + P * kMaxNC + 1) & ~1));
   const int p = threadIdx.x / G;                         // trajectory slot
   const int g0 = threadIdx.x % G;
-  cplx *X = V + (size_t)p * n;                           // this group's vector
+  cplx *X = V + (size_t)p * n;                           // this group's Taylor vector
+  cplx *PS = V + (size_t)(P + p) * n;                    // this group's state psi
   const bool in_group = p < P;
   const cplx *psi0 = reinterpret_cast<const cplx *>(a.psi0);
   cplx *ex = reinterpret_cast<cplx *>(a.ex_traj);
@@ -171,19 +173,20 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
     int g = launder(g0);
     const int traj = pack * P + p;
     const bool alive0 = in_group && traj < a.n_traj;
-    cplx psi[R], acc[R];
-    // the initial ket, normalised
+    // the initial ket, normalised, into PS (each thread its own rows)
     double nn[1] = {0.0};
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int i = g + q * G;
-      psi[q] = (alive0 && i < n) ? psi0[i] : cplx{0.0, 0.0};
-      nn[0] += cabs2(psi[q]);
+      if (alive0 && i < n) nn[0] += cabs2(psi0[i]);
     }
     group_sum<1>(nn, G, red);
-    const double sc = 1.0 / sqrt(nn[0]);
+    const double sc = nn[0] > 0.0 ? 1.0 / sqrt(nn[0]) : 0.0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) psi[q] = cscale(sc, psi[q]);
+    for (int q = 0; q < R; ++q) {
+      const int i = g + q * G;
+      if (in_group && i < n) PS[i] = alive0 ? cscale(sc, psi0[i]) : cplx{0.0, 0.0};
+    }
     // outputs of a trajectory that stops early stay zero
     if (alive0)
       for (int e = g; e < a.ne * a.n_t; e += G) ex[(size_t)traj * a.ne * a.n_t + e] = {0.0, 0.0};
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int i = g + q * G;
-        if (in_group && i < n) X[i] = psi[q];
+        if (in_group && i < n) X[i] = PS[i];
       }
       __syncthreads();
       for (int m0 = 0; m0 < a.ne; m0 += 2) {
@@ -211,15 +214,16 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
         for (int q = 0; q < R; ++q) {
           const int i = g + q * G;
           if (in_group && i < n) {
+            const cplx ps = X[i];
 #pragma unroll
             for (int d = 0; d < 2; ++d)
               if (m0 + d < a.ne) {
                 const cplx e = row_eop(tb, n, a.we, X, m0 + d, i);
                 // conj(psi_i) * (E psi)_i
-                v[2 * d] += psi[q].x * e.x + psi[q].y * e.y;
-                v[2 * d + 1] += psi[q].x * e.y - psi[q].y * e.x;
+                v[2 * d] += ps.x * e.x + ps.y * e.y;
+                v[2 * d + 1] += ps.x * e.y - ps.y * e.x;
               }
-            v[4] += cabs2(psi[q]);
+            v[4] += cabs2(ps);
           }
         }
         group_sum<5>(v, G, red);
@@ -241,12 +245,13 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
         if (!__syncthreads_or(left > 0.0)) break;
         g = launder(g0);
         const double s = left;
-        // Taylor form of the RK4 step of length s
+        cplx acc[R];
+        // Taylor form of the RK4 step of length s: acc = sum_k s^k v_k
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const int i = g + q * G;
-          if (in_group && i < n) X[i] = psi[q];
-          acc[q] = psi[q];
+          acc[q] = (in_group && i < n) ? PS[i] : cplx{0.0, 0.0};
+          if (in_group && i < n) X[i] = acc[q];
         }
         double sk = 1.0;
         for (int k = 1; k <= 4; ++k) {
@@ -281,7 +286,10 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
             left = 0.0;
           } else if (nt[0] > r) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) psi[q] = acc[q];
+            for (int q = 0; q < R; ++q) {
+              const int i = g + q * G;
+              if (in_group && i < n) PS[i] = acc[q];
+            }
             left = 0.0;
           } else {
             cross = true;
@@ -296,7 +304,7 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const int i = g + q * G;
-          if (in_group && i < n) X[i] = psi[q];
+          if (in_group && i < n) X[i] = PS[i];
         }
         for (int k = 1; k <= 4; ++k) {
           __syncthreads();
@@ -324,7 +332,7 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
           const int i = g + q * G;
           if (in_group && i < n) {
             cplx v[5];
-            v[0] = psi[q];
+            v[0] = PS[i];
 #pragma unroll
             for (int k = 1; k <= 4; ++k) v[k] = ld_c(tb.vb, ((k - 1) * P + p) * n + i);
 #pragma unroll
@@ -352,7 +360,10 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
               lo = mid;
           }
           tau = hi;
-          // psi(tau) by Horner
+        }
+        __syncthreads();
+        // psi(tau) by Horner into X (crossing trajectories)
+        if (cross)
 #pragma unroll
           for (int q = 0; q < R; ++q) {
             const int i = g + q * G;
@@ -362,16 +373,10 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
                 const cplx vk = ld_c(tb.vb, ((k - 1) * P + p) * n + i);
                 h4 = {fma(h4.x, tau, vk.x), fma(h4.y, tau, vk.y)};
               }
-              acc[q] = {fma(h4.x, tau, psi[q].x), fma(h4.y, tau, psi[q].y)};
+              const cplx v0 = PS[i];
+              X[i] = {fma(h4.x, tau, v0.x), fma(h4.y, tau, v0.y)};
             }
           }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const int i = g + q * G;
-          if (in_group && i < n && cross) X[i] = acc[q];
-        }
         __syncthreads();
         // jump weights <psi|C_k^+ C_k|psi> at tau, four operators at a time,
         // into this trajectory's slots of wts
@@ -426,11 +431,12 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
                 chosen = last_nonzero;
                 w_chosen = w_last;
               }
+              // the projected, renormalised state (Eq. (project)) into PS
               const double rs = 1.0 / sqrt(w_chosen);
 #pragma unroll
               for (int q = 0; q < R; ++q) {
                 const int i = g + q * G;
-                if (in_group && i < n) psi[q] = cscale(rs, row_jump(tb, n, a.wc, X, chosen, i));
+                if (in_group && i < n) PS[i] = cscale(rs, row_jump(tb, n, a.wc, X, chosen, i));
               }
               t += tau;
               if (g == 0) {
@@ -449,6 +455,7 @@ __global__ __launch_bounds__(mc_max_threads(R)) void mc_kernel(McArgs a) {
       if (a.n_jumps) a.n_jumps[traj] = jumps;
       if (a.status) a.status[traj] = status;
     }
+    __syncthreads();   // PS and X are reused by the next pack
   }
 }
 
@@ -492,7 +499,7 @@ extern "C" int lme_internal_mc_rows(int *rows, int *max_threads, int cap) {
 // Dynamic LDS of a workgroup of T threads holding P vectors of dimension n.
 extern "C" int lme_internal_mc_lds_bytes(int T, int P, int n) {
   const int nwaves = (T + 63) / 64;
-  return 8 * ((nwaves * 9 + P * kMaxNC + 1) & ~1) + 16 * P * n;
+  return 8 * ((nwaves * 9 + P * kMaxNC + 1) & ~1) + 32 * P * n;   // + X and psi
 }
 
 extern "C" hipError_t lme_internal_launch_mc(int R, const McArgs *a, int grid, int lds,
