@@ -80,7 +80,7 @@ class _System(C.Structure):
                 ("n_c", C.c_int32), ("C", C.POINTER(_Csr)),
                 ("n_e", C.c_int32), ("E", C.POINTER(_Csr)),
                 ("n_seg", C.c_int32), ("edges", C.POINTER(C.c_double)),
-                ("u", C.POINTER(C.c_double))]
+                ("u", C.POINTER(C.c_double)), ("fn", C.POINTER(C.c_double))]
 
 
 _PD = C.POINTER(C.c_double)
@@ -154,6 +154,11 @@ class _Marshalled:
                 np.zeros((len(H_ctrl), n_seg)) if u is None else u,
                 dtype=np.float64).reshape(len(H_ctrl), n_seg)
             keep.extend([e_arr, u_arr])
+        fn = getattr(system, "fn", None)
+        fn_arr = None
+        if fn is not None:
+            fn_arr = np.ascontiguousarray(fn, dtype=np.float64).reshape(len(H_ctrl), 7)
+            keep.append(fn_arr)
         self.n = system.H0.shape[0]
         self.n_e = len(system.E)
         self.n_ctrl = len(H_ctrl)
@@ -162,13 +167,15 @@ class _Marshalled:
                          len(H_ctrl), csr_array(H_ctrl),
                          len(system.C), csr_array(list(system.C)),
                          len(system.E), csr_array(list(system.E)),
-                         n_seg, _dptr(e_arr), _dptr(u_arr))
+                         n_seg, _dptr(e_arr), _dptr(u_arr), _dptr(fn_arr))
         self.keep = keep
 
 
 def _marshal(system, u=None):
     """``system`` needs: H0 (n x n sparse/dense), C (list), E (list) and,
-    optionally, H_ctrl (list), edges (n_seg+1,), u (n_ctrl, n_seg)."""
+    optionally, H_ctrl (list), edges (n_seg+1,), u (n_ctrl, n_seg), or fn
+    (n_ctrl, 7): closed-form amplitudes c0 + c1 t + c2 t^2 + c3 t^3
+    + a cos(w t + phi)."""
     return _Marshalled(system, u)
 
 

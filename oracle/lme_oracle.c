@@ -113,7 +113,11 @@ static int check_system(const orc_system *s) {
     if ((rc = check_csr(&s->C[k], s->n))) return rc;
   for (int m = 0; m < s->n_e; ++m)
     if ((rc = check_csr(&s->E[m], s->n))) return rc;
-  if (s->n_seg > 0) {
+  if (s->fn) {
+    if (s->n_ctrl < 1) return ORC_EINVAL;
+    for (int i = 0; i < 7 * s->n_ctrl; ++i)
+      if (!isfinite(s->fn[i])) return ORC_EINVAL;
+  } else if (s->n_seg > 0) {
     if (!s->edges || (s->n_ctrl > 0 && !s->u)) return ORC_EINVAL;
     for (int q = 0; q < s->n_seg; ++q)
       if (!(s->edges[q + 1] > s->edges[q])) return ORC_EINVAL;
@@ -125,6 +129,14 @@ static int check_system(const orc_system *s) {
  * [edges[q], edges[q+1]) containing t, zero outside all segments.  Returns q,
  * or -1 when t lies outside. */
 static int controls_at(const orc_system *s, double t, double *uval) {
+  if (s->fn) {
+    /* closed-form amplitudes: c0 + c1 t + c2 t^2 + c3 t^3 + a cos(w t + phi) */
+    for (int j = 0; j < s->n_ctrl; ++j) {
+      const double *c = s->fn + 7 * (size_t)j;
+      uval[j] = c[0] + c[1] * t + c[2] * t * t + c[3] * t * t * t + c[4] * cos(c[5] * t + c[6]);
+    }
+    return 0;
+  }
   int q = -1;
   if (s->n_seg > 0 && t >= s->edges[0] && t < s->edges[s->n_seg])
     for (q = 0; q < s->n_seg - 1; ++q)
@@ -319,37 +331,43 @@ static int rk4_grid(const orc_system *s, int32_t n_t, const double *tlist,
   }
   if (n_t > 1 && out_step[n_t - 1] != nsteps) return ORC_EGRID;
   const double t1 = tlist[n_t - 1];
-  for (int q = 0; q <= s->n_seg && s->n_seg > 0; ++q) {
+  for (int q = 0; q <= s->n_seg && s->n_seg > 0 && !s->fn; ++q) {
     const double e = s->edges[q];
     if (e > t0 && e < t1 && grid_index(e, t0, h) < 0) return ORC_EGRID;
   }
   return ORC_OK;
 }
 
-/* One classic RK4 step: rho <- rho + h/6 (k1 + 2 k2 + 2 k3 + k4). */
-static void rk4_step(const orc_system *s, const double *uval, double h, cplx *rho,
-                     cplx *y, cplx *k, cplx *acc, work_t *w) {
+/* One classic RK4 step: rho <- rho + h/6 (k1 + 2 k2 + 2 k3 + k4).  The stages
+ * use the amplitudes u1 (k1), u2 (k2, k3) and u4 (k4). */
+static void rk4_step3(const orc_system *s, const double *u1, const double *u2, const double *u4,
+                      double h, cplx *rho, cplx *y, cplx *k, cplx *acc, work_t *w) {
   const size_t n2 = (size_t)s->n * s->n;
-  lindblad(s, uval, rho, k, w); /* k1 */
+  lindblad(s, u1, rho, k, w); /* k1 */
   for (size_t e = 0; e < n2; ++e) {
     acc[e] = k[e];
     y[e] = rho[e] + (0.5 * h) * k[e];
   }
-  lindblad(s, uval, y, k, w); /* k2 */
+  lindblad(s, u2, y, k, w); /* k2 */
   for (size_t e = 0; e < n2; ++e) {
     acc[e] += 2.0 * k[e];
     y[e] = rho[e] + (0.5 * h) * k[e];
   }
-  lindblad(s, uval, y, k, w); /* k3 */
+  lindblad(s, u2, y, k, w); /* k3 */
   for (size_t e = 0; e < n2; ++e) {
     acc[e] += 2.0 * k[e];
     y[e] = rho[e] + h * k[e];
   }
-  lindblad(s, uval, y, k, w); /* k4 */
+  lindblad(s, u4, y, k, w); /* k4 */
   for (size_t e = 0; e < n2; ++e) {
     acc[e] += k[e];
     rho[e] += (h / 6.0) * acc[e];
   }
+}
+
+static void rk4_step(const orc_system *s, const double *uval, double h, cplx *rho,
+                     cplx *y, cplx *k, cplx *acc, work_t *w) {
+  rk4_step3(s, uval, uval, uval, h, rho, y, k, acc, w);
 }
 
 int orc_rk4(const orc_system *s, const double *rho0, int32_t n_t,
@@ -365,7 +383,7 @@ int orc_rk4(const orc_system *s, const double *rho0, int32_t n_t,
 
   long *out_step = (long *)malloc(sizeof(long) * (size_t)n_t);
   cplx *buf = (cplx *)malloc(4 * n2 * sizeof(cplx));
-  double *uval = (double *)calloc((size_t)s->n_ctrl + 1, sizeof(double));
+  double *uval = (double *)calloc(3 * ((size_t)s->n_ctrl + 1), sizeof(double));
   work_t w;
   if (!out_step || !buf || !uval || work_init(&w, n)) {
     free(out_step);
@@ -373,6 +391,7 @@ int orc_rk4(const orc_system *s, const double *rho0, int32_t n_t,
     free(uval);
     return ORC_ENOMEM;
   }
+  double *uval2 = uval + s->n_ctrl + 1, *uval4 = uval2 + s->n_ctrl + 1;
   if (n_t > 1) rc = rk4_grid(s, n_t, tlist, nsteps, h, out_step);
   if (rc) goto done;
 
@@ -381,10 +400,19 @@ int orc_rk4(const orc_system *s, const double *rho0, int32_t n_t,
   record(s, rho, n_t, 0, expect, states);
   int next = 1;
   for (long st = 0; st < (n_t > 1 ? nsteps : 0); ++st) {
-    /* every stage of a step uses the controls of the segment holding the
-       step's midpoint (steps never straddle an edge) */
-    controls_at(s, t0 + ((double)st + 0.5) * h, uval);
-    rk4_step(s, uval, h, rho, y, k, acc, &w);
+    if (s->fn) {
+      /* function amplitudes: each stage at its own time */
+      const double ts = t0 + (double)st * h;
+      controls_at(s, ts, uval);
+      controls_at(s, ts + 0.5 * h, uval2);
+      controls_at(s, ts + h, uval4);
+      rk4_step3(s, uval, uval2, uval4, h, rho, y, k, acc, &w);
+    } else {
+      /* every stage of a step uses the controls of the segment holding the
+         step's midpoint (steps never straddle an edge) */
+      controls_at(s, t0 + ((double)st + 0.5) * h, uval);
+      rk4_step(s, uval, h, rho, y, k, acc, &w);
+    }
     while (next < n_t && out_step[next] == st + 1) {
       if (!all_finite(rho, n2)) {
         rc = ORC_ENONFINITE;
@@ -458,6 +486,7 @@ int orc_dopri5_step(const orc_system *s, double t, double h, const double *y,
                     double *y5, double *err) {
   int rc = check_system(s);
   if (rc) return rc;
+  if (s->fn) return ORC_EINVAL;
   const size_t n2 = (size_t)s->n * s->n;
   cplx *buf = (cplx *)malloc(8 * n2 * sizeof(cplx));
   double *uval = (double *)calloc((size_t)s->n_ctrl + 1, sizeof(double));
@@ -490,7 +519,7 @@ int orc_dopri5(const orc_system *s, const double *rho0, int32_t n_t,
                int64_t *counts, double *h_log, int64_t h_log_cap) {
   int rc = check_system(s);
   if (rc) return rc;
-  if (!rho0 || !tlist || n_t < 1 || (s->n_e > 0 && !expect)) return ORC_EINVAL;
+  if (!rho0 || !tlist || n_t < 1 || (s->n_e > 0 && !expect) || s->fn) return ORC_EINVAL;
   if (!(rtol > 0.0) || !(atol >= 0.0) || max_steps < 1 || !(h_min >= 0.0))
     return ORC_EINVAL;
   for (int k = 1; k < n_t; ++k)
@@ -664,7 +693,7 @@ int orc_rk4_cost_grad(const orc_system *s, const double *rho0, const double *O,
                       double *grad) {
   int rc = check_system(s);
   if (rc) return rc;
-  if (!rho0 || !O || !cost || nsteps < 1 || !(t1 > t0)) return ORC_EINVAL;
+  if (!rho0 || !O || !cost || nsteps < 1 || !(t1 > t0) || s->fn) return ORC_EINVAL;
   if (s->n_ctrl > 0 && s->n_seg > 0 && !grad) return ORC_EINVAL;
   const int n = s->n;
   const size_t n2 = (size_t)n * n;

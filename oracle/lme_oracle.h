@@ -57,6 +57,12 @@ typedef struct {
   int32_t n_seg;   const double *edges; /* n_seg+1 increasing times            */
   const double *u;                      /* u[j*n_seg + s]: amplitude of H_j on
                                            [edges[s], edges[s+1])            */
+  const double *fn;                     /* NULL, or fn[7*j .. 7*j+6] =
+                                           (c0, c1, c2, c3, a, w, phi): the
+                                           amplitude of H_j is the function
+                                           c0 + c1 t + c2 t^2 + c3 t^3
+                                           + a cos(w t + phi) (segments then
+                                           unused)                           */
 } orc_system;
 
 /* out = L(t) y, the right-hand side of the Lindblad equation. */
@@ -67,13 +73,17 @@ int orc_apply_Ldag(const orc_system *s, double t, const double *x, double *out);
 int orc_expect(const orc_system *s, const double *rho, double *out);
 
 /* Classic fixed-step RK4 from tlist[0] to tlist[n_t-1] in nsteps equal steps.
+ * Piecewise-constant amplitudes: every stage of a step uses the segment
+ * holding the step's midpoint.  Function amplitudes (fn): each stage uses
+ * the amplitudes at its own time t, t + h/2, t + h/2, t + h (the classic
+ * scheme for a time-dependent right-hand side).
  * expect: [n_e][n_t] complex (may be NULL when n_e == 0);
  * states: [n_t][n*n] complex or NULL. */
 int orc_rk4(const orc_system *s, const double *rho0, int32_t n_t,
             const double *tlist, int32_t nsteps, double *expect, double *states);
 
 /* Dormand-Prince 5(4) with per-step error control; steps stop exactly on every
- * output time and control edge.  h_log (may be NULL) receives the accepted step
+ * output time and control edge (ORC_EINVAL with function amplitudes).  h_log (may be NULL) receives the accepted step
  * sizes, at most h_log_cap of them.  counts[0] = accepted, counts[1] = rejected. */
 int orc_dopri5(const orc_system *s, const double *rho0, int32_t n_t,
                const double *tlist, double rtol, double atol, double h0,

@@ -115,6 +115,7 @@ class System:
     edges: np.ndarray | None = None
     u: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    fn: np.ndarray | None = None    # [n_ctrl, 7] closed-form amplitudes (see coeff_fn)
 
     @property
     def n(self):
@@ -302,6 +303,46 @@ def damped_cavity(N=5, kappa=1.0 / 0.129, n_th=0.0, n0=1):
         C.append(tidy(np.sqrt(kappa * n_th) * ad))
     return System(tidy(ad @ a), C, [tidy(ad @ a)], ket2dm(ket(N, n0)),
                   meta=dict(kappa=kappa, n_th=n_th))
+
+
+# --------------------------------------------------------------------------
+# time-dependent Hamiltonians in closed form (Sec. 4.4)
+# --------------------------------------------------------------------------
+
+def coeff_fn(c0=0.0, c1=0.0, c2=0.0, c3=0.0, a=0.0, w=0.0, phi=0.0):
+    """Parameters of the amplitude u(t) = c0 + c1 t + c2 t^2 + c3 t^3
+    + a cos(w t + phi), in the order both sides read them."""
+    return np.array([c0, c1, c2, c3, a, w, phi], np.float64)
+
+
+def landau_zener(delta=0.5 * TWO_PI, v=2.0 * TWO_PI, gamma=0.0):
+    """Landau-Zener two-level system (Sec. 4.4, Eq. (lz-hamiltonian)):
+    H(t) = delta/2 sigma_x + (v t / 2) sigma_z, written as H0 = delta/2 sigma_x
+    plus the control term sigma_z with amplitude u(t) = v t / 2; optional
+    relaxation C = sqrt(gamma) sigma-.  rho0 = |0><0| (the paper's basis(2, 0),
+    the first basis state); E-ops: the population of |1>, sigma_x, sigma_y,
+    sigma_z (the paper's sm^+ sm, sx, sy, sz with sm = destroy(2))."""
+    sm = destroy(2)
+    H0 = tidy(0.5 * delta * sigmax())
+    C = [tidy(np.sqrt(gamma) * sm)] if gamma > 0 else []
+    E = [tidy(dag(sm) @ sm), tidy(sigmax()), tidy(sigmay()), tidy(sigmaz())]
+    s = System(H0, C, E, ket2dm(ket(2, 0)), H_ctrl=[tidy(sigmaz())],
+               fn=coeff_fn(c1=0.5 * v)[None, :], meta=dict(delta=delta, v=v, gamma=gamma))
+    return s
+
+
+def landau_zener_sweep(n_inst=4096, seed=8, t0=-10.0, t1=10.0, n_out=1500, steps_per_out=20):
+    """A sweep of Landau-Zener problems: delta = 0.5 * 2pi, sweep rates v
+    log-uniform in [0.5, 8] * 2pi (final-state probability from near 0 to
+    near 1), relaxation gamma log-uniform in [1e-4, 1e-2]; RK4 on the paper's
+    grid t in [-10, 10] with 1500 outputs, steps_per_out steps between
+    outputs."""
+    rng = np.random.default_rng(seed)
+    vs = np.exp(rng.uniform(np.log(0.5), np.log(8.0), size=n_inst)) * TWO_PI
+    gs = np.exp(rng.uniform(np.log(1e-4), np.log(1e-2), size=n_inst))
+    systems = [landau_zener(v=vs[b], gamma=gs[b]) for b in range(n_inst)]
+    return Workload(f"landau_zener_{n_inst}", systems, np.linspace(t0, t1, n_out), "rk4",
+                    nsteps=(n_out - 1) * steps_per_out)
 
 
 # --------------------------------------------------------------------------

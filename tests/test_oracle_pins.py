@@ -611,3 +611,92 @@ def test_mc_runs_out_of_draws():
     d[:, :, 0] = 0.999                       # every trajectory jumps almost at once
     r = oracle.mc(s, s.meta["psi0"], np.array([0.0, 0.6]), 600, d, raise_on_error=False)
     assert r["rc"] == oracle.EDRAWS and (r["status"] == oracle.EDRAWS).all()
+
+
+# --------------------------------------------------------------------------
+# closed-form time-dependent amplitudes (Sec. 4.4)
+# --------------------------------------------------------------------------
+
+def test_apply_L_with_function_amplitudes_equals_superoperator():
+    """u_j(t) = c0 + c1 t + c2 t^2 + c3 t^3 + a cos(w t + phi) enters L(t)
+    exactly as a constant amplitude u_j(t) would (every parameter used)."""
+    s = S.random_system(4, n_c=2, n_ctrl=2, seed=61, hermitian_rho=False)
+    s.fn = np.array([S.coeff_fn(0.3, -0.7, 0.2, 0.05, 0.9, 2.1, 0.4),
+                     S.coeff_fn(-0.1, 0.0, 0.0, 0.0, 1.3, 0.7, -1.2)])
+    t = 0.83
+    u = [c[0] + c[1] * t + c[2] * t ** 2 + c[3] * t ** 3 + c[4] * np.cos(c[5] * t + c[6])
+         for c in s.fn]
+    want = brute.unvec(brute.superop(s.H0, s.C, s.H_ctrl, u) @ brute.vec(s.rho0), 4)
+    np.testing.assert_allclose(oracle.apply_L(s, s.rho0, t=t), want, atol=1e-12)
+
+
+def _phase_system(fn):
+    """H(t) = u(t) sigma_z, rho0 = |+><+|: rho_ge(t) = 1/2 exp(2i int_t0^t u)."""
+    s = S.System(S.tidy(0 * S.sigmaz()), [], [S.tidy(S.sigmam())], S.ket2dm(np.ones(2) / np.sqrt(2)),
+                 H_ctrl=[S.tidy(S.sigmaz())], fn=np.asarray(fn)[None, :])
+    return s
+
+
+def test_rk4_time_dependent_phase_closed_form_and_fourth_order():
+    """A qubit under H = u(t) sigma_z has rho_ge(t) = 1/2 exp(2i U(t)), U the
+    antiderivative of u: RK4 with every stage at its own time converges to
+    it at fourth order (the error falls ~16x per halving of h); evaluating
+    the amplitude at one time per step would cap the order at two."""
+    c = S.coeff_fn(0.4, 1.1, -0.3, 0.08, 0.9, 3.0, 0.5)
+    s = _phase_system(c)
+    t0, t1 = -0.5, 1.5
+
+    def U(t):
+        return (c[0] * t + c[1] * t ** 2 / 2 + c[2] * t ** 3 / 3 + c[3] * t ** 4 / 4
+                + c[4] / c[5] * np.sin(c[5] * t + c[6]))
+
+    tl = np.linspace(t0, t1, 5)
+    want = 0.5 * np.exp(2j * (U(tl) - U(t0)))
+    errs = []
+    for nsteps in (80, 160, 320):
+        ex, _ = oracle.rk4(s, s.rho0, tl, nsteps)   # <sigma_-> = rho_eg = conj(rho_ge)
+        errs.append(np.max(np.abs(np.conj(ex[0]) - want)))
+    assert errs[-1] < 1e-7
+    assert 12 < errs[0] / errs[1] < 20 and 12 < errs[1] / errs[2] < 20, errs
+
+
+def test_rk4_landau_zener_matches_library_integrator():
+    """The paper's Landau-Zener run (Delta = 0.5 2pi, v = 2 2pi, t in [-10, 10],
+    1500 outputs): oracle RK4 (20 and 40 steps per output) against SciPy's
+    DOP853 on the Schroedinger equation of the same Hamiltonian (rtol 1e-12):
+    within 3e-7 at 40 steps per output, and the error falls ~16x from 20."""
+    from scipy.integrate import solve_ivp
+    s = S.landau_zener()
+    d, v = s.meta["delta"], s.meta["v"]
+    tl = np.linspace(-10.0, 10.0, 1500)
+    ex20, _ = oracle.rk4(s, s.rho0, tl, 1499 * 20)
+    ex, _ = oracle.rk4(s, s.rho0, tl, 1499 * 40)
+    sx, sz = S.sigmax().toarray(), S.sigmaz().toarray()
+
+    def f(t, y):
+        psi = y[:2] + 1j * y[2:]
+        d_psi = -1j * ((0.5 * d) * sx + (0.5 * v * t) * sz) @ psi
+        return np.concatenate([d_psi.real, d_psi.imag])
+    sol = solve_ivp(f, (tl[0], tl[-1]), [1.0, 0.0, 0.0, 0.0], method="DOP853", t_eval=tl,
+                    rtol=1e-12, atol=1e-14)
+    p1 = sol.y[1] ** 2 + sol.y[3] ** 2          # population of |1>
+    e40, e20 = np.max(np.abs(ex[0].real - p1)), np.max(np.abs(ex20[0].real - p1))
+    assert e40 < 3e-7 and 12 < e20 / e40 < 20, (e20, e40)
+
+
+def test_rk4_landau_zener_final_probability_formula():
+    """Eq. (lz): long after the crossing the population moved to |1> is
+    1 - exp(-pi Delta^2 / (2 v)); the finite window [-100, 100] leaves a
+    correction ~1e-6 (it falls like 1/T^2)."""
+    s = S.landau_zener()
+    d, v = s.meta["delta"], s.meta["v"]
+    tl = np.linspace(-100.0, 100.0, 201)
+    ex, _ = oracle.rk4(s, s.rho0, tl, 200000)
+    assert abs(ex[0, -1].real - (1.0 - np.exp(-np.pi * d ** 2 / (2 * v)))) < 5e-6
+
+
+def test_function_amplitudes_are_refused_where_unsupported():
+    s = S.landau_zener()
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.dopri5(s, s.rho0, np.array([0.0, 1.0]), 1e-6, 1e-9)
+    assert e.value.code == oracle.EINVAL
