@@ -207,6 +207,23 @@ int lme_create(const lme_csr *H0, int32_t n_ctrl, const lme_csr *H_ctrl,
                const lme_segments *seg, const double *u_host, int32_t n_c,
                const lme_csr *C, int32_t n_e, const lme_csr *E, lme_handle *out);
 
+/* Closed-form amplitudes (Sec. 4.4: a time-dependent Hamiltonian given as
+ * constant operators times scalar functions of time, such as the
+ * Landau-Zener sweep H0 + t H1 of Eq. (lz-hamiltonian)).
+ *   fn_host: host double [n_inst][n_ctrl][7] = (c0, c1, c2, c3, a, w, phi),
+ *            u_j(t) = c0 + c1 t + c2 t^2 + c3 t^3 + a cos(w t + phi) for
+ *            control term j of each instance; copied.  NULL returns the
+ *            handle to its piecewise-constant segments.
+ * While set, lme_evolve integrates with fixed-step RK4 on the resident
+ * kernels, every stage evaluating the amplitudes at its own time (t,
+ * t + h/2, t + h/2, t + h); segment edges no longer constrain the grid; the
+ * u_dev override is refused; lme_apply evaluates the amplitudes at its t.
+ * LME_ENOTSUP from lme_evolve with LME_DOPRI5 or the streamed path, and from
+ * lme_cost_grad (its gradient is with respect to segment amplitudes).
+ * Errors: LME_EINVAL (NULL handle, no control terms, non-finite values),
+ * LME_ENOMEM, LME_EHIP. */
+int lme_set_coeff_fn(lme_handle h, const double *fn_host);
+
 /* Releases the handle and every device buffer it owns.  NULL is a no-op.
  * Work already queued on a stream that uses the handle must have completed. */
 void lme_destroy(lme_handle h);

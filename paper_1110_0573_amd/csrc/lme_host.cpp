@@ -281,6 +281,11 @@ struct lme_ctx {
   // lme_evolve_noalloc: host image of the tables it copies into the scratch
   // array (kept until the next such call on this handle)
   std::vector<uint8_t> na_host;
+  // closed-form amplitudes (lme_set_coeff_fn): [n_inst][n_ctrl][7], empty =
+  // piecewise-constant segments; d_fnu holds u(t) of the last lme_apply
+  std::vector<double> fn;
+  DevBuf d_fn, d_fnu;
+  std::vector<double> fnu_key;
   ~lme_ctx() {
     for (Plan *p : plans) delete p;
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -558,6 +563,37 @@ extern "C" int lme_create(const lme_csr *H0, int32_t n_ctrl, const lme_csr *H_ct
 
 extern "C" void lme_destroy(lme_handle h) { delete h; }
 
+extern "C" int lme_set_coeff_fn(lme_handle h, const double *fn_host) {
+  try {
+    if (!h) return fail(LME_EINVAL, "handle is NULL");
+    if (!fn_host) {
+      h->fn.clear();
+      h->d_fn.release();
+      h->d_fnu.release();
+      h->fnu_key.clear();
+      return LME_OK;
+    }
+    if (h->n_ctrl < 1) return fail(LME_EINVAL, "the batch has no control terms");
+    const size_t cnt = (size_t)h->n_inst * h->n_ctrl * 7;
+    for (size_t i = 0; i < cnt; ++i)
+      if (!std::isfinite(fn_host[i])) return fail(LME_EINVAL, "fn has a non-finite value");
+    std::vector<double> fn(fn_host, fn_host + cnt);
+    if (h->on_device) {
+      int rc = ensure_device(h);
+      if (rc) return rc;
+      if ((rc = h->d_fn.upload(fn.data(), cnt * sizeof(double), "closed-form amplitudes")))
+        return rc;
+    }
+    h->fn.swap(fn);
+    h->fnu_key.clear();
+    return LME_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
 extern "C" int lme_layout(lme_handle h, int32_t *n_inst, int64_t *state_elems,
                           int64_t *offsets, int32_t *dims) {
   if (!h) return fail(LME_EINVAL, "handle is NULL");
@@ -590,6 +626,9 @@ static int ensure_device(lme_ctx *h) {
   if ((rc = h->d_eops.upload(h->eops.data(), h->eops.size(), "e-op pool"))) return rc;
   if (!h->u_default.empty() &&
       (rc = h->d_u.upload(h->u_default.data(), h->u_default.size() * sizeof(double), "controls")))
+    return rc;
+  if (!h->fn.empty() &&
+      (rc = h->d_fn.upload(h->fn.data(), h->fn.size() * sizeof(double), "closed-form amplitudes")))
     return rc;
   h->on_device = true;
   return LME_OK;
@@ -892,7 +931,7 @@ static int rk4_tables(const lme_ctx *h, int32_t n_t, const double *tlist, int32_
   if (n_t > 1 && tab[nsteps + n_t - 1] != nsteps)
     return fail(LME_EGRID, "last output time is not the end of the grid");
   const double t1 = tlist[n_t - 1];
-  for (int q = 0; q <= h->n_seg && h->n_seg > 0; ++q) {
+  for (int q = 0; q <= h->n_seg && h->n_seg > 0 && h->fn.empty(); ++q) {
     const double e = h->edges[q];
     if (e > t0 && e < t1 && grid_index(e, t0, hstep) < 0)
       return fail(LME_EGRID, "control edge %.17g is not on the RK4 grid", e);
@@ -1410,6 +1449,15 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     return fail(LME_EINVAL, "hermitian must be 0 or 1");
   if (opt->layout < LME_LAYOUT_AUTO || opt->layout > LME_LAYOUT_COLUMN)
     return fail(LME_EINVAL, "unknown layout %d", opt->layout);
+  if (!h->fn.empty()) {
+    if (opt->method == LME_DOPRI5)
+      return fail(LME_ENOTSUP, "closed-form amplitudes are integrated with fixed-step RK4 only");
+    if (opt->path == LME_PATH_STREAMED)
+      return fail(LME_ENOTSUP, "closed-form amplitudes run on the resident kernels only");
+    if (u_dev)
+      return fail(LME_EINVAL, "u_dev overrides piecewise amplitudes; this handle has "
+                  "closed-form amplitudes");
+  }
   if (opt->method == LME_DOPRI5)
     return evolve_dp5(h, opt, n_t, tlist, rho0_dev, u_dev, expect_dev, states_dev, rho_out_dev,
                       counts_dev, status_dev, stream, noalloc);
@@ -1452,7 +1500,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
     if (opt->block == 768) return fail(LME_EINVAL, "block 768 exists only in the column layout");
     // the row layout has no Hermitian variant: it computes every element
     rc = pick_rk4_config(h, opt->block, &T, &EPT);
-    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !noalloc)
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !noalloc && h->fn.empty())
       streamed = true;  // an instance is too large for a resident workgroup
     else if (rc)
       return rc;
@@ -1471,7 +1519,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   Plan *plan = nullptr;
   if (!streamed) {
     rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan, 0, !noalloc);
-    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !column && !noalloc)
+    if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !column && !noalloc && h->fn.empty())
       streamed = true;
     else if (rc)
       return rc;
@@ -1507,6 +1555,8 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   }
   a.nsteps = nsteps;
   a.h = hstep;
+  a.fn = h->fn.empty() ? nullptr : static_cast<const double *>(h->d_fn.p);
+  a.t0 = tlist[0];
   a.state_elems = h->state_elems;
   a.rho0 = static_cast<const double *>(rho0_dev);
   a.rho_out = static_cast<double *>(rho_out_dev);
@@ -1663,6 +1713,36 @@ static int ensure_row_tiles(lme_ctx *h) {
 // Streamed application (stage input and result in HBM).  rows: allow the
 // row-block kernel (every instance 128 <= n <= 1024); otherwise, and for the
 // explicit streamed form, every element gathers straight from memory.
+// Controls of an application at time t: the caller's or the create-time
+// piecewise amplitudes with the segment holding t, or, with closed-form
+// amplitudes, u(t) evaluated here into a one-segment table.
+struct ApplyCtl {
+  const double *u;
+  int n_seg, seg;
+};
+
+static int apply_controls(lme_ctx *h, double t, const double *u_dev, hipStream_t s,
+                          ApplyCtl *c) {
+  if (h->fn.empty()) {
+    c->u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+    c->n_seg = h->n_seg;
+    c->seg = segment_at(h, t);
+    return LME_OK;
+  }
+  std::vector<double> uval((size_t)h->n_inst * h->n_ctrl);
+  for (size_t q = 0; q < uval.size(); ++q) uval[q] = lme::coeff_fn_at(h->fn.data() + 7 * q, t);
+  if (uval != h->fnu_key || !h->d_fnu.p) {
+    int rc = h->d_fnu.upload(uval.data(), uval.size() * sizeof(double), "amplitudes at t");
+    if (rc) return rc;
+    h->fnu_key.swap(uval);
+  }
+  (void)s;
+  c->u = static_cast<const double *>(h->d_fnu.p);
+  c->n_seg = 1;
+  c->seg = 0;
+  return LME_OK;
+}
+
 static int apply_streamed(lme_ctx *h, int adjoint, double t, const double *u_dev,
                           const void *y_dev, void *out_dev, hipStream_t s, bool rows) {
   if (h->state_elems >= (int64_t)1 << 31)
@@ -1678,10 +1758,12 @@ static int apply_streamed(lme_ctx *h, int adjoint, double t, const double *u_dev
   a.inst = static_cast<const InstDesc *>(h->d_inst.p);
   a.adjoint = adjoint;
   a.ops = static_cast<const uint8_t *>(adjoint ? h->d_adj.p : h->d_ops.p);
-  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  ApplyCtl ctl;
+  if ((rc = apply_controls(h, t, u_dev, s, &ctl))) return rc;
+  a.u = ctl.u;
   a.n_ctrl = h->n_ctrl;
-  a.n_seg = h->n_seg;
-  a.seg = segment_at(h, t);
+  a.n_seg = ctl.n_seg;
+  a.seg = ctl.seg;
   a.y = static_cast<const double *>(y_dev);
   a.out = static_cast<double *>(out_dev);
   if (rows) {
@@ -1941,10 +2023,15 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
     return fail(LME_EINVAL, "unknown form %d", form);
   if (form == LME_FORM_SUPEROP && (adjoint || h->n_ctrl > 0))
     return fail(LME_ENOTSUP, "the superoperator form is forward-only and takes no controls");
+  if (u_dev && !h->fn.empty())
+    return fail(LME_EINVAL, "u_dev overrides piecewise amplitudes; this handle has closed-form "
+                "amplitudes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int rc = ensure_device(h);
   if (rc) return rc;
   adjoint = adjoint ? 1 : 0;
+  ApplyCtl ctl;
+  if ((rc = apply_controls(h, t, u_dev, s, &ctl))) return rc;
   if (form == LME_FORM_SUPEROP) {
     if ((rc = ensure_superop(h)) || (rc = ensure_tiles(h))) return rc;
     lme::SuperArgs a;
@@ -1973,10 +2060,10 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
       a.tiles = static_cast<const lme::PTile *>(h->d_pt.p);
       a.n_tiles = h->n_pipe;
       a.recs = static_cast<const uint8_t *>(h->d_recs.p);
-      a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+      a.u = ctl.u;
       a.n_ctrl = h->n_ctrl;
-      a.n_seg = h->n_seg;
-      a.seg = segment_at(h, t);
+      a.n_seg = ctl.n_seg;
+      a.seg = ctl.seg;
       a.y = static_cast<const double *>(y_dev);
       a.out = static_cast<double *>(out_dev);
       hipError_t e = lme_internal_launch_apply_pipe(wo, nc, nb, real_structure(h), &a,
@@ -1996,10 +2083,10 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
       a.order = static_cast<const int32_t *>(cp->d_order.p);
       a.inst = static_cast<const InstDesc *>(h->d_inst.p);
       a.ops = static_cast<const uint8_t *>(h->d_ops.p);
-      a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+      a.u = ctl.u;
       a.n_ctrl = h->n_ctrl;
-      a.n_seg = h->n_seg;
-      a.seg = segment_at(h, t);
+      a.n_seg = ctl.n_seg;
+      a.seg = ctl.seg;
       a.y = static_cast<const double *>(y_dev);
       a.out = static_cast<double *>(out_dev);
       hipError_t e = lme_internal_launch_apply_col(T, wo, nc, nb, real_structure(h), &a,
@@ -2021,10 +2108,10 @@ static int apply_impl(lme_handle h, int32_t form, int32_t adjoint, double t, con
   a.inst = static_cast<const InstDesc *>(h->d_inst.p);
   a.adjoint = adjoint;
   a.ops = static_cast<const uint8_t *>(adjoint ? h->d_adj.p : h->d_ops.p);
-  a.u = u_dev ? u_dev : static_cast<const double *>(h->d_u.p);
+  a.u = ctl.u;
   a.n_ctrl = h->n_ctrl;
-  a.n_seg = h->n_seg;
-  a.seg = segment_at(h, t);
+  a.n_seg = ctl.n_seg;
+  a.seg = ctl.seg;
   a.y = static_cast<const double *>(y_dev);
   a.out = static_cast<double *>(out_dev);
   hipError_t e;
@@ -2062,6 +2149,9 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
     return fail(LME_EINVAL, "need finite t0 < t1");
   if (h->n_ctrl < 1 || h->n_seg < 1)
     return fail(LME_EINVAL, "the gradient needs control terms and segments");
+  if (!h->fn.empty())
+    return fail(LME_ENOTSUP, "the gradient is taken with respect to piecewise-constant "
+                "amplitudes; this handle has closed-form amplitudes");
   if (h->n_ctrl > 2) return fail(LME_ENOTSUP, "the gradient kernel takes at most 2 control terms");
   const double hstep = (t1 - t0) / nsteps;
   const double tl[2] = {t0, t1};

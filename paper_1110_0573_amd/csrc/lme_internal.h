@@ -21,6 +21,7 @@
 // i+1 of one slot next to each other, so a wave reading consecutive rows
 // reads consecutive addresses.
 #pragma once
+#include <math.h>
 #include <stdint.h>
 
 #ifdef __HIPCC__
@@ -149,6 +150,8 @@ struct Rk4Args {
   const int32_t *out_step;     // [n_t] step index after which output k is due
   int32_t nsteps;
   double h;
+  const double *fn;         // [n_inst][n_ctrl][7] closed-form amplitudes or null
+  double t0;                // time of step 0 (closed-form amplitudes)
   int64_t state_elems;
   const double *rho0;       // complex128 packed (interleaved)
   double *rho_out;
@@ -157,6 +160,12 @@ struct Rk4Args {
   int64_t *counts;          // [n_inst][2]
   int32_t *status;          // [n_inst]
 };
+
+// Closed-form amplitude c0 + c1 t + c2 t^2 + c3 t^3 + a cos(w t + phi) with
+// p = (c0, c1, c2, c3, a, w, phi).
+LME_HD inline double coeff_fn_at(const double *p, double t) {
+  return p[0] + t * (p[1] + t * (p[2] + t * p[3])) + p[4] * cos(p[5] * t + p[6]);
+}
 
 // Monte-Carlo wave-function kernel (lme_mc.hip).  Operators of one system:
 // A = -i H - 1/2 sum_n C_n^+ C_n as diagonal D[n] plus ELL off-diagonal

@@ -213,6 +213,23 @@ __device__ void write_outputs(const Rk4Args &a, const PackDesc &pk, const PackLd
   }
 }
 
+// Amplitudes of stage `stage` (0..3) of RK4 step st: the segment values
+// (the same for every stage) or, with closed-form amplitudes, their values at
+// the stage's time t, t + h/2, t + h/2, t + h.  One thread per (instance,
+// term) of the pack; the caller synchronises.
+__device__ __forceinline__ void rk4_stage_controls(const Rk4Args &a, const PackDesc &pk,
+                                                   const int32_t *ids, double *u, int st,
+                                                   int stage, int tid, int T) {
+  const double tb = a.t0 + (double)st * a.h;
+  const double ts = stage == 0 ? tb : (stage == 3 ? tb + a.h : tb + 0.5 * a.h);
+  const int seg = a.seg_of_step[st];
+  for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
+    const int b = idx / pk.nb, q = idx - b * pk.nb;
+    const int64_t c = (int64_t)ids[b] * a.n_ctrl + q;
+    u[idx] = a.fn ? coeff_fn_at(a.fn + 7 * c, ts) : (seg >= 0 ? a.u[c * a.n_seg + seg] : 0.0);
+  }
+}
+
 template <int T, int EPT>
 __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -282,13 +299,8 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
       const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
       const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
       __syncthreads();  // every reader of the previous stage input is done
-      if (stage == 0 && pk.nb > 0) {
-        const int seg = a.seg_of_step[st];
-        for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
-          const int b = idx / pk.nb, q = idx - b * pk.nb;
-          L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
-        }
-      }
+      if (pk.nb > 0 && (stage == 0 || a.fn))
+        rk4_stage_controls(a, pk, L.ids, L.u, st, stage, tid, T);
 #pragma unroll
       for (int s = 0; s < EPT; ++s) {
         const int f = tid + s * T;
@@ -859,13 +871,8 @@ __global__ __launch_bounds__(T) void rk4_herm_kernel(Rk4Args a) {
       const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
       if (!(NB == 0 && stage == 0 && staged)) {
         __syncthreads();
-        if (stage == 0 && NB > 0) {
-          const int seg = a.seg_of_step[st];
-          for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
-            const int bb = idx / pk.nb, q = idx - bb * pk.nb;
-            L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
-          }
-        }
+        if (NB > 0 && (stage == 0 || a.fn))
+          rk4_stage_controls(a, pk, L.ids, L.u, st, stage, tid, T);
 #pragma unroll
         for (int r = 0; r < EPT; ++r)
           if (r < nown) {
@@ -992,13 +999,8 @@ __global__ __launch_bounds__(T) void rk4_colown_kernel(Rk4Args a) {
       asm volatile("" : "+v"(gg));
       if (!(NB == 0 && stage == 0 && staged)) {
         __syncthreads();
-        if (stage == 0 && NB > 0) {
-          const int seg = a.seg_of_step[st];
-          for (int idx = tid; idx < pk.m * pk.nb; idx += T) {
-            const int bb = idx / pk.nb, q = idx - bb * pk.nb;
-            L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[bb] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
-          }
-        }
+        if (NB > 0 && (stage == 0 || a.fn))
+          rk4_stage_controls(a, pk, L.ids, L.u, st, stage, tid, T);
 #pragma unroll
         for (int r = 0; r < EPT; ++r)
           if (owns(gg, r)) Yb[mul24(row_of(gg, r), n) + j] = yn[r];

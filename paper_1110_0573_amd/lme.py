@@ -30,6 +30,7 @@ LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
            "lme_last_error", "lme_layout", "lme_evolve", "lme_evolve_noalloc", "lme_apply",
+           "lme_set_coeff_fn",
            "lme_cost_grad", "lme_get_tuning", "lme_set_tuning", "lme_autotune",
            "lme_mc_create", "lme_mc_destroy", "lme_mc_evolve"]
 
@@ -82,6 +83,7 @@ def load():
         lib.lme_create.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(Csr),
                                    C.POINTER(Segments), _PD, C.c_int32, C.POINTER(Csr),
                                    C.c_int32, C.POINTER(Csr), C.POINTER(H)]
+        lib.lme_set_coeff_fn.argtypes = [H, _PD]
         lib.lme_destroy.argtypes = [H]
         lib.lme_destroy.restype = None
         lib.lme_last_error.argtypes = []
@@ -244,6 +246,26 @@ class Handle:
                               self.offsets.ctypes.data_as(C.POINTER(C.c_int64)),
                               self.dims.ctypes.data_as(C.POINTER(C.c_int32))), "lme_layout")
         self.state_elems = int(tot.value)
+        fns = [getattr(s, "fn", None) for s in systems]
+        if n_ctrl and any(f is not None for f in fns):
+            if any(f is None for f in fns):
+                raise LmeError(LME_EINVAL, "closed-form amplitudes must be given for every "
+                                           "instance or none")
+            self.set_coeff_fn(np.stack([np.asarray(f, np.float64).reshape(n_ctrl, 7)
+                                        for f in fns]))
+
+    def set_coeff_fn(self, fn):
+        """lme_set_coeff_fn: fn [n_inst, n_ctrl, 7] = (c0, c1, c2, c3, a, w,
+        phi) per control term, u(t) = c0 + c1 t + c2 t^2 + c3 t^3
+        + a cos(w t + phi); None returns to the piecewise-constant segments."""
+        if fn is None:
+            _check(load().lme_set_coeff_fn(self._h, None), "lme_set_coeff_fn")
+            return
+        arr = np.ascontiguousarray(fn, np.float64)
+        if arr.size != self.n_inst * self.n_ctrl * 7:
+            raise LmeError(LME_EINVAL, f"fn has {arr.size} values, expected "
+                                       f"{self.n_inst * self.n_ctrl * 7}")
+        _check(load().lme_set_coeff_fn(self._h, arr.ctypes.data_as(_PD)), "lme_set_coeff_fn")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -358,9 +380,9 @@ class Handle:
 class _Spec:
     """One system for :func:`evolve` (the attributes Handle reads)."""
 
-    def __init__(self, H0, C, E, H_ctrl=(), edges=None, u=None):
+    def __init__(self, H0, C, E, H_ctrl=(), edges=None, u=None, fn=None):
         self.H0, self.C, self.E = H0, list(C), list(E)
-        self.H_ctrl, self.edges, self.u = list(H_ctrl), edges, u
+        self.H_ctrl, self.edges, self.u, self.fn = list(H_ctrl), edges, u, fn
 
 
 def evolve(H0, c_ops, rho0, tlist, e_ops, controls=None, method="rk4", nsteps=None,
@@ -373,7 +395,9 @@ def evolve(H0, c_ops, rho0, tlist, e_ops, controls=None, method="rk4", nsteps=No
     H0, c_ops, e_ops: square matrices (NumPy or SciPy sparse).  rho0: a ket
     (converted to |psi><psi|) or a density matrix.  controls: optional
     (H_ctrl list, edges[n_seg + 1], u[n_ctrl][n_seg]) for piecewise-constant
-    u_j(t).  method "rk4" takes nsteps equal steps over [tlist[0], tlist[-1]]
+    u_j(t), or (H_ctrl list, fn[n_ctrl][7]) for closed-form amplitudes
+    c0 + c1 t + c2 t^2 + c3 t^3 + a cos(w t + phi) (Sec. 4.4: e.g. the
+    Landau-Zener sweep, H_ctrl = [v/2 sigma_z] with fn = [(0, 1, 0, ...)]).  method "rk4" takes nsteps equal steps over [tlist[0], tlist[-1]]
     (every output time on that grid); "dopri5" adapts its steps to rtol/atol
     (atol defaults to 1e-3 rtol).  hermitian: use the Hermitian RK4 path
     (default: whenever rho0 is Hermitian).
@@ -398,9 +422,17 @@ def evolve(H0, c_ops, rho0, tlist, e_ops, controls=None, method="rk4", nsteps=No
     want_states = len(E) == 0
     if want_states:  # the batch needs one expectation operator; its values are dropped
         E = [sp.identity(n, dtype=np.complex128, format="csr")]
-    hc, edges, u = ((), None, None) if controls is None else controls
+    fn = None
+    if controls is None:
+        hc, edges, u = (), None, None
+    elif len(controls) == 2:      # (H_ctrl, fn[n_ctrl][7]): closed-form amplitudes
+        hc, fn = controls
+        edges, u = None, None
+        fn = np.asarray(fn, np.float64).reshape(len(hc), 7)
+    else:
+        hc, edges, u = controls
     spec = _Spec(H0, [m(c) for c in c_ops], E, [m(x) for x in hc], edges,
-                 None if u is None else np.asarray(u, np.float64))
+                 None if u is None else np.asarray(u, np.float64), fn)
     tlist = np.asarray(tlist, np.float64)
     if method == "rk4" and nsteps is None:
         raise LmeError(LME_EINVAL, "rk4 needs nsteps")

@@ -274,3 +274,25 @@ def test_mc_create_and_evolve_validation_before_device_use():
         assert e.value.code == lme.LME_EINVAL
     lib.lme_mc_destroy(None)
     h.close()
+
+
+def test_set_coeff_fn_validation():
+    lib = lme.load()
+    assert lib.lme_set_coeff_fn(None, None) == lme.LME_EINVAL
+    h, w = _handle()                       # no control terms
+    with pytest.raises(lme.LmeError) as e:
+        h.set_coeff_fn(np.zeros((3, 1, 7)))
+    assert e.value.code == lme.LME_EINVAL
+    wd = S.jc_drive(n_inst=2, N=3, n_seg=2, t_end=1.0, steps_per_seg=2)
+    hd = lme.Handle(wd.systems)
+    bad = np.zeros((2, 1, 7))
+    bad[1, 0, 4] = np.inf
+    with pytest.raises(lme.LmeError) as e:
+        hd.set_coeff_fn(bad)
+    assert e.value.code == lme.LME_EINVAL
+    hd.set_coeff_fn(np.zeros((2, 1, 7)))
+    # closed-form amplitudes lift the edge grid constraint, refuse DOPRI5
+    assert _evolve_rc(hd, [0.0, 1.0], nsteps=7)[0] in (lme.LME_OK, lme.LME_EHIP)
+    assert _evolve_rc(hd, [0.0, 1.0], method=lme.LME_DOPRI5)[0] == lme.LME_ENOTSUP
+    hd.set_coeff_fn(None)
+    assert _evolve_rc(hd, [0.0, 1.0], nsteps=7)[0] == lme.LME_EGRID
