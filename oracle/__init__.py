@@ -109,6 +109,8 @@ def _lib():
             lib.orc_mc.argtypes = [P, _PD, C.c_int32, _PD, C.c_int32, C.c_int32, _PD,
                                    C.c_int32, _PD, _PD, C.POINTER(C.c_int32), _PD,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]
+            lib.orc_correlation.argtypes = [P, _PD, C.c_int32, _PD, C.c_int32, C.c_int32,
+                                            _PD, C.c_int32, C.POINTER(_Csr), _PD]
             lib.orc_rk4_batch.argtypes = [C.c_int32, P, C.POINTER(_PD), C.c_int32,
                                           _PD, C.c_int32, C.POINTER(_PD), C.c_int32,
                                           C.POINTER(C.c_int32)]
@@ -335,3 +337,25 @@ def mc(system, psi0, tlist, nsteps, draws, n_threads=1, raise_on_error=True):
         _check(rc, "mc")
     return {"expect": avg[:m.n_e], "expect_traj": per[:, :m.n_e], "n_jumps": nj,
             "jump_t": jt[:, :max_jumps], "jump_op": jo[:, :max_jumps], "status": st, "rc": rc}
+
+
+def correlation(system, rho0, tlist, nsteps, taulist, tau_nsteps, B):
+    """Two-time correlations by the quantum regression theorem:
+    corr[i, m, j] = Tr(E_m V(tau_j)[B rho(t_i)]), rho(t) and V from RK4
+    (nsteps over tlist, tau_nsteps over taulist, taulist[0] = 0)."""
+    m = _marshal(system)
+    rho0 = _cplx(rho0, (m.n, m.n))
+    tl = np.ascontiguousarray(tlist, dtype=np.float64)
+    ta = np.ascontiguousarray(taulist, dtype=np.float64)
+    Bm = sp.csr_matrix(B, dtype=np.complex128)
+    Bm.sort_indices()
+    rp = np.ascontiguousarray(Bm.indptr, dtype=np.int32)
+    ci = np.ascontiguousarray(Bm.indices, dtype=np.int32)
+    va = np.ascontiguousarray(Bm.data, dtype=np.complex128).view(np.float64)
+    Bc = _Csr(m.n, Bm.nnz, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+              ci.ctypes.data_as(C.POINTER(C.c_int32)), va.ctypes.data_as(_PD))
+    out = np.zeros((len(tl), max(1, m.n_e), len(ta)), np.complex128)
+    _check(_lib().orc_correlation(C.byref(m.s), _dptr(rho0.view(np.float64)), len(tl), _dptr(tl),
+                                  int(nsteps), len(ta), _dptr(ta), int(tau_nsteps), C.byref(Bc),
+                                  _dptr(out.view(np.float64))), "correlation")
+    return out[:, :m.n_e]

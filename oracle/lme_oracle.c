@@ -796,6 +796,53 @@ int orc_rk4_cost_grad(const orc_system *s, const double *rho0, const double *O,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Two-time correlation functions (quantum regression theorem)                 */
+/* ------------------------------------------------------------------------- */
+
+int orc_correlation(const orc_system *s, const double *rho0, int32_t n_t, const double *tlist,
+                    int32_t nsteps, int32_t n_tau, const double *taulist, int32_t tau_nsteps,
+                    const orc_csr *B, double *corr) {
+  int rc = check_system(s);
+  if (rc) return rc;
+  if (s->n_ctrl != 0 || !rho0 || !tlist || !taulist || !B || !corr || n_t < 1 || n_tau < 1)
+    return ORC_EINVAL;
+  if ((rc = check_csr(B, s->n))) return rc;
+  if (taulist[0] != 0.0) return ORC_EINVAL;
+  const int n = s->n;
+  const size_t n2 = (size_t)n * n;
+  cplx *states = (cplx *)malloc((size_t)n_t * n2 * sizeof(cplx));
+  cplx *sigma = (cplx *)malloc(n2 * sizeof(cplx));
+  double *ex_t = (double *)malloc(2 * ((size_t)s->n_e + 1) * n_t * sizeof(double));
+  double *ex_tau = (double *)malloc(2 * ((size_t)s->n_e + 1) * n_tau * sizeof(double));
+  if (!states || !sigma || !ex_t || !ex_tau) {
+    rc = ORC_ENOMEM;
+    goto done;
+  }
+  /* rho(t_i) at every t_i */
+  if ((rc = orc_rk4(s, rho0, n_t, tlist, nsteps, ex_t, (double *)states))) goto done;
+  for (int i = 0; i < n_t; ++i) {
+    /* sigma = B rho(t_i) */
+    memset(sigma, 0, n2 * sizeof(cplx));
+    mul_csr_dense(n, B, states + (size_t)i * n2, 1.0, sigma);
+    /* Tr(E_m V(tau_j) sigma) */
+    if ((rc = orc_rk4(s, (const double *)sigma, n_tau, taulist, tau_nsteps, ex_tau, NULL)))
+      goto done;
+    for (int m = 0; m < s->n_e; ++m)
+      for (int j = 0; j < n_tau; ++j) {
+        const size_t o = 2 * (((size_t)i * s->n_e + m) * n_tau + j);
+        corr[o] = ex_tau[2 * ((size_t)m * n_tau + j)];
+        corr[o + 1] = ex_tau[2 * ((size_t)m * n_tau + j) + 1];
+      }
+  }
+done:
+  free(states);
+  free(sigma);
+  free(ex_t);
+  free(ex_tau);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Monte-Carlo wave-function trajectories (Sec. 3.2)                           */
 /* ------------------------------------------------------------------------- */
 

@@ -122,6 +122,17 @@ int orc_mc(const orc_system *s, const double *psi0, int32_t n_t, const double *t
            double *expect_avg, double *expect_traj, int32_t *n_jumps, double *jump_t,
            int32_t *jump_op, int32_t *status, int32_t n_threads);
 
+/* Two-time correlation functions by the quantum regression theorem (the
+ * paper's correlation_ode, Table A1): with rho(t) the master-equation state,
+ *   corr[i][m][j] = Tr( E_m V(tau_j) [ B rho(t_i) ] ),
+ * V(tau) the evolution of Eq. (master_equation) over tau.  rho(t) comes from
+ * orc_rk4 over tlist in nsteps steps; every B rho(t_i) is evolved by orc_rk4
+ * over taulist (taulist[0] = 0, increasing) in tau_nsteps steps.  B is CSR;
+ * the system must have no control terms.  corr: [n_t][n_e][n_tau] complex. */
+int orc_correlation(const orc_system *s, const double *rho0, int32_t n_t, const double *tlist,
+                    int32_t nsteps, int32_t n_tau, const double *taulist, int32_t tau_nsteps,
+                    const orc_csr *B, double *corr);
+
 /* RK4 over many independent instances on n_threads host threads (dynamic
  * scheduling); used for timing the oracle on the host. rc[b] per instance. */
 int orc_rk4_batch(int32_t n_inst, const orc_system *systems,

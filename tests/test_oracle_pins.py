@@ -700,3 +700,53 @@ def test_function_amplitudes_are_refused_where_unsupported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.dopri5(s, s.rho0, np.array([0.0, 1.0]), 1e-6, 1e-9)
     assert e.value.code == oracle.EINVAL
+
+
+# --------------------------------------------------------------------------
+# two-time correlation functions (quantum regression theorem)
+# --------------------------------------------------------------------------
+
+def test_correlation_damped_cavity_closed_form():
+    """Cavity H = w a^+a with decay kappa (zero temperature), rho0 = |1><1|:
+    <a^+(t + tau) a(t)> = <n>(t) exp((i w - kappa/2) tau), <n>(t) = e^(-kappa t)
+    (exact in the truncated space: the state never reaches the top level)."""
+    w, kappa = 1.3, 0.7
+    a = S.destroy(5)
+    s = S.System(S.tidy(w * (S.dag(a) @ a)), [S.tidy(np.sqrt(kappa) * a)], [S.tidy(S.dag(a))],
+                 S.ket2dm(S.ket(5, 1)))
+    tl = np.linspace(0.0, 2.0, 5)
+    ta = np.linspace(0.0, 3.0, 7)
+    c = oracle.correlation(s, s.rho0, tl, 2000, ta, 3000, a)
+    want = np.exp(-kappa * tl)[:, None] * np.exp((1j * w - 0.5 * kappa) * ta)[None, :]
+    np.testing.assert_allclose(c[:, 0, :], want, atol=1e-11)
+
+
+def test_correlation_equals_exact_regression_formula():
+    """Random open system: Tr(E V(tau) [B rho(t)]) against the same quantity
+    built from dense matrix exponentials of the Kronecker superoperator, at
+    every (t, tau), within the RK4 error of h = 1e-3."""
+    s = S.random_system(4, n_c=2, n_e=2, seed=71)
+    rng = np.random.default_rng(72)
+    B = S.tidy((rng.random((4, 4)) < 0.5) * (rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))))
+    tl = np.linspace(0.0, 1.0, 3)
+    ta = np.linspace(0.0, 0.8, 5)
+    c = oracle.correlation(s, s.rho0, tl, 1000, ta, 800, B)
+    Sm = brute.superop(s.H0, s.C)
+    for i, t in enumerate(tl):
+        rt = brute.unvec(sl.expm(t * Sm) @ brute.vec(s.rho0), 4)
+        sig = B.toarray() @ rt
+        for j, tau in enumerate(ta):
+            st = brute.unvec(sl.expm(tau * Sm) @ brute.vec(sig), 4)
+            for m, E in enumerate(s.E):
+                assert abs(c[i, m, j] - np.trace(E.toarray() @ st)) < 1e-10
+
+
+def test_correlation_at_zero_delay_is_expectation_of_product():
+    """tau = 0: Tr(E B rho(t)), the expectation value of the product E B."""
+    s = S.random_system(5, n_c=2, n_e=2, seed=73)
+    B = S.tidy(S.random_system(5, n_c=0, seed=74).H0 @ S.random_system(5, n_c=0, seed=75).H0)
+    tl = np.linspace(0.0, 1.0, 4)
+    c = oracle.correlation(s, s.rho0, tl, 300, np.array([0.0, 0.1]), 100, B)
+    prod = S.System(s.H0, s.C, [S.tidy(E @ B) for E in s.E], s.rho0)
+    ex, _ = oracle.rk4(prod, s.rho0, tl, 300)
+    np.testing.assert_allclose(c[:, :, 0], ex.T, atol=1e-13)
