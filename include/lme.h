@@ -293,6 +293,28 @@ int lme_apply(lme_handle h, int32_t form, int32_t adjoint, double t,
               const double *u_dev, const void *y_dev, void *out_dev,
               void *stream);
 
+/* Two-time correlation functions by the quantum regression theorem (the
+ * correlation_ode entry of the paper's function table, Appendix A):
+ *   corr[b][i][m][j] = Tr( E_m V(tau_j) [ B_b rho_b(t_i) ] ),
+ * rho(t) the solution of Eq. (master_equation) from rho0, V(tau) the same
+ * evolution over a delay tau; for E_m = A this is <A(t_i + tau_j) B(t_i)>.
+ * rho(t) is integrated with opt (fixed-step RK4, opt->nsteps over tlist,
+ * every tlist entry on the grid); every B rho(t_i) with RK4 in tau_nsteps
+ * steps over taulist (taulist[0] = 0, increasing), all n_inst * n_t of them
+ * as one batch on the general (non-Hermitian) kernels.
+ *   B: host CSR [n_inst], B_b of dimension n_b (copied);
+ *   rho0_dev: packed initial states (lme_layout);
+ *   corr_dev: device complex128 [n_inst][n_t][n_e][n_tau];
+ *   status_dev: device int32 [n_inst] or NULL: the first device-detected
+ *               failure of the instance's evolutions.
+ * Needs a time-independent generator: LME_ENOTSUP with control terms or
+ * LME_DOPRI5.  The handle keeps a workspace of 2 n_t state copies and a
+ * batch repeated n_t times.  Asynchronous on `stream`.
+ * Errors: LME_EINVAL, LME_EGRID, LME_ENOTSUP, LME_ENOMEM, LME_EHIP. */
+int lme_correlation(lme_handle h, const lme_options *opt, int32_t n_t, const double *tlist,
+                    int32_t n_tau, const double *taulist, int32_t tau_nsteps, const lme_csr *B,
+                    const void *rho0_dev, void *corr_dev, int32_t *status_dev, void *stream);
+
 /* Cost and gradient for optimal control of piecewise-constant drives.
  * Integrates every instance with fixed-step RK4 (nsteps equal steps on
  * [t0, t1]; every control edge inside must be on that grid, else LME_EGRID)

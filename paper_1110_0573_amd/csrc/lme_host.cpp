@@ -286,7 +286,11 @@ struct lme_ctx {
   std::vector<double> fn;
   DevBuf d_fn, d_fnu;
   std::vector<double> fnu_key;
+  // two-time correlations: replicated batch and workspace (CorrCache)
+  void *corr = nullptr;
+  void (*corr_free)(void *) = nullptr;
   ~lme_ctx() {
+    if (corr && corr_free) corr_free(corr);
     for (Plan *p : plans) delete p;
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -2682,6 +2686,167 @@ extern "C" int lme_mc_evolve(lme_mc_handle h, int32_t n_t, const double *tlist, 
     return mc_evolve_impl(h, n_t, tlist, nsteps, psi0_dev, n_traj, draws_dev, max_jumps,
                           expect_dev, expect_traj_dev, n_jumps_dev, jump_t_dev, jump_op_dev,
                           status_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-time correlation functions (quantum regression theorem)
+// ---------------------------------------------------------------------------
+extern "C" hipError_t lme_internal_launch_left_mul(int n_inst, int n_t, int wB, int64_t state_elems,
+                                                   const int64_t *off, const int32_t *dims,
+                                                   const int64_t *boff, const double *Bval,
+                                                   const int32_t *Bcol, const double *states,
+                                                   double *sigma, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_corr_status(const int32_t *st1, const int32_t *st2,
+                                                      int32_t *status, int n_inst, int n_t,
+                                                      hipStream_t s);
+
+// The batch repeated `reps` times, instance b*reps + i a copy of instance b
+// (the same operators), packed instance after instance.
+static std::unique_ptr<lme_ctx> make_replica(const lme_ctx *h, int reps) {
+  std::unique_ptr<lme_ctx> r(new lme_ctx);
+  r->n_inst = h->n_inst * reps;
+  r->n_ctrl = h->n_ctrl;
+  r->n_e = h->n_e;
+  r->n_seg = 0;
+  r->ops = h->ops;
+  r->adj = h->adj;
+  r->eops = h->eops;
+  r->inst.resize((size_t)r->n_inst);
+  r->offsets.resize((size_t)r->n_inst);
+  r->dims.resize((size_t)r->n_inst);
+  for (int b = 0; b < h->n_inst; ++b)
+    for (int i = 0; i < reps; ++i) {
+      const int q = b * reps + i;
+      InstDesc d = h->inst[b];
+      const int64_t n2 = (int64_t)d.n * d.n;
+      d.rho_off = (int64_t)reps * h->offsets[b] + i * n2;
+      r->inst[q] = d;
+      r->offsets[q] = d.rho_off;
+      r->dims[q] = d.n;
+    }
+  r->state_elems = (int64_t)reps * h->state_elems;
+  return r;
+}
+
+struct CorrCache {
+  std::unique_ptr<lme_ctx> rep;
+  int reps = 0;
+  DevBuf d_states, d_sigma, d_st1, d_st2, d_boff, d_bval, d_bcol, d_off, d_dims;
+};
+
+static void corr_cache_free(void *p) { delete static_cast<CorrCache *>(p); }
+
+static int correlation_impl(lme_handle h, const lme_options *opt, int32_t n_t,
+                            const double *tlist, int32_t n_tau, const double *taulist,
+                            int32_t tau_nsteps, const lme_csr *B, const void *rho0_dev,
+                            void *corr_dev, int32_t *status_dev, void *stream) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (!opt) return fail(LME_EINVAL, "options are NULL");
+  if (!rho0_dev || !corr_dev) return fail(LME_EINVAL, "rho0 and corr are required");
+  if (!B) return fail(LME_EINVAL, "B is NULL");
+  if (h->n_ctrl > 0)
+    return fail(LME_ENOTSUP, "correlation functions need a time-independent generator (no "
+                "control terms)");
+  if (h->n_e < 1) return fail(LME_EINVAL, "correlation functions need expectation operators");
+  if (opt->method != LME_RK4) return fail(LME_ENOTSUP, "correlation functions use fixed-step RK4");
+  int rc = check_times(n_tau, taulist);
+  if (rc) return rc;
+  if (taulist[0] != 0.0) return fail(LME_EINVAL, "taulist must start at 0");
+  if (n_tau > 1 && tau_nsteps < 1) return fail(LME_EINVAL, "need tau_nsteps >= 1");
+  if ((int64_t)h->n_inst * n_t > (int64_t)1 << 30)
+    return fail(LME_ENOTSUP, "too many (instance, time) pairs");
+  // B as ELL per instance
+  int wB = 0;
+  std::vector<Sparse> Bs((size_t)h->n_inst);
+  for (int b = 0; b < h->n_inst; ++b) {
+    if ((rc = check_csr(&B[b], h->dims[b], "B", b, &Bs[b]))) return rc;
+    wB = std::max(wB, Bs[b].width());
+  }
+  wB = std::max(wB, 1);
+  std::vector<int64_t> boff((size_t)h->n_inst);
+  std::vector<cd> bval;
+  std::vector<int32_t> bcol;
+  for (int b = 0; b < h->n_inst; ++b) {
+    boff[b] = (int64_t)bval.size();
+    Ell e = to_ell(Bs[b], wB, false);
+    bval.insert(bval.end(), e.val.begin(), e.val.end());
+    bcol.insert(bcol.end(), e.col.begin(), e.col.end());
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = ensure_device(h))) return rc;
+  if (!h->corr) {
+    h->corr = new CorrCache;
+    h->corr_free = corr_cache_free;
+  }
+  CorrCache *cc = static_cast<CorrCache *>(h->corr);
+  if (cc->reps != n_t || !cc->rep) {
+    cc->rep = make_replica(h, n_t);
+    cc->reps = n_t;
+  }
+  lme_ctx *rep = cc->rep.get();
+  auto ensure = [&](DevBuf &buf, size_t bytes, const char *what) -> int {
+    if (buf.p && buf.bytes >= bytes) return LME_OK;
+    buf.release();
+    hipError_t e = hipMalloc(&buf.p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+      buf.p = nullptr;
+      return fail(LME_ENOMEM, "hipMalloc(%s, %zu B) failed", what, bytes);
+    }
+    buf.bytes = std::max<size_t>(bytes, 16);
+    return LME_OK;
+  };
+  const size_t sbytes = (size_t)n_t * h->state_elems * 16;
+  if ((rc = ensure(cc->d_states, sbytes, "states at the first times"))) return rc;
+  if ((rc = ensure(cc->d_sigma, sbytes, "B rho(t)"))) return rc;
+  if ((rc = ensure(cc->d_st1, 4 * (size_t)h->n_inst, "status"))) return rc;
+  if ((rc = ensure(cc->d_st2, 4 * (size_t)h->n_inst * n_t, "status"))) return rc;
+  if ((rc = cc->d_boff.upload(boff.data(), boff.size() * 8, "B offsets"))) return rc;
+  if ((rc = cc->d_bval.upload(bval.data(), bval.size() * 16, "B values"))) return rc;
+  if ((rc = cc->d_bcol.upload(bcol.data(), bcol.size() * 4, "B columns"))) return rc;
+  if ((rc = cc->d_off.upload(h->offsets.data(), h->offsets.size() * 8, "offsets"))) return rc;
+  if ((rc = cc->d_dims.upload(h->dims.data(), h->dims.size() * 4, "dims"))) return rc;
+  // 1. rho(t_i) for every first time
+  lme_options o1 = *opt;
+  if ((rc = evolve_impl(h, &o1, n_t, tlist, rho0_dev, nullptr, nullptr, cc->d_states.p, nullptr,
+                        nullptr, static_cast<int32_t *>(cc->d_st1.p), stream, false)))
+    return rc;
+  // 2. sigma = B rho(t_i), packed as the replicated batch
+  hipError_t e = lme_internal_launch_left_mul(
+      h->n_inst, n_t, wB, h->state_elems, static_cast<const int64_t *>(cc->d_off.p),
+      static_cast<const int32_t *>(cc->d_dims.p), static_cast<const int64_t *>(cc->d_boff.p),
+      static_cast<const double *>(cc->d_bval.p), static_cast<const int32_t *>(cc->d_bcol.p),
+      static_cast<const double *>(cc->d_states.p), static_cast<double *>(cc->d_sigma.p), s);
+  if (e != hipSuccess) return hip_fail(e, "launch B rho(t)");
+  // 3. Tr(E_m V(tau_j) sigma) for every (instance, first time); sigma is not
+  // Hermitian, so the general kernels run
+  lme_options o2 = *opt;
+  o2.nsteps = tau_nsteps;
+  o2.hermitian = 0;
+  o2.path = LME_PATH_AUTO;
+  if ((rc = evolve_impl(rep, &o2, n_tau, taulist, cc->d_sigma.p, nullptr, corr_dev, nullptr,
+                        nullptr, nullptr, static_cast<int32_t *>(cc->d_st2.p), stream, false)))
+    return rc;
+  if (status_dev) {
+    e = lme_internal_launch_corr_status(static_cast<const int32_t *>(cc->d_st1.p),
+                                        static_cast<const int32_t *>(cc->d_st2.p), status_dev,
+                                        h->n_inst, n_t, s);
+    if (e != hipSuccess) return hip_fail(e, "launch correlation status");
+  }
+  return LME_OK;
+}
+
+extern "C" int lme_correlation(lme_handle h, const lme_options *opt, int32_t n_t,
+                               const double *tlist, int32_t n_tau, const double *taulist,
+                               int32_t tau_nsteps, const lme_csr *B, const void *rho0_dev,
+                               void *corr_dev, int32_t *status_dev, void *stream) {
+  try {
+    return correlation_impl(h, opt, n_t, tlist, n_tau, taulist, tau_nsteps, B, rho0_dev,
+                            corr_dev, status_dev, stream);
   } catch (const std::bad_alloc &) {
     return fail(LME_ENOMEM, "out of host memory");
   } catch (...) {

@@ -30,7 +30,7 @@ LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
            "lme_last_error", "lme_layout", "lme_evolve", "lme_evolve_noalloc", "lme_apply",
-           "lme_set_coeff_fn",
+           "lme_set_coeff_fn", "lme_correlation",
            "lme_cost_grad", "lme_get_tuning", "lme_set_tuning", "lme_autotune",
            "lme_mc_create", "lme_mc_destroy", "lme_mc_evolve"]
 
@@ -84,6 +84,9 @@ def load():
                                    C.POINTER(Segments), _PD, C.c_int32, C.POINTER(Csr),
                                    C.c_int32, C.POINTER(Csr), C.POINTER(H)]
         lib.lme_set_coeff_fn.argtypes = [H, _PD]
+        lib.lme_correlation.argtypes = [H, C.POINTER(Options), C.c_int32, _PD, C.c_int32, _PD,
+                                        C.c_int32, C.POINTER(Csr), C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
         lib.lme_destroy.argtypes = [H]
         lib.lme_destroy.restype = None
         lib.lme_last_error.argtypes = []
@@ -364,6 +367,32 @@ class Handle:
         for k, v in kw.items():
             setattr(t, k, v)
         _check(load().lme_set_tuning(self._h, C.byref(t)), "lme_set_tuning")
+
+    def correlation(self, rho0, tlist, nsteps, taulist, tau_nsteps, B, hermitian=False,
+                    stream=None):
+        """lme_correlation: corr[b, i, m, j] = Tr(E_m V(tau_j)[B_b rho_b(t_i)])
+        (quantum regression theorem).  B: one matrix per instance (or one for
+        all).  Returns (corr device tensor [n_inst, n_t, n_e, n_tau], status)."""
+        import torch
+        self._check_state(rho0, "rho0")
+        tl = np.ascontiguousarray(tlist, np.float64)
+        ta = np.ascontiguousarray(taulist, np.float64)
+        Bs = list(B) if isinstance(B, (list, tuple)) else [B] * self.n_inst
+        if len(Bs) != self.n_inst:
+            raise LmeError(LME_EINVAL, f"{len(Bs)} B matrices for {self.n_inst} instances")
+        keep = _CsrKeep()
+        Barr = keep.array([sp.csr_matrix(b, dtype=np.complex128) for b in Bs])
+        opt = default_options(method=LME_RK4, nsteps=int(nsteps),
+                              hermitian=1 if hermitian else 0)
+        corr = torch.zeros((self.n_inst, len(tl), self.n_e, len(ta)), dtype=torch.complex128,
+                           device=rho0.device)
+        status = torch.full((self.n_inst,), -1, dtype=torch.int32, device=rho0.device)
+        rc = load().lme_correlation(self._h, C.byref(opt), len(tl), tl.ctypes.data_as(_PD),
+                                    len(ta), ta.ctypes.data_as(_PD), int(tau_nsteps),
+                                    C.cast(Barr, C.POINTER(Csr)), _ptr(rho0), _ptr(corr),
+                                    _ptr(status), _stream_ptr(stream))
+        _check(rc, "lme_correlation")
+        return corr, status
 
     def apply(self, y, t=0.0, adjoint=False, form=LME_FORM_OPERATOR, u=None, stream=None):
         """out = L(t) y (or L^+ y) for every instance of the packed batch."""

@@ -345,6 +345,30 @@ def landau_zener_sweep(n_inst=4096, seed=8, t0=-10.0, t1=10.0, n_out=1500, steps
                     nsteps=(n_out - 1) * steps_per_out)
 
 
+def jc_correlation_sweep(n_inst=64, seed=9, n_t=26, n_tau=101):
+    """First-order coherence <a^+(t + tau) a(t)> of a sweep of damped JC
+    systems (the JC sweep's parameter draws, N ~ U{5..20}), rho0 = |1, g>:
+    first times t on [0, 25] (n_t points), delays tau on [0, 25] (n_tau
+    points), RK4 with h = 0.025 on both axes; B = a, E-ops a^+ (and a^+a,
+    sigma_z kept from the JC system for context)."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.integers(5, 21, size=n_inst)
+    gs = rng.uniform(0.01, 0.2, size=n_inst) * TWO_PI
+    ds = rng.uniform(-0.5, 0.5, size=n_inst)
+    ks = np.exp(rng.uniform(np.log(1e-3), np.log(1e-1), size=n_inst))
+    gm = np.exp(rng.uniform(np.log(1e-3), np.log(1e-1), size=n_inst))
+    systems, Bs = [], []
+    for b in range(n_inst):
+        s = jc_system(int(Ns[b]), wc=1.0, wa=1.0 + ds[b], g=gs[b], kappa=ks[b], gamma=gm[b])
+        a = jc_ops(int(Ns[b]))[0]
+        s.E = [tidy(dag(a))] + s.E
+        systems.append(s)
+        Bs.append(tidy(a))
+    return Workload(f"jc_correlation_{n_inst}", systems, np.linspace(0.0, 25.0, n_t), "rk4",
+                    nsteps=1000, extra=dict(B=Bs, taulist=np.linspace(0.0, 25.0, n_tau),
+                                            tau_nsteps=1000))
+
+
 # --------------------------------------------------------------------------
 # Monte-Carlo workloads (Sec. 3.2 and Sec. 4.3)
 # --------------------------------------------------------------------------

@@ -296,3 +296,28 @@ def test_set_coeff_fn_validation():
     assert _evolve_rc(hd, [0.0, 1.0], method=lme.LME_DOPRI5)[0] == lme.LME_ENOTSUP
     hd.set_coeff_fn(None)
     assert _evolve_rc(hd, [0.0, 1.0], nsteps=7)[0] == lme.LME_EGRID
+
+
+def test_correlation_validation_before_device_use():
+    lib = lme.load()
+    h, w = _handle()
+    o = lme.default_options(nsteps=10)
+    tl = np.array([0.0, 1.0])
+    keep = lme._CsrKeep()
+    Bs = keep.array([S.jc_ops(s.n // 2)[0] for s in w.systems])
+
+    def rc(ta, B=Bs, opt=o, tns=10):
+        ta = np.ascontiguousarray(ta, np.float64)
+        return lib.lme_correlation(h._h, C.byref(opt), 2, tl.ctypes.data_as(C.POINTER(C.c_double)),
+                                   len(ta), ta.ctypes.data_as(C.POINTER(C.c_double)), tns,
+                                   C.cast(B, C.POINTER(lme.Csr)) if B is not None else None,
+                                   C.c_void_p(16), C.c_void_p(32), None, None)
+    assert rc([0.5, 1.0]) == lme.LME_EINVAL                 # delays must start at 0
+    assert rc([0.0, 1.0], B=None) == lme.LME_EINVAL
+    assert rc([0.0, 1.0], tns=0) == lme.LME_EINVAL
+    assert rc([0.0, 1.0], opt=lme.default_options(method=lme.LME_DOPRI5)) == lme.LME_ENOTSUP
+    bad = keep.array([S.jc_ops(2)[0]] * 3)                  # wrong dimensions
+    assert rc([0.0, 1.0], B=bad) == lme.LME_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        assert rc([0.0, 1.0]) == lme.LME_EHIP
