@@ -109,6 +109,8 @@ def _lib():
             lib.orc_mc.argtypes = [P, _PD, C.c_int32, _PD, C.c_int32, C.c_int32, _PD,
                                    C.c_int32, _PD, _PD, C.POINTER(C.c_int32), _PD,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]
+            lib.orc_propagator.argtypes = [P, C.c_double, C.c_double, C.c_int32, _PD]
+            lib.orc_steadystate.argtypes = [P, _PD]
             lib.orc_correlation.argtypes = [P, _PD, C.c_int32, _PD, C.c_int32, C.c_int32,
                                             _PD, C.c_int32, C.POINTER(_Csr), _PD]
             lib.orc_rk4_batch.argtypes = [C.c_int32, P, C.POINTER(_PD), C.c_int32,
@@ -359,3 +361,23 @@ def correlation(system, rho0, tlist, nsteps, taulist, tau_nsteps, B):
                                   int(nsteps), len(ta), _dptr(ta), int(tau_nsteps), C.byref(Bc),
                                   _dptr(out.view(np.float64))), "correlation")
     return out[:, :m.n_e]
+
+
+def propagator(system, t0, t1, nsteps):
+    """U with vec(rho(t1)) = U vec(rho(t0)) (row-major vec), from RK4 on each
+    basis matrix; returned as an n^2 x n^2 array."""
+    m = _marshal(system)
+    N = m.n * m.n
+    U = np.zeros((N, N), np.complex128)          # column-major storage: U.T here
+    _check(_lib().orc_propagator(C.byref(m.s), float(t0), float(t1), int(nsteps),
+                                 _dptr(U.view(np.float64))), "propagator")
+    return U.T.copy()
+
+
+def steadystate(system):
+    """The density matrix with L rho = 0 and Tr rho = 1 (Gaussian elimination
+    on the explicit superoperator with the trace condition)."""
+    m = _marshal(system)
+    rho = np.zeros((m.n, m.n), np.complex128)
+    _check(_lib().orc_steadystate(C.byref(m.s), _dptr(rho.view(np.float64))), "steadystate")
+    return rho

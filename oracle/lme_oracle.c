@@ -796,6 +796,115 @@ int orc_rk4_cost_grad(const orc_system *s, const double *rho0, const double *O,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Propagator and steady state                                                 */
+/* ------------------------------------------------------------------------- */
+
+int orc_propagator(const orc_system *s, double t0, double t1, int32_t nsteps, double *U) {
+  int rc = check_system(s);
+  if (rc) return rc;
+  if (!U || nsteps < 1 || !(t1 > t0)) return ORC_EINVAL;
+  const int n = s->n;
+  const size_t n2 = (size_t)n * n;
+  cplx *basis = (cplx *)calloc(n2, sizeof(cplx));
+  cplx *states = (cplx *)malloc(2 * n2 * sizeof(cplx));
+  double *ex = (double *)malloc(4 * ((size_t)s->n_e + 1) * sizeof(double));
+  if (!basis || !states || !ex) {
+    free(basis);
+    free(states);
+    free(ex);
+    return ORC_ENOMEM;
+  }
+  const double tl[2] = {t0, t1};
+  for (size_t c = 0; c < n2 && rc == ORC_OK; ++c) {
+    basis[c] = 1.0; /* |i><j| with c = i*n + j */
+    rc = orc_rk4(s, (const double *)basis, 2, tl, nsteps, ex, (double *)states);
+    basis[c] = 0.0;
+    if (rc == ORC_OK) memcpy((cplx *)U + c * n2, states + n2, n2 * sizeof(cplx));
+  }
+  free(basis);
+  free(states);
+  free(ex);
+  return rc;
+}
+
+int orc_steadystate(const orc_system *s, double *rho) {
+  int rc = check_system(s);
+  if (rc) return rc;
+  if (!rho || s->n_ctrl != 0) return ORC_EINVAL;
+  const int n = s->n;
+  const size_t N = (size_t)n * n;
+  cplx *M = (cplx *)calloc(N * N, sizeof(cplx)); /* row-major M[r*N + c] */
+  cplx *x = (cplx *)calloc(N, sizeof(cplx));
+  cplx *out = (cplx *)malloc(N * sizeof(cplx));
+  double *uval = (double *)calloc((size_t)s->n_ctrl + 1, sizeof(double));
+  work_t w;
+  if (!M || !x || !out || !uval || work_init(&w, n)) {
+    free(M);
+    free(x);
+    free(out);
+    free(uval);
+    return ORC_ENOMEM;
+  }
+  /* column c of the superoperator: L applied to the basis matrix |i><j| */
+  for (size_t c = 0; c < N; ++c) {
+    x[c] = 1.0;
+    lindblad(s, uval, x, out, &w);
+    x[c] = 0.0;
+    for (size_t r = 0; r < N; ++r) M[r * N + c] = out[r];
+  }
+  /* the trace condition replaces row 0: sum_i rho_ii = 1 */
+  cplx *b = x; /* right-hand side, reused */
+  for (size_t c = 0; c < N; ++c) M[c] = 0.0;
+  for (int i = 0; i < n; ++i) M[(size_t)i * n + i] = 1.0;
+  memset(b, 0, N * sizeof(cplx));
+  b[0] = 1.0;
+  /* Gaussian elimination with partial pivoting */
+  for (size_t k = 0; k < N && rc == ORC_OK; ++k) {
+    size_t p = k;
+    double best = cabs(M[k * N + k]);
+    for (size_t r = k + 1; r < N; ++r)
+      if (cabs(M[r * N + k]) > best) {
+        best = cabs(M[r * N + k]);
+        p = r;
+      }
+    if (!(best > 0.0)) {
+      rc = ORC_ENONFINITE; /* singular: no unique steady state */
+      break;
+    }
+    if (p != k) {
+      for (size_t c = 0; c < N; ++c) {
+        const cplx tmp = M[k * N + c];
+        M[k * N + c] = M[p * N + c];
+        M[p * N + c] = tmp;
+      }
+      const cplx tb = b[k];
+      b[k] = b[p];
+      b[p] = tb;
+    }
+    for (size_t r = k + 1; r < N; ++r) {
+      const cplx f = M[r * N + k] / M[k * N + k];
+      if (f == 0.0) continue;
+      for (size_t c = k; c < N; ++c) M[r * N + c] -= f * M[k * N + c];
+      b[r] -= f * b[k];
+    }
+  }
+  if (rc == ORC_OK) {
+    for (size_t k = N; k-- > 0;) {
+      cplx acc = b[k];
+      for (size_t c = k + 1; c < N; ++c) acc -= M[k * N + c] * out[c];
+      out[k] = acc / M[k * N + k];
+    }
+    memcpy(rho, out, N * sizeof(cplx));
+  }
+  work_free(&w);
+  free(M);
+  free(x);
+  free(out);
+  free(uval);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Two-time correlation functions (quantum regression theorem)                 */
 /* ------------------------------------------------------------------------- */
 

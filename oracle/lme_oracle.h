@@ -133,6 +133,19 @@ int orc_correlation(const orc_system *s, const double *rho0, int32_t n_t, const 
                     int32_t nsteps, int32_t n_tau, const double *taulist, int32_t tau_nsteps,
                     const orc_csr *B, double *corr);
 
+/* Propagator (the paper's propagator, Table A1): the linear map U with
+ * rho(t1) = U rho(t0), as the n^2 x n^2 matrix acting on row-major vec(rho):
+ * column c = i*n + j is vec of the RK4 solution (nsteps steps) from
+ * rho(t0) = |i><j|.  U: n^2 * n^2 complex, column-major (U[c*n^2 + r]). */
+int orc_propagator(const orc_system *s, double t0, double t1, int32_t nsteps, double *U);
+
+/* Steady state (the paper's steadystate, Table A1): the density matrix with
+ * L rho = 0 and Tr rho = 1, from the explicit n^2 x n^2 superoperator of
+ * Eq. (master_equation) (time-independent: no control terms) with the
+ * trace condition in place of its first row, solved by Gaussian
+ * elimination with partial pivoting.  rho: n*n complex. */
+int orc_steadystate(const orc_system *s, double *rho);
+
 /* RK4 over many independent instances on n_threads host threads (dynamic
  * scheduling); used for timing the oracle on the host. rc[b] per instance. */
 int orc_rk4_batch(int32_t n_inst, const orc_system *systems,

@@ -750,3 +750,56 @@ def test_correlation_at_zero_delay_is_expectation_of_product():
     prod = S.System(s.H0, s.C, [S.tidy(E @ B) for E in s.E], s.rho0)
     ex, _ = oracle.rk4(prod, s.rho0, tl, 300)
     np.testing.assert_allclose(c[:, :, 0], ex.T, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# propagator and steady state
+# --------------------------------------------------------------------------
+
+def test_propagator_equals_taylor_power_and_exact_map():
+    """U(t1, t0) of fixed-step RK4 is exactly P(hS)^N (P the fourth-order
+    Taylor polynomial, S the Kronecker superoperator) and within the RK4
+    error of expm((t1 - t0) S)."""
+    s = S.random_system(3, n_c=2, seed=81)
+    Sm = brute.superop(s.H0, s.C)
+    U = oracle.propagator(s, 0.2, 1.0, 40)
+    want = np.linalg.matrix_power(brute.rk4_map(Sm, 0.8 / 40), 40)
+    np.testing.assert_allclose(U, want, atol=1e-13)
+    assert np.max(np.abs(U - sl.expm(0.8 * Sm))) < 1e-7
+
+
+def test_steadystate_thermal_cavity_detailed_balance():
+    """Damped cavity with thermal excitation: decay sqrt(kappa(1+n)) a and
+    excitation sqrt(kappa n) a^+ obey detailed balance level by level, so even
+    in the truncated space the steady state is diagonal with
+    p_k proportional to (n/(1+n))^k."""
+    nth = 0.3
+    s = S.damped_cavity(N=6, kappa=0.8, n_th=nth)
+    rho = oracle.steadystate(s)
+    q = (nth / (1 + nth)) ** np.arange(6)
+    np.testing.assert_allclose(rho, np.diag(q / q.sum()), atol=1e-13)
+
+
+def test_steadystate_driven_two_level_optical_bloch():
+    """Resonance fluorescence: H = Delta/2 sigma_z + Omega/2 sigma_x, decay
+    sqrt(Gamma) sigma-: rho_ee = (Omega^2/4) / (Delta^2 + Gamma^2/4 + Omega^2/2)
+    and rho_eg = (Omega/2)(Delta + i Gamma/2)... checked through the
+    excited population and L rho = 0, Tr rho = 1, rho = rho^+."""
+    D, Om, G = 0.7, 1.3, 0.9
+    s = S.System(S.tidy(0.5 * D * S.sigmaz() + 0.5 * Om * S.sigmax()),
+                 [S.tidy(np.sqrt(G) * S.sigmam())], [], np.eye(2) / 2)
+    rho = oracle.steadystate(s)
+    assert abs(rho[1, 1] - (Om ** 2 / 4) / (D ** 2 + G ** 2 / 4 + Om ** 2 / 2)) < 1e-14
+    assert abs(np.trace(rho) - 1) < 1e-14 and np.max(np.abs(rho - rho.conj().T)) < 1e-14
+    assert np.max(np.abs(oracle.apply_L(s, rho))) < 1e-14
+
+
+def test_steadystate_is_the_long_time_limit():
+    """A random open system: the steady state is a fixed point of the
+    propagator over any time and the limit of the evolution."""
+    s = S.random_system(4, n_c=3, seed=83)
+    rho = oracle.steadystate(s)
+    Sm = brute.superop(s.H0, s.C)
+    np.testing.assert_allclose(brute.unvec(sl.expm(50.0 * Sm) @ brute.vec(s.rho0), 4), rho,
+                               atol=1e-10)
+    np.testing.assert_allclose(Sm @ brute.vec(rho), 0, atol=1e-13)
