@@ -438,6 +438,49 @@ int lme_mc_evolve(lme_mc_handle h, int32_t n_t, const double *tlist, int32_t nst
                   int32_t *n_jumps_dev, double *jump_t_dev, int32_t *jump_op_dev,
                   int32_t *status_dev, void *stream);
 
+/* Propagator (the propagator entry of the paper's function table,
+ * Appendix A): for every instance the n^2 x n^2 matrix U_b with
+ * vec(rho(t1)) = U_b vec(rho(t0)), vec row-major (element i n + j of vec is
+ * rho[i][j]) and U the fixed-step RK4 map of Eq. (master_equation) in
+ * opt->nsteps steps.  Column c = i n + j of U_b is the solution from the
+ * basis matrix |i><j|; the n^2 basis matrices of all instances are evolved
+ * as one batch on the general (non-Hermitian) kernels.
+ *   U_dev: device complex128, instance blocks of n_b^4 elements one after
+ *          another (block b at sum_{b'<b} n_{b'}^4), each column-major:
+ *          U_b[r][c] at element c n_b^2 + r of the block;
+ *   status_dev: device int32 [n_inst] or NULL: the first device-detected
+ *               failure among the instance's basis evolutions.
+ * Needs a time-independent generator (no control terms: LME_ENOTSUP) and
+ * opt->method LME_RK4; n_b <= 128.  The handle keeps the batch repeated
+ * n_b^2 times.  Asynchronous on `stream`.
+ * Errors: LME_EINVAL, LME_ENOTSUP, LME_ENOMEM, LME_EHIP. */
+int lme_propagator(lme_handle h, const lme_options *opt, double t0, double t1, void *U_dev,
+                   int32_t *status_dev, void *stream);
+
+/* Steady state (the steadystate and propagator_steadystate entries of the
+ * paper's function table, Appendix A): the density matrix rho_ss with
+ * L rho_ss = 0 and Tr rho_ss = 1, as the limit of repeated propagation.
+ * U = U(T) as in lme_propagator over [0, T] (opt->nsteps RK4 steps), then
+ * U <- U U (complex FP64 products on the matrix cores) until, for every
+ * instance, max |U_new - U_old| <= tol max |U_new| or max_squarings products
+ * are done; the columns of the limit are Tr(X) rho_ss, and rho_ss is column
+ * 0 (the image of |0><0|) divided by its trace.  The fixed points of the
+ * RK4 map are exactly the null space of L, so the limit carries no
+ * time-step error; T sets the convergence rate (the gap of L times T
+ * 2^k).
+ *   T > 0; max_squarings in [0, 200]; tol >= 0 (0 means 1e-12);
+ *   rho_ss_dev: packed states (lme_layout), written for every instance;
+ *   status_dev: device int32 [n_inst] or NULL: LME_OK (converged),
+ *               LME_EMAXSTEPS (not within max_squarings; rho_ss_dev holds
+ *               the last iterate) or LME_ENONFINITE;
+ *   squarings: host int32 or NULL, the number of products done.
+ * Synchronises `stream` once per product (the convergence test).  The
+ * handle keeps two propagator sets.
+ * Errors: LME_EINVAL, LME_ENOTSUP, LME_ENOMEM, LME_EHIP. */
+int lme_steadystate(lme_handle h, const lme_options *opt, double T, int32_t max_squarings,
+                    double tol, void *rho_ss_dev, int32_t *status_dev, int32_t *squarings,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

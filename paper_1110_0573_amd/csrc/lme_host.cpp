@@ -2705,11 +2705,13 @@ extern "C" hipError_t lme_internal_launch_corr_status(const int32_t *st1, const 
                                                       int32_t *status, int n_inst, int n_t,
                                                       hipStream_t s);
 
-// The batch repeated `reps` times, instance b*reps + i a copy of instance b
-// (the same operators), packed instance after instance.
-static std::unique_ptr<lme_ctx> make_replica(const lme_ctx *h, int reps) {
+// The batch with instance b repeated reps[b] times (copies share the
+// operators), the copies of b packed one after another, instances in order.
+static std::unique_ptr<lme_ctx> make_replica(const lme_ctx *h, const std::vector<int> &reps) {
   std::unique_ptr<lme_ctx> r(new lme_ctx);
-  r->n_inst = h->n_inst * reps;
+  int64_t total = 0;
+  for (int b = 0; b < h->n_inst; ++b) total += reps[b];
+  r->n_inst = (int32_t)total;
   r->n_ctrl = h->n_ctrl;
   r->n_e = h->n_e;
   r->n_seg = 0;
@@ -2719,27 +2721,38 @@ static std::unique_ptr<lme_ctx> make_replica(const lme_ctx *h, int reps) {
   r->inst.resize((size_t)r->n_inst);
   r->offsets.resize((size_t)r->n_inst);
   r->dims.resize((size_t)r->n_inst);
+  int q = 0;
+  int64_t off = 0;
   for (int b = 0; b < h->n_inst; ++b)
-    for (int i = 0; i < reps; ++i) {
-      const int q = b * reps + i;
+    for (int i = 0; i < reps[b]; ++i, ++q) {
       InstDesc d = h->inst[b];
-      const int64_t n2 = (int64_t)d.n * d.n;
-      d.rho_off = (int64_t)reps * h->offsets[b] + i * n2;
+      d.rho_off = off;
+      off += (int64_t)d.n * d.n;
       r->inst[q] = d;
       r->offsets[q] = d.rho_off;
       r->dims[q] = d.n;
     }
-  r->state_elems = (int64_t)reps * h->state_elems;
+  r->state_elems = off;
   return r;
+}
+
+static std::unique_ptr<lme_ctx> make_replica(const lme_ctx *h, int reps) {
+  return make_replica(h, std::vector<int>((size_t)h->n_inst, reps));
 }
 
 struct CorrCache {
   std::unique_ptr<lme_ctx> rep;
   int reps = 0;
   DevBuf d_states, d_sigma, d_st1, d_st2, d_boff, d_bval, d_bcol, d_off, d_dims;
+  // propagators: the batch repeated n_b^2 times, workspace of two
+  // propagator sets, their offsets, the product's tile list
+  std::unique_ptr<lme_ctx> prep;
+  DevBuf d_p0, d_p1, d_pst, d_off4, d_first, d_tiles, d_diff;
+  int n_tiles = 0;
 };
 
 static void corr_cache_free(void *p) { delete static_cast<CorrCache *>(p); }
+static CorrCache *corr_cache(lme_ctx *h);
 
 static int correlation_impl(lme_handle h, const lme_options *opt, int32_t n_t,
                             const double *tlist, int32_t n_tau, const double *taulist,
@@ -2779,11 +2792,7 @@ static int correlation_impl(lme_handle h, const lme_options *opt, int32_t n_t,
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((rc = ensure_device(h))) return rc;
-  if (!h->corr) {
-    h->corr = new CorrCache;
-    h->corr_free = corr_cache_free;
-  }
-  CorrCache *cc = static_cast<CorrCache *>(h->corr);
+  CorrCache *cc = corr_cache(h);
   if (cc->reps != n_t || !cc->rep) {
     cc->rep = make_replica(h, n_t);
     cc->reps = n_t;
@@ -2847,6 +2856,224 @@ extern "C" int lme_correlation(lme_handle h, const lme_options *opt, int32_t n_t
   try {
     return correlation_impl(h, opt, n_t, tlist, n_tau, taulist, tau_nsteps, B, rho0_dev,
                             corr_dev, status_dev, stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Propagators and the steady state of repeated propagation
+// ---------------------------------------------------------------------------
+extern "C" hipError_t lme_internal_launch_prop_identity(double *U, const int64_t *off4,
+                                                        const int32_t *dims, int n_inst,
+                                                        hipStream_t s);
+extern "C" hipError_t lme_internal_launch_zgemm(const void *tiles, int n_tiles, const int64_t *off4,
+                                                const int32_t *dims, const double *A,
+                                                const double *B, double *C, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_prop_norm_diff(double *Un, const double *Uo,
+                                                         const int64_t *off4, const int32_t *dims,
+                                                         int n_inst, int64_t max_block,
+                                                         double *tau, void *dm, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_prop_column0(const double *U, const int64_t *off4,
+                                                       const int32_t *dims, const int64_t *off2,
+                                                       int n_inst, double *rho, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_range_status(const int32_t *st, const int64_t *first,
+                                                       int32_t *status, int n_inst,
+                                                       hipStream_t s);
+
+static CorrCache *corr_cache(lme_ctx *h) {
+  if (!h->corr) {
+    h->corr = new CorrCache;
+    h->corr_free = corr_cache_free;
+  }
+  return static_cast<CorrCache *>(h->corr);
+}
+
+static int dev_ensure(DevBuf &buf, size_t bytes, const char *what) {
+  if (buf.p && buf.bytes >= bytes) return LME_OK;
+  buf.release();
+  hipError_t e = hipMalloc(&buf.p, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) {
+    buf.p = nullptr;
+    return fail(LME_ENOMEM, "hipMalloc(%s, %zu B) failed", what, bytes);
+  }
+  buf.bytes = std::max<size_t>(bytes, 16);
+  return LME_OK;
+}
+
+// Offsets of the propagator blocks: off4[b] = sum_{b' < b} n_{b'}^4.
+static std::vector<int64_t> prop_offsets(const lme_ctx *h, int64_t *total) {
+  std::vector<int64_t> off4((size_t)h->n_inst + 1, 0);
+  for (int b = 0; b < h->n_inst; ++b) {
+    const int64_t N = (int64_t)h->dims[b] * h->dims[b];
+    off4[b + 1] = off4[b] + N * N;
+  }
+  *total = off4[h->n_inst];
+  return off4;
+}
+
+// U of every instance into U_dev (column-major blocks at off4).
+static int propagator_run(lme_ctx *h, const lme_options *opt, double t0, double t1, void *U_dev,
+                          int32_t *status_dev, hipStream_t s, void *stream) {
+  int64_t total = 0;
+  std::vector<int64_t> off4 = prop_offsets(h, &total);
+  CorrCache *cc = corr_cache(h);
+  if (!cc->prep) {
+    std::vector<int> reps((size_t)h->n_inst);
+    for (int b = 0; b < h->n_inst; ++b) reps[b] = h->dims[b] * h->dims[b];
+    cc->prep = make_replica(h, reps);
+  }
+  int rc;
+  if ((rc = cc->d_off4.upload(off4.data(), off4.size() * 8, "propagator offsets"))) return rc;
+  if ((rc = cc->d_dims.upload(h->dims.data(), h->dims.size() * 4, "dims"))) return rc;
+  std::vector<int64_t> first((size_t)h->n_inst + 1, 0);
+  for (int b = 0; b < h->n_inst; ++b) first[b + 1] = first[b] + (int64_t)h->dims[b] * h->dims[b];
+  if ((rc = cc->d_first.upload(first.data(), first.size() * 8, "replica ranges"))) return rc;
+  if ((rc = dev_ensure(cc->d_p1, (size_t)total * 16, "basis matrices"))) return rc;
+  if ((rc = dev_ensure(cc->d_pst, 4 * (size_t)first[h->n_inst], "status"))) return rc;
+  hipError_t e = lme_internal_launch_prop_identity(static_cast<double *>(cc->d_p1.p),
+                                                   static_cast<const int64_t *>(cc->d_off4.p),
+                                                   static_cast<const int32_t *>(cc->d_dims.p),
+                                                   h->n_inst, s);
+  if (e != hipSuccess) return hip_fail(e, "launch basis matrices");
+  lme_options o = *opt;
+  o.hermitian = 0;   // the basis matrices |i><j| are not Hermitian
+  const double tl[2] = {t0, t1};
+  if ((rc = evolve_impl(cc->prep.get(), &o, 2, tl, cc->d_p1.p, nullptr, nullptr, nullptr, U_dev,
+                        nullptr, static_cast<int32_t *>(cc->d_pst.p), stream, false)))
+    return rc;
+  if (status_dev) {
+    e = lme_internal_launch_range_status(static_cast<const int32_t *>(cc->d_pst.p),
+                                         static_cast<const int64_t *>(cc->d_first.p), status_dev,
+                                         h->n_inst, s);
+    if (e != hipSuccess) return hip_fail(e, "launch propagator status");
+  }
+  return LME_OK;
+}
+
+static int prop_check(lme_ctx *h, const lme_options *opt, double t0, double t1) {
+  if (!h) return fail(LME_EINVAL, "handle is NULL");
+  if (!opt) return fail(LME_EINVAL, "options are NULL");
+  if (h->n_ctrl > 0)
+    return fail(LME_ENOTSUP, "propagators here are for time-independent generators (no control "
+                "terms)");
+  if (opt->method != LME_RK4) return fail(LME_ENOTSUP, "propagators use fixed-step RK4");
+  if (opt->nsteps < 1) return fail(LME_EINVAL, "need nsteps >= 1");
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 > t0))
+    return fail(LME_EINVAL, "need finite t1 > t0");
+  for (int b = 0; b < h->n_inst; ++b)
+    if (h->dims[b] > 128)
+      return fail(LME_ENOTSUP, "instance %d: n = %d; propagators are formed for n <= 128", b,
+                  h->dims[b]);
+  return LME_OK;
+}
+
+extern "C" int lme_propagator(lme_handle h, const lme_options *opt, double t0, double t1,
+                              void *U_dev, int32_t *status_dev, void *stream) {
+  try {
+    int rc = prop_check(h, opt, t0, t1);
+    if (rc) return rc;
+    if (!U_dev) return fail(LME_EINVAL, "U is NULL");
+    if ((rc = ensure_device(h))) return rc;
+    return propagator_run(h, opt, t0, t1, U_dev, status_dev, reinterpret_cast<hipStream_t>(stream),
+                          stream);
+  } catch (const std::bad_alloc &) {
+    return fail(LME_ENOMEM, "out of host memory");
+  } catch (...) {
+    return fail(LME_EINVAL, "unexpected host exception");
+  }
+}
+
+static int steadystate_impl(lme_handle h, const lme_options *opt, double T, int32_t max_sq,
+                            double tol, void *rho_dev, int32_t *status_dev, int32_t *squarings,
+                            void *stream) {
+  int rc = prop_check(h, opt, 0.0, T);
+  if (rc) return rc;
+  if (!rho_dev) return fail(LME_EINVAL, "rho_ss is NULL");
+  if (max_sq < 0 || max_sq > 200) return fail(LME_EINVAL, "max_squarings must be in [0, 200]");
+  if (!std::isfinite(tol) || tol < 0.0) return fail(LME_EINVAL, "tol must be finite, >= 0");
+  if (tol == 0.0) tol = 1e-12;
+  if ((rc = ensure_device(h))) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  CorrCache *cc = corr_cache(h);
+  int64_t total = 0;
+  std::vector<int64_t> off4 = prop_offsets(h, &total);
+  if ((rc = dev_ensure(cc->d_p0, (size_t)total * 16, "propagators"))) return rc;
+  if ((rc = propagator_run(h, opt, 0.0, T, cc->d_p0.p, nullptr, s, stream))) return rc;
+  // tiles of the products: 16 x 16 per wavefront, every instance
+  std::vector<int32_t> tiles;
+  for (int b = 0; b < h->n_inst; ++b) {
+    const int N = h->dims[b] * h->dims[b], nt = (N + 15) / 16;
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) {
+        tiles.push_back(b);
+        tiles.push_back(i);
+        tiles.push_back(j);
+        tiles.push_back(0);
+      }
+  }
+  if ((rc = cc->d_tiles.upload(tiles.data(), tiles.size() * 4, "product tiles"))) return rc;
+  const int n_tiles = (int)(tiles.size() / 4);
+  if ((rc = dev_ensure(cc->d_p1, (size_t)total * 16, "propagators"))) return rc;
+  if ((rc = dev_ensure(cc->d_diff, 32 * (size_t)h->n_inst, "differences"))) return rc;
+  std::vector<double> dm(2 * (size_t)h->n_inst);
+  int64_t max_block = 0;
+  for (int b = 0; b < h->n_inst; ++b) max_block = std::max(max_block, off4[b + 1] - off4[b]);
+  std::vector<int32_t> st((size_t)h->n_inst, LME_EMAXSTEPS);
+  double *P0 = static_cast<double *>(cc->d_p0.p), *P1 = static_cast<double *>(cc->d_p1.p);
+  const int64_t *doff4 = static_cast<const int64_t *>(cc->d_off4.p);
+  const int32_t *ddims = static_cast<const int32_t *>(cc->d_dims.p);
+  double *diff = static_cast<double *>(cc->d_diff.p);
+  int k = 0;
+  for (; k < max_sq; ++k) {
+    hipError_t e = lme_internal_launch_zgemm(cc->d_tiles.p, n_tiles, doff4, ddims, P0, P0, P1, s);
+    if (e != hipSuccess) return hip_fail(e, "launch propagator product");
+    // rescale to unit trace (rounding moves the eigenvalue 1 by ~1e-16, which
+    // k squarings would raise to the power 2^k), then the change and size
+    e = lme_internal_launch_prop_norm_diff(P1, P0, doff4, ddims, h->n_inst, max_block, diff,
+                                           diff + 2 * h->n_inst, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dm.data(), diff + 2 * h->n_inst, dm.size() * 8, hipMemcpyDeviceToHost,
+                         s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "propagator convergence check");
+    std::swap(P0, P1);
+    bool all = true;
+    for (int b = 0; b < h->n_inst; ++b) {
+      const double d = dm[2 * b], m = dm[2 * b + 1];
+      if (!std::isfinite(d) || !std::isfinite(m)) st[b] = LME_ENONFINITE;
+      else if (d <= tol * m) st[b] = LME_OK;
+      else st[b] = LME_EMAXSTEPS;
+      all = all && st[b] != LME_EMAXSTEPS;
+    }
+    if (all) {
+      ++k;
+      break;
+    }
+  }
+  if (squarings) *squarings = k;
+  std::vector<int64_t> off2(h->offsets.begin(), h->offsets.end());
+  if ((rc = cc->d_off.upload(off2.data(), off2.size() * 8, "offsets"))) return rc;
+  hipError_t e = lme_internal_launch_prop_column0(P0, doff4, ddims,
+                                                  static_cast<const int64_t *>(cc->d_off.p),
+                                                  h->n_inst, static_cast<double *>(rho_dev), s);
+  if (e != hipSuccess) return hip_fail(e, "launch steady state");
+  if (status_dev) {
+    e = hipMemcpyAsync(status_dev, st.data(), st.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "steady-state status");
+  }
+  return LME_OK;
+}
+
+extern "C" int lme_steadystate(lme_handle h, const lme_options *opt, double T,
+                               int32_t max_squarings, double tol, void *rho_ss_dev,
+                               int32_t *status_dev, int32_t *squarings, void *stream) {
+  try {
+    return steadystate_impl(h, opt, T, max_squarings, tol, rho_ss_dev, status_dev, squarings,
+                            stream);
   } catch (const std::bad_alloc &) {
     return fail(LME_ENOMEM, "out of host memory");
   } catch (...) {

@@ -1,0 +1,242 @@
+// lme_prop.hip -- propagators and the steady state of repeated propagation.
+//
+// The propagator U of an instance (dimension n) is the n^2 x n^2 matrix
+// with vec(rho(t1)) = U vec(rho(t0)) (row-major vec); it is integrated as a
+// batch of the n^2 basis matrices, column c = vec of the solution from
+// |i><j|, c = i n + j, stored column-major.  The steady state of repeated
+// application is the limit of U^(2^k): the columns converge to Tr(X) rho_ss.
+// Squaring is a dense complex FP64 matrix product on the matrix cores
+// (v_mfma_f64_16x16x4f64): one wavefront per 16 x 16 output tile, the real
+// and imaginary parts as four real products per k-step.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace {
+
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+// Identity (the n^2 basis matrices) in every instance's propagator block:
+// block b at offset off4[b] (elements), N = n_b^2, column-major.
+__global__ void prop_identity_kernel(double *U, const int64_t *off4, const int32_t *dims,
+                                     int n_inst) {
+  const int b = blockIdx.y;
+  if (b >= n_inst) return;
+  const int64_t N = (int64_t)dims[b] * dims[b];
+  double *Ub = U + 2 * off4[b];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / N, r = e - c * N;
+    Ub[2 * e] = (r == c) ? 1.0 : 0.0;
+    Ub[2 * e + 1] = 0.0;
+  }
+}
+
+// One 16 x 16 output tile per wavefront: C = A B for the tile's instance.
+// Tiles of instance b: (N/16 rounded up)^2, listed in tiles[] as (b, ti, tj).
+struct GemmTile {
+  int32_t b, ti, tj, pad;
+};
+
+// Lane layout of v_mfma_f64_16x16x4f64 (wave64): A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k; the four accumulator elements q of lane
+// j + 16 g hold D[4 q + g][j] (rows interleaved by lane group, measured).
+__global__ __launch_bounds__(64) void zgemm_kernel(const GemmTile *tiles, int n_tiles,
+                                                   const int64_t *off4, const int32_t *dims,
+                                                   const double *A, const double *B, double *C) {
+  const int t = blockIdx.x;
+  if (t >= n_tiles) return;
+  const GemmTile tl = tiles[t];
+  const int N = dims[tl.b] * dims[tl.b];
+  const int64_t o = 2 * off4[tl.b];
+  const double *Ab = A + o, *Bb = B + o;
+  double *Cb = C + o;
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row = tl.ti * 16 + li;      // A row of this lane
+  const int col = tl.tj * 16 + li;      // B column of this lane
+  double4v rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < N; k0 += 4) {
+    const int k = k0 + lk;
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    if (row < N && k < N) {   // A column-major: A[row][k] at k N + row
+      ar = Ab[2 * ((int64_t)k * N + row)];
+      ai = Ab[2 * ((int64_t)k * N + row) + 1];
+    }
+    if (col < N && k < N) {   // B[k][col] at col N + k
+      br = Bb[2 * ((int64_t)col * N + k)];
+      bi = Bb[2 * ((int64_t)col * N + k) + 1];
+    }
+    rr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, rr, 0, 0, 0);
+    ii = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, ii, 0, 0, 0);
+    ri = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ri, 0, 0, 0);
+    ir = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ir, 0, 0, 0);
+  }
+  const int j = tl.tj * 16 + li;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = tl.ti * 16 + 4 * q + lk;
+    if (i < N && j < N) {
+      Cb[2 * ((int64_t)j * N + i)] = rr[q] - ii[q];
+      Cb[2 * ((int64_t)j * N + i) + 1] = ri[q] + ir[q];
+    }
+  }
+}
+
+// Per instance: tau[b] = Tr of column 0 of U (the image of |0><0|, which a
+// trace-preserving map keeps at 1); also clears the maxima of the check.
+__global__ __launch_bounds__(64) void prop_trace_kernel(const double *U, const int64_t *off4,
+                                                        const int32_t *dims, int n_inst,
+                                                        double *tau, unsigned long long *dm) {
+  const int b = blockIdx.x;
+  if (b >= n_inst) return;
+  const int n = dims[b];
+  const double *c0 = U + 2 * off4[b];
+  double sx = 0.0, sy = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) {
+    sx += c0[2 * ((int64_t)i * n + i)];
+    sy += c0[2 * ((int64_t)i * n + i) + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+  }
+  if (threadIdx.x == 0) {
+    tau[2 * b] = sx;
+    tau[2 * b + 1] = sy;
+    dm[2 * b] = 0ull;
+    dm[2 * b + 1] = 0ull;
+  }
+}
+
+// U_new /= tau[b] in place, then per instance the largest |U_new - U_old|
+// (into dm[2b]) and |U_new| (into dm[2b+1]), as bit patterns of
+// non-negative doubles (ordered like the values; NaN above all).
+// Grid (blocks, n_inst).
+__global__ __launch_bounds__(256) void prop_norm_diff_kernel(double *Un, const double *Uo,
+                                                             const int64_t *off4,
+                                                             const int32_t *dims,
+                                                             const double *tau,
+                                                             unsigned long long *dm) {
+  const int b = blockIdx.y;
+  const int64_t N = (int64_t)dims[b] * dims[b];
+  double *x = Un + 2 * off4[b];
+  const double *y = Uo + 2 * off4[b];
+  const double tr = tau[2 * b], ti = tau[2 * b + 1];
+  const double den = tr * tr + ti * ti;
+  const double qr = tr / den, qi = -ti / den;   // 1 / tau
+  double d = 0.0, m = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double ur = x[2 * e], ui = x[2 * e + 1];
+    const double vr = ur * qr - ui * qi, vi = ur * qi + ui * qr;
+    x[2 * e] = vr;
+    x[2 * e + 1] = vi;
+    const double dx = vr - y[2 * e], dy = vi - y[2 * e + 1];
+    const double v = sqrt(dx * dx + dy * dy), w = sqrt(vr * vr + vi * vi);
+    d = (v > d || v != v) ? v : d;   // NaN propagates
+    m = (w > m || w != w) ? w : m;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double a = __shfl_xor(d, o), c = __shfl_xor(m, o);
+    d = (a > d || a != a) ? a : d;
+    m = (c > m || c != c) ? c : m;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    // |NaN| so that its pattern is the positive quiet NaN, above +inf
+    atomicMax(&dm[2 * b], (unsigned long long)__double_as_longlong(d != d ? __builtin_nan("") : d));
+    atomicMax(&dm[2 * b + 1],
+              (unsigned long long)__double_as_longlong(m != m ? __builtin_nan("") : m));
+  }
+}
+
+// rho_ss of instance b: column 0 of its limit propagator (the image of
+// |0><0|), divided by its trace; packed state layout.
+__global__ __launch_bounds__(256) void prop_column0_kernel(const double *U, const int64_t *off4,
+                                                           const int32_t *dims,
+                                                           const int64_t *off2, double *rho) {
+  const int b = blockIdx.x;
+  const int n = dims[b];
+  const double *c0 = U + 2 * off4[b];      // column 0: the first N entries
+  __shared__ double tr[2];
+  if (threadIdx.x == 0) {
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < n; ++i) {
+      sx += c0[2 * ((int64_t)i * n + i)];
+      sy += c0[2 * ((int64_t)i * n + i) + 1];
+    }
+    tr[0] = sx;
+    tr[1] = sy;
+  }
+  __syncthreads();
+  const double den = tr[0] * tr[0] + tr[1] * tr[1];
+  double *out = rho + 2 * off2[b];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+    const double x = c0[2 * e], y = c0[2 * e + 1];
+    out[2 * e] = (x * tr[0] + y * tr[1]) / den;
+    out[2 * e + 1] = (y * tr[0] - x * tr[1]) / den;
+  }
+}
+
+// status[b] = the first non-zero status of the replicated instances
+// [first[b], first[b+1]) (the basis matrices of instance b).
+__global__ void range_status_kernel(const int32_t *st, const int64_t *first, int32_t *status,
+                                    int n_inst) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_inst) return;
+  int v = 0;
+  for (int64_t q = first[b]; q < first[b + 1] && v == 0; ++q) v = st[q];
+  status[b] = v;
+}
+
+}  // namespace
+
+extern "C" hipError_t lme_internal_launch_range_status(const int32_t *st, const int64_t *first,
+                                                       int32_t *status, int n_inst,
+                                                       hipStream_t s) {
+  hipLaunchKernelGGL(range_status_kernel, dim3((n_inst + 255) / 256), dim3(256), 0, s, st, first,
+                     status, n_inst);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t lme_internal_launch_prop_identity(double *U, const int64_t *off4,
+                                                        const int32_t *dims, int n_inst,
+                                                        hipStream_t s) {
+  hipLaunchKernelGGL(prop_identity_kernel, dim3(64, n_inst), dim3(256), 0, s, U, off4, dims,
+                     n_inst);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t lme_internal_launch_zgemm(const void *tiles, int n_tiles, const int64_t *off4,
+                                                const int32_t *dims, const double *A,
+                                                const double *B, double *C, hipStream_t s) {
+  hipLaunchKernelGGL(zgemm_kernel, dim3(n_tiles), dim3(64), 0, s,
+                     static_cast<const GemmTile *>(tiles), n_tiles, off4, dims, A, B, C);
+  return hipGetLastError();
+}
+
+// tau: device double [2 n_inst]; dm: device uint64 [2 n_inst] (the
+// maxima as double bit patterns: diff at 2b, magnitude at 2b+1).
+extern "C" hipError_t lme_internal_launch_prop_norm_diff(double *Un, const double *Uo,
+                                                         const int64_t *off4, const int32_t *dims,
+                                                         int n_inst, int64_t max_block,
+                                                         double *tau, void *dm, hipStream_t s) {
+  unsigned long long *m = static_cast<unsigned long long *>(dm);
+  hipLaunchKernelGGL(prop_trace_kernel, dim3(n_inst), dim3(64), 0, s, Un, off4, dims, n_inst, tau,
+                     m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((max_block + 1023) / 1024, 1), 1024);
+  hipLaunchKernelGGL(prop_norm_diff_kernel, dim3((unsigned)blocks, n_inst), dim3(256), 0, s, Un,
+                     Uo, off4, dims, tau, m);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t lme_internal_launch_prop_column0(const double *U, const int64_t *off4,
+                                                       const int32_t *dims, const int64_t *off2,
+                                                       int n_inst, double *rho, hipStream_t s) {
+  hipLaunchKernelGGL(prop_column0_kernel, dim3(n_inst), dim3(256), 0, s, U, off4, dims, off2, rho);
+  return hipGetLastError();
+}

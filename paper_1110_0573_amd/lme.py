@@ -30,7 +30,7 @@ LME_LAYOUT_AUTO, LME_LAYOUT_ROW, LME_LAYOUT_COLUMN = 0, 1, 2
 # every symbol include/lme.h declares
 EXPORTS = ["lme_default_options", "lme_create_batch", "lme_create", "lme_destroy",
            "lme_last_error", "lme_layout", "lme_evolve", "lme_evolve_noalloc", "lme_apply",
-           "lme_set_coeff_fn", "lme_correlation",
+           "lme_set_coeff_fn", "lme_correlation", "lme_propagator", "lme_steadystate",
            "lme_cost_grad", "lme_get_tuning", "lme_set_tuning", "lme_autotune",
            "lme_mc_create", "lme_mc_destroy", "lme_mc_evolve"]
 
@@ -87,6 +87,11 @@ def load():
         lib.lme_correlation.argtypes = [H, C.POINTER(Options), C.c_int32, _PD, C.c_int32, _PD,
                                         C.c_int32, C.POINTER(Csr), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]
+        lib.lme_propagator.argtypes = [H, C.POINTER(Options), C.c_double, C.c_double,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.lme_steadystate.argtypes = [H, C.POINTER(Options), C.c_double, C.c_int32,
+                                        C.c_double, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_int32), C.c_void_p]
         lib.lme_destroy.argtypes = [H]
         lib.lme_destroy.restype = None
         lib.lme_last_error.argtypes = []
@@ -393,6 +398,39 @@ class Handle:
                                     _ptr(status), _stream_ptr(stream))
         _check(rc, "lme_correlation")
         return corr, status
+
+    def propagator(self, t0, t1, nsteps, device="cuda", stream=None):
+        """lme_propagator: the RK4 maps U_b (vec(rho(t1)) = U_b vec(rho(t0)),
+        row-major vec) of every instance.  Returns ([U_b as n^2 x n^2 device
+        tensors], status)."""
+        import torch
+        sizes = [int(n) ** 4 for n in self.dims]
+        flat = torch.empty(sum(sizes), dtype=torch.complex128, device=device)
+        status = torch.full((self.n_inst,), -1, dtype=torch.int32, device=device)
+        opt = default_options(method=LME_RK4, nsteps=int(nsteps))
+        rc = load().lme_propagator(self._h, C.byref(opt), float(t0), float(t1), _ptr(flat),
+                                   _ptr(status), _stream_ptr(stream))
+        _check(rc, "lme_propagator")
+        out, o = [], 0
+        for n, sz in zip(self.dims, sizes):
+            N = int(n) ** 2
+            out.append(flat[o:o + sz].view(N, N).t())   # stored column-major
+            o += sz
+        return out, status
+
+    def steadystate(self, T, nsteps, max_squarings=60, tol=1e-12, device="cuda", stream=None):
+        """lme_steadystate: rho_ss of every instance as the limit of U(T)^(2^k).
+        Returns (packed rho_ss device tensor, status, number of products)."""
+        import torch
+        rho = torch.empty(self.state_elems, dtype=torch.complex128, device=device)
+        status = torch.full((self.n_inst,), -1, dtype=torch.int32, device=device)
+        k = C.c_int32(-1)
+        opt = default_options(method=LME_RK4, nsteps=int(nsteps))
+        rc = load().lme_steadystate(self._h, C.byref(opt), float(T), int(max_squarings),
+                                    float(tol), _ptr(rho), _ptr(status), C.byref(k),
+                                    _stream_ptr(stream))
+        _check(rc, "lme_steadystate")
+        return rho, status, k.value
 
     def apply(self, y, t=0.0, adjoint=False, form=LME_FORM_OPERATOR, u=None, stream=None):
         """out = L(t) y (or L^+ y) for every instance of the packed batch."""

@@ -321,3 +321,34 @@ def test_correlation_validation_before_device_use():
     import torch
     if not torch.cuda.is_available():
         assert rc([0.0, 1.0]) == lme.LME_EHIP
+
+
+def test_propagator_and_steadystate_validation_before_device_use():
+    lib = lme.load()
+    h, w = _handle()
+    o = lme.default_options(nsteps=10)
+    P = C.c_void_p(16)
+    prop = lambda opt=o, t0=0.0, t1=1.0, U=P: lib.lme_propagator(h._h, C.byref(opt), t0, t1, U,
+                                                                 None, None)
+    ss = lambda opt=o, T=1.0, k=10, tol=0.0, r=P: lib.lme_steadystate(
+        h._h, C.byref(opt), T, k, tol, r, None, None, None)
+    assert lib.lme_propagator(None, C.byref(o), 0.0, 1.0, P, None, None) == lme.LME_EINVAL
+    assert prop(t1=0.0) == lme.LME_EINVAL                      # t1 must exceed t0
+    assert prop(t1=float("nan")) == lme.LME_EINVAL
+    assert prop(U=None) == lme.LME_EINVAL
+    assert prop(opt=lme.default_options(nsteps=0)) == lme.LME_EINVAL
+    assert prop(opt=lme.default_options(method=lme.LME_DOPRI5)) == lme.LME_ENOTSUP
+    assert ss(T=-1.0) == lme.LME_EINVAL
+    assert ss(k=-1) == lme.LME_EINVAL and ss(k=201) == lme.LME_EINVAL
+    assert ss(tol=float("inf")) == lme.LME_EINVAL and ss(tol=-1.0) == lme.LME_EINVAL
+    assert ss(r=None) == lme.LME_EINVAL
+    wd = S.jc_drive(n_inst=2, N=3, n_seg=2, t_end=1.0, steps_per_seg=2)
+    hd = lme.Handle(wd.systems)                                # control terms
+    assert lib.lme_propagator(hd._h, C.byref(o), 0.0, 1.0, P, None, None) == lme.LME_ENOTSUP
+    big = lme.Handle([S.random_system(130, n_c=1, n_e=1, seed=1, density=0.02)])
+    assert lib.lme_propagator(big._h, C.byref(o), 0.0, 1.0, P, None, None) == lme.LME_ENOTSUP
+    assert lib.lme_steadystate(big._h, C.byref(o), 1.0, 5, 0.0, P, None, None,
+                               None) == lme.LME_ENOTSUP
+    import torch
+    if not torch.cuda.is_available():
+        assert prop() == lme.LME_EHIP and ss() == lme.LME_EHIP
