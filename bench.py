@@ -271,6 +271,72 @@ def mc_trilinear_bench(lme, systems, torch, reps=3):
             "kernel": "mc_kernel"}
 
 
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def steady_state_bench(lme, systems, torch, reps=3):
+    """Steady states of 16 thermal JC systems (dimension 32): the propagator
+    U(10) of each (its 1024 basis matrices as one RK4 batch), then squarings
+    on the matrix cores.  Timed with HIP events on the launch stream: the
+    propagator, the whole steady-state call (it synchronises once per
+    product for the convergence test), and one launch of the complex product
+    alone on the same operands (the matrix-core roofline)."""
+    import ctypes
+    w = systems.jc_steady_sweep()
+    T = float(w.tlist[-1])
+    h = lme.Handle(w.systems)
+    stream = torch.cuda.current_stream()
+
+    def ev_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms, out = [], None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms)), out
+
+    p_ms, (Us, pst) = ev_ms(lambda: h.propagator(0.0, T, w.nsteps, stream=stream))
+    s_ms, (rho, st, k) = ev_ms(lambda: h.steadystate(T, w.nsteps, stream=stream))
+    # one product on the propagators just formed
+    dims = [int(n) for n in h.dims]
+    Ns = [n * n for n in dims]
+    off4 = np.concatenate([[0], np.cumsum([N * N for N in Ns])]).astype(np.int64)
+    tiles = np.array([(b, i, j, 0) for b, N in enumerate(Ns)
+                      for i in range((N + 63) // 64) for j in range((N + 63) // 64)],
+                     np.int32).reshape(-1)
+    A = torch.cat([U.t().contiguous().reshape(-1) for U in Us])
+    Cm = torch.empty_like(A)
+    t_tiles, t_off = torch.from_numpy(tiles).cuda(), torch.from_numpy(off4).cuda()
+    t_dims = torch.tensor(dims, dtype=torch.int32, device="cuda")
+    f = lme.load().lme_internal_launch_zgemm
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6
+    f.restype = ctypes.c_int
+
+    def gemm():
+        rc = f(t_tiles.data_ptr(), len(tiles) // 4, t_off.data_ptr(), t_dims.data_ptr(),
+               A.data_ptr(), A.data_ptr(), Cm.data_ptr(), stream.cuda_stream)
+        assert rc == 0
+    g_ms, _ = ev_ms(gemm)
+    flops = float(sum(8.0 * N ** 3 for N in Ns))
+    n_basis = sum(Ns)
+    return {"workload": "jc_steady_sweep: 16 thermal JC systems, N = 16 (dim 32), U(10) by "
+                        "RK4 in 200 steps over the 1024 basis matrices, then squarings",
+            "propagator_ms": p_ms,
+            "propagator_instance_steps_per_s": n_basis * w.nsteps / (p_ms * 1e-3),
+            "steadystate_ms": s_ms, "squarings": int(k),
+            "status_ok": bool((st.cpu().numpy() == 0).all()),
+            "zgemm": {"kernel": "zgemm_kernel", "ms": g_ms, "algorithmic_flops": flops,
+                      "achieved_tflops": flops / (g_ms * 1e-3) / 1e12,
+                      "peak": FP64_MFMA_PEAK_TFLOPS, "bound": "mfma",
+                      "frac": flops / (g_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                      "note": "8 N^3 real flops per complex N x N product, N = 1024"}}
+
+
 def streamed_apply_bench(lme, systems, torch, reps=20):
     """HBM roofline of the streamed Liouvillian application (stage input read
     from HBM, result written back): algorithmic bytes 32 n^2 per instance,
@@ -423,6 +489,24 @@ def other_configs(lme, systems, torch):
     res["tfim_8spin_64_dopri5_t20"] = {"ms": ms, "accepted_mean": float(acc.mean()),
                                        "instance_steps_per_s": float(acc.sum()) / (ms * 1e-3),
                                        "path": "streamed"}
+
+    w = systems.landau_zener_sweep()
+    h = lme.Handle(w.systems)
+    r0 = h.pack([s.rho0 for s in w.systems])
+    ms, _ = timed(lambda: h.evolve(r0, w.tlist, nsteps=w.nsteps, hermitian=True))
+    res["landau_zener_4096_rk4"] = {"ms": ms, "instance_steps_per_s":
+                                    len(w.systems) * w.nsteps / (ms * 1e-3),
+                                    "amplitudes": "closed form, evaluated per stage"}
+
+    w = systems.jc_correlation_sweep()
+    h = lme.Handle(w.systems)
+    r0 = h.pack([s.rho0 for s in w.systems])
+    ms, _ = timed(lambda: h.correlation(r0, w.tlist, w.nsteps, w.extra["taulist"],
+                                        w.extra["tau_nsteps"], w.extra["B"], hermitian=True))
+    n_evol = len(w.systems) * (1 + len(w.tlist))
+    res["jc_correlation_64x26x101"] = {"ms": ms, "instance_steps_per_s":
+                                       n_evol * w.nsteps / (ms * 1e-3)}
+    res["jc_steady_16_dim32"] = steady_state_bench(lme, systems, torch)
     return res
 
 

@@ -3002,10 +3002,10 @@ static int steadystate_impl(lme_handle h, const lme_options *opt, double T, int3
   std::vector<int64_t> off4 = prop_offsets(h, &total);
   if ((rc = dev_ensure(cc->d_p0, (size_t)total * 16, "propagators"))) return rc;
   if ((rc = propagator_run(h, opt, 0.0, T, cc->d_p0.p, nullptr, s, stream))) return rc;
-  // tiles of the products: 16 x 16 per wavefront, every instance
+  // tiles of the products: 64 x 64 per workgroup, every instance
   std::vector<int32_t> tiles;
   for (int b = 0; b < h->n_inst; ++b) {
-    const int N = h->dims[b] * h->dims[b], nt = (N + 15) / 16;
+    const int N = h->dims[b] * h->dims[b], nt = (N + 63) / 64;
     for (int i = 0; i < nt; ++i)
       for (int j = 0; j < nt; ++j) {
         tiles.push_back(b);

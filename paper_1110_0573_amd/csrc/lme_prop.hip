@@ -6,8 +6,9 @@
 // |i><j|, c = i n + j, stored column-major.  The steady state of repeated
 // application is the limit of U^(2^k): the columns converge to Tr(X) rho_ss.
 // Squaring is a dense complex FP64 matrix product on the matrix cores
-// (v_mfma_f64_16x16x4f64): one wavefront per 16 x 16 output tile, the real
-// and imaginary parts as four real products per k-step.
+// (v_mfma_f64_16x16x4f64): a 64 x 64 output tile per workgroup, panels
+// staged through LDS, the real and imaginary parts as four real products per
+// k-step.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -34,55 +35,90 @@ __global__ void prop_identity_kernel(double *U, const int64_t *off4, const int32
   }
 }
 
-// One 16 x 16 output tile per wavefront: C = A B for the tile's instance.
-// Tiles of instance b: (N/16 rounded up)^2, listed in tiles[] as (b, ti, tj).
+// C = A B for one instance, one 64 x 64 output tile per workgroup of four
+// wavefronts (each a 32 x 32 quarter: 2 x 2 matrix-core tiles of 16 x 16).
+// Tiles of instance b: (N/64 rounded up)^2, listed in tiles[] as (b, ti, tj).
+// The k dimension advances 16 at a time through LDS: A's 64 x 16 panel and
+// B's 16 x 64 panel (both stored k-major, B's rows padded by one element so
+// that its transposing store spreads over the banks).
 struct GemmTile {
   int32_t b, ti, tj, pad;
 };
 
+constexpr int kGemmTile = 64, kGemmK = 16;
+
 // Lane layout of v_mfma_f64_16x16x4f64 (wave64): A[i][k] in lane i + 16 k,
 // B[k][j] in lane j + 16 k; the four accumulator elements q of lane
 // j + 16 g hold D[4 q + g][j] (rows interleaved by lane group, measured).
-__global__ __launch_bounds__(64) void zgemm_kernel(const GemmTile *tiles, int n_tiles,
-                                                   const int64_t *off4, const int32_t *dims,
-                                                   const double *A, const double *B, double *C) {
+__global__ __launch_bounds__(256) void zgemm_kernel(const GemmTile *tiles, int n_tiles,
+                                                    const int64_t *off4, const int32_t *dims,
+                                                    const double *A, const double *B, double *C) {
+  __shared__ double2 As[kGemmK][kGemmTile];
+  __shared__ double2 Bs[kGemmK][kGemmTile + 1];
   const int t = blockIdx.x;
   if (t >= n_tiles) return;
   const GemmTile tl = tiles[t];
   const int N = dims[tl.b] * dims[tl.b];
-  const int64_t o = 2 * off4[tl.b];
-  const double *Ab = A + o, *Bb = B + o;
-  double *Cb = C + o;
-  const int lane = threadIdx.x;
+  const int64_t o = off4[tl.b];
+  const double2 *Ab = reinterpret_cast<const double2 *>(A) + o;
+  const double2 *Bb = reinterpret_cast<const double2 *>(B) + o;
+  double2 *Cb = reinterpret_cast<double2 *>(C) + o;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int row = tl.ti * 16 + li;      // A row of this lane
-  const int col = tl.tj * 16 + li;      // B column of this lane
-  double4v rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < N; k0 += 4) {
-    const int k = k0 + lk;
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-    if (row < N && k < N) {   // A column-major: A[row][k] at k N + row
-      ar = Ab[2 * ((int64_t)k * N + row)];
-      ai = Ab[2 * ((int64_t)k * N + row) + 1];
-    }
-    if (col < N && k < N) {   // B[k][col] at col N + k
-      br = Bb[2 * ((int64_t)col * N + k)];
-      bi = Bb[2 * ((int64_t)col * N + k) + 1];
-    }
-    rr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, rr, 0, 0, 0);
-    ii = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, ii, 0, 0, 0);
-    ri = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ri, 0, 0, 0);
-    ir = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ir, 0, 0, 0);
-  }
-  const int j = tl.tj * 16 + li;
+  const int r0 = tl.ti * kGemmTile, c0 = tl.tj * kGemmTile;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double4v re[2][2], im[2][2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = tl.ti * 16 + 4 * q + lk;
-    if (i < N && j < N) {
-      Cb[2 * ((int64_t)j * N + i)] = rr[q] - ii[q];
-      Cb[2 * ((int64_t)j * N + i) + 1] = ri[q] + ir[q];
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      re[a][b] = double4v{0, 0, 0, 0};
+      im[a][b] = double4v{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < N; k0 += kGemmK) {
+    __syncthreads();   // the previous panel is consumed
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      // A panel: column k0 + ka, rows r0 .. r0 + 63 (contiguous in A)
+      const int ka = idx >> 6, ra = idx & 63;
+      const int row = r0 + ra, kk = k0 + ka;
+      As[ka][ra] = (row < N && kk < N) ? Ab[(int64_t)kk * N + row] : double2{0.0, 0.0};
+      // B panel: column c0 + cb, rows k0 .. k0 + 15 (contiguous in B)
+      const int cb = idx >> 4, kb = idx & 15;
+      const int col = c0 + cb, kr = k0 + kb;
+      Bs[kb][cb] = (col < N && kr < N) ? Bb[(int64_t)col * N + kr] : double2{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kGemmK; ks += 4) {
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[ks + lk][wr + 16 * a + li];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[ks + lk][wc + 16 * b + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, re[a][b], 0, 0, 0);
+          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[b].y, re[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, im[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, im[a][b], 0, 0, 0);
+        }
     }
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = c0 + wc + 16 * b + li;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = r0 + wr + 16 * a + 4 * q + lk;
+        if (i < N && j < N) Cb[(int64_t)j * N + i] = double2{re[a][b][q], im[a][b][q]};
+      }
+    }
 }
 
 // Per instance: tau[b] = Tr of column 0 of U (the image of |0><0|, which a
@@ -212,7 +248,7 @@ extern "C" hipError_t lme_internal_launch_prop_identity(double *U, const int64_t
 extern "C" hipError_t lme_internal_launch_zgemm(const void *tiles, int n_tiles, const int64_t *off4,
                                                 const int32_t *dims, const double *A,
                                                 const double *B, double *C, hipStream_t s) {
-  hipLaunchKernelGGL(zgemm_kernel, dim3(n_tiles), dim3(64), 0, s,
+  hipLaunchKernelGGL(zgemm_kernel, dim3(n_tiles), dim3(256), 0, s,
                      static_cast<const GemmTile *>(tiles), n_tiles, off4, dims, A, B, C);
   return hipGetLastError();
 }

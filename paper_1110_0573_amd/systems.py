@@ -369,6 +369,24 @@ def jc_correlation_sweep(n_inst=64, seed=9, n_t=26, n_tau=101):
                                             tau_nsteps=1000))
 
 
+def jc_steady_sweep(n_inst=16, seed=10, N=16, T=10.0, nsteps=200):
+    """Steady states of a sweep of thermal Jaynes-Cummings systems (the
+    cavity of Sec. 3.2 at a thermal occupation, coupled to a two-level atom):
+    N photon states (dimension 2N, propagators of (2N)^2 = 1024 rows for
+    N = 16), wa in [0.9, 1.1], g in [0.02, 0.08] 2pi, kappa and gamma in
+    [0.05, 0.2], n_th in [0.05, 0.5].  U(T) from RK4 (nsteps steps over
+    [0, T]), then repeated squaring."""
+    rng = np.random.default_rng(seed)
+    wa = rng.uniform(0.9, 1.1, size=n_inst)
+    gs = rng.uniform(0.02, 0.08, size=n_inst) * TWO_PI
+    ks = rng.uniform(0.05, 0.2, size=n_inst)
+    gm = rng.uniform(0.05, 0.2, size=n_inst)
+    nth = rng.uniform(0.05, 0.5, size=n_inst)
+    systems = [jc_system(N, wc=1.0, wa=wa[b], g=gs[b], kappa=ks[b], gamma=gm[b], n_th=nth[b])
+               for b in range(n_inst)]
+    return Workload(f"jc_steady_{n_inst}", systems, np.array([0.0, T]), "rk4", nsteps=nsteps)
+
+
 # --------------------------------------------------------------------------
 # Monte-Carlo workloads (Sec. 3.2 and Sec. 4.3)
 # --------------------------------------------------------------------------

@@ -26,14 +26,14 @@ from paper_1110_0573_amd import lme  # noqa: E402
 
 def test_zgemm_matrix_core_layout():
     """The batched complex product on its own (the lane layout of the FP64
-    matrix-core instruction): ragged blocks of N = 9, 25, 64, 100 (partial
-    16 x 16 tiles, several k-steps) against numpy."""
+    matrix-core instruction, the LDS panels): ragged blocks of N = 9, 25,
+    64, 100, 169 (partial 64 x 64 tiles, several k-panels) against numpy."""
     lib = lme.load()
     f = lib.lme_internal_launch_zgemm
     f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     f.restype = ctypes.c_int
-    dims = [3, 5, 8, 10]
+    dims = [3, 5, 8, 10, 13]
     rng = np.random.default_rng(17)
     As, Bs, off4, tiles = [], [], [0], []
     for b, n in enumerate(dims):
@@ -41,7 +41,7 @@ def test_zgemm_matrix_core_layout():
         As.append(rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N)))
         Bs.append(rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N)))
         off4.append(off4[-1] + N * N)
-        nt = (N + 15) // 16
+        nt = (N + 63) // 64
         tiles += [(b, i, j, 0) for i in range(nt) for j in range(nt)]
     # column-major blocks: element r + c N holds M[r, c]
     flat = lambda Ms: torch.tensor(np.concatenate([M.T.reshape(-1) for M in Ms]),
@@ -133,3 +133,14 @@ def test_steadystate_not_converged_status():
     _, (r,), st, k = steady([s], 0.5, 20, max_sq=1, tol=0.0)
     assert k == 1 and st[0] == lme.LME_EMAXSTEPS
     assert abs(np.trace(r) - 1) < 1e-13     # the last iterate, normalised
+
+
+def test_steadystate_sweep_as_benchmarked_sampled():
+    """The benchmark's workload (16 thermal JC systems, dimension 32,
+    propagators of 1024 rows): every instance converges, a seeded sample of
+    2 matches the oracle's direct solve."""
+    w = S.jc_steady_sweep()
+    _, rhos, st, k = steady(w.systems, w.tlist[-1], w.nsteps)
+    assert (st == 0).all() and k < 60
+    for b in np.sort(np.random.default_rng(4).choice(len(w.systems), 2, replace=False)):
+        assert np.max(np.abs(rhos[b] - oracle.steadystate(w.systems[b]))) < 1e-10
