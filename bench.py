@@ -552,6 +552,8 @@ def pmc_pass(lme, systems, torch):
     hm = lme.McHandle(sm.H0, sm.C, sm.E)
     hm.evolve(torch.from_numpy(sm.meta["psi0"]).cuda(), wm.tlist, wm.nsteps,
               torch.from_numpy(wm.extra["draws"]).cuda(), want_traj=False)
+    ws = systems.jc_steady_sweep()
+    lme.Handle(ws.systems).steadystate(float(ws.tlist[-1]), ws.nsteps)
     src = torch.ones(32 * 2**20, dtype=torch.float64, device="cuda:0")   # 256 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)

@@ -965,12 +965,24 @@ static int upload_tables(lme_ctx *h, std::vector<int32_t> &tab, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // evolve
 // ---------------------------------------------------------------------------
-static int pick_rk4_config(const lme_ctx *h, int block, int *T, int *EPT) {
+static int pick_rk4_config(const lme_ctx *h, int block, int *T, int *EPT, int *cap = nullptr) {
   int max_n2 = 0;
-  for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
+  int64_t tot = 0;
+  for (auto &d : h->inst) {
+    max_n2 = std::max(max_n2, d.n * d.n);
+    tot += (int64_t)d.n * d.n;
+  }
   int Ts[64], Es[64];
   const int nc = lme_internal_rk4_configs(Ts, Es, 64);
-  const int want_T = block > 0 ? block : 512;
+  int want_T = block > 0 ? block : 512;
+  // small instances whose whole batch would fill fewer than two 512-thread
+  // workgroups per CU: one wavefront per pack, so that every CU gets packs
+  // (and the stage barriers are a single wavefront's)
+  int cus = 0;
+  if (block <= 0 && max_n2 <= 64 * 8 &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+      cus > 0 && tot < (int64_t)2 * 512 * cus)
+    want_T = 64;
   int best = -1;
   for (int i = 0; i < nc; ++i)
     if (Ts[i] == want_T && Ts[i] * Es[i] >= max_n2 && (best < 0 || Es[i] < Es[best])) best = i;
@@ -982,6 +994,14 @@ static int pick_rk4_config(const lme_ctx *h, int block, int *T, int *EPT) {
                 "workgroup capacity for block %d", max_n2, want_T);
   *T = Ts[best];
   *EPT = Es[best];
+  if (cap) {
+    // one-wavefront packs: at most a quarter of the batch per CU slot (so
+    // that a CU holds several latency-bound wavefronts), never below one
+    // instance
+    *cap = Ts[best] * Es[best];
+    if (Ts[best] == 64 && cus > 0)
+      *cap = (int)std::max<int64_t>(max_n2, std::min<int64_t>(*cap, tot / (4 * cus)));
+  }
   return LME_OK;
 }
 
@@ -1482,7 +1502,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   opt = &tuned;
   // column layout: T in {512, 768} (also Hermitian); row layout:
   // T in {256, 512, 1024}
-  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0;
+  int T = 0, EPT = 0, column = 0, col_cfg = -1, wo = 0, nc = 0, nb = 0, pack_cap = 0;
   const int re = real_structure(h);
   if (opt->layout != LME_LAYOUT_ROW && column_eligible(h, &wo, &nc, &nb)) {
     for (int c = 1; c >= 0; --c) {   // prefer the larger workgroup
@@ -1503,7 +1523,7 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
       return fail(LME_ENOTSUP, "the column layout does not cover these operators / block size");
     if (opt->block == 768) return fail(LME_EINVAL, "block 768 exists only in the column layout");
     // the row layout has no Hermitian variant: it computes every element
-    rc = pick_rk4_config(h, opt->block, &T, &EPT);
+    rc = pick_rk4_config(h, opt->block, &T, &EPT, &pack_cap);
     if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !noalloc && h->fn.empty())
       streamed = true;  // an instance is too large for a resident workgroup
     else if (rc)
@@ -1522,7 +1542,8 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   hipError_t e;
   Plan *plan = nullptr;
   if (!streamed) {
-    rc = plan_packs(h, T, EPT, 0, T * EPT, column, 0, &plan, 0, !noalloc);
+    rc = plan_packs(h, T, EPT, 0, pack_cap > 0 ? pack_cap : T * EPT, column, 0, &plan, 0,
+                    !noalloc);
     if (rc == LME_ENOTSUP && opt->path == LME_PATH_AUTO && !column && !noalloc && h->fn.empty())
       streamed = true;
     else if (rc)

@@ -2881,7 +2881,8 @@ static hipError_t launch_rk4_t(const Rk4Args &a, int n_packs, int lds, hipStream
 
 // Resident RK4 configurations: threads per workgroup x elements per thread.
 extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap) {
-  static const int cfg[][2] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}, {256, 32},
+  static const int cfg[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8},
+                               {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}, {256, 32},
                                {512, 1}, {512, 2}, {512, 4}, {512, 8}, {512, 13}, {512, 16},
                                {1024, 1}, {1024, 2}, {1024, 4}, {1024, 6}};
   const int nc = (int)(sizeof(cfg) / sizeof(cfg[0]));
@@ -2903,6 +2904,7 @@ extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args
   using namespace lme;
 #define LME_RK4_CASE(TT, EE) \
   if (T == TT && EPT == EE) return launch_rk4_t<TT, EE>(*a, n_packs, lds, s);
+  LME_RK4_CASE(64, 1) LME_RK4_CASE(64, 2) LME_RK4_CASE(64, 4) LME_RK4_CASE(64, 8)
   LME_RK4_CASE(256, 1) LME_RK4_CASE(256, 2) LME_RK4_CASE(256, 4) LME_RK4_CASE(256, 8)
   LME_RK4_CASE(256, 16) LME_RK4_CASE(256, 32)
   LME_RK4_CASE(512, 1) LME_RK4_CASE(512, 2) LME_RK4_CASE(512, 4) LME_RK4_CASE(512, 8)
