@@ -332,11 +332,13 @@ static std::vector<cd> diag_of(const Sparse &S) {
   return d;
 }
 
+// (memcpy with a null source is undefined even for zero bytes: an empty
+// table, e.g. the off-diagonal part of a diagonal operator, copies nothing)
 static void put_cd(std::vector<uint8_t> &blob, int off, const std::vector<cd> &v) {
-  std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(cd));
+  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(cd));
 }
 static void put_i32(std::vector<uint8_t> &blob, int off, const std::vector<int32_t> &v) {
-  std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(int32_t));
+  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(int32_t));
 }
 
 // Blob of (A, {B_j}, {C_k}) with A, B_j already folded.
@@ -885,7 +887,7 @@ static int noalloc_stage(lme_ctx *h, const void *tab, size_t tab_bytes, const Pl
                 "(the adaptive stepper's stage derivatives take 112 bytes per state element)",
                 na->total, cap);
   h->na_host.assign(host_end, 0);
-  std::memcpy(h->na_host.data(), tab, tab_bytes);
+  if (tab_bytes) std::memcpy(h->na_host.data(), tab, tab_bytes);
   std::memcpy(h->na_host.data() + na->packs_off, plan->packs.data(),
               plan->packs.size() * sizeof(PackDesc));
   std::memcpy(h->na_host.data() + na->order_off, plan->order.data(),
@@ -1360,9 +1362,11 @@ static int evolve_dp5(lme_handle h, const lme_options *opt, int32_t n_t, const d
   // tables: [stops | out_idx | seg], content-cached
   const size_t ns = stops.size();
   std::vector<uint8_t> buf(ns * 8 + 2 * ns * 4 + 16, 0);
-  std::memcpy(buf.data(), stops.data(), ns * 8);
-  std::memcpy(buf.data() + ns * 8, out_idx.data(), ns * 4);
-  std::memcpy(buf.data() + ns * 12, seg.data(), ns * 4);
+  if (ns) {
+    std::memcpy(buf.data(), stops.data(), ns * 8);
+    std::memcpy(buf.data() + ns * 8, out_idx.data(), ns * 4);
+    std::memcpy(buf.data() + ns * 12, seg.data(), ns * 4);
+  }
   if (!noalloc) {
     std::vector<double> key(stops);
     key.push_back((double)n_t);
@@ -2520,11 +2524,12 @@ static int mc_create_impl(const lme_csr *H, int32_t n_c, const lme_csr *C, int32
   h->L = lme::mc_layout(n, h->wo, h->nc, h->wc, h->ne, h->we);
   if (h->L.bytes > (int64_t)1 << 31) return fail(LME_ENOTSUP, "operator tables exceed 2 GiB");
   h->tabs.assign((size_t)h->L.bytes, 0);
+  // (an empty table, e.g. A with no off-diagonal entries, copies nothing)
   auto put_c = [&](int64_t off, const std::vector<cd> &v) {
-    std::memcpy(h->tabs.data() + off, v.data(), v.size() * sizeof(cd));
+    if (!v.empty()) std::memcpy(h->tabs.data() + off, v.data(), v.size() * sizeof(cd));
   };
   auto put_i = [&](int64_t off, const std::vector<int32_t> &v) {
-    std::memcpy(h->tabs.data() + off, v.data(), v.size() * sizeof(int32_t));
+    if (!v.empty()) std::memcpy(h->tabs.data() + off, v.data(), v.size() * sizeof(int32_t));
   };
   put_c(h->L.offD, diag_of(A));
   Ell o = to_ell(A, h->wo, true);
