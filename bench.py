@@ -27,19 +27,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "instance-RK-steps/sec + HBM GB/s, batched vs plain, at 1e-10 trace distance"
 # HBM bytes per launch of the timed kernels from the FETCH_SIZE / WRITE_SIZE passes
-# (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0), valid only for the kernel
-# source with this SHA-256; any other source reports null.
-TRAFFIC = {"sha256": "987fbade1ff7cd2ae172481d8a87eb7961fc72077c29043a6429fa7497858b26",
-           "rk4_herm_kernel": 192.59e6 + 178.17e6, "rk4_colown_kernel": 217.17e6 + 233.98e6,
-           "apply_pipe_kernel": 184.46e6 + 158.35e6, "apply_rows_kernel": 154.71e6 + 104.86e6}
+# (rocprofv3 --pmc, scaled by a 256 MiB copy: x2.0 and x1.0; profiles/README.md), valid
+# only while the kernel's source file has the SHA-256 recorded with them; any other
+# source reports null.
+TRAFFIC_SOURCES = {
+    "lme_kernels.hip": "9c56e4f34b179369280fac9d3d279d6b5f6d94f9f534d0cfab4b9a6b045bfb80",
+    "lme_mc.hip": "430556a8477c37b2518b1ef033bf9e5d02253ea52ef0d06223e0015092f8d385",
+    "lme_prop.hip": "17915d2fe5c6b52196bb124b74649cbe8953799ed1a992a61f1446ee4bb16c53",
+}
+TRAFFIC = {
+    "rk4_herm_kernel": ("lme_kernels.hip", 192.3e6 + 178.2e6),
+    "rk4_colown_kernel": ("lme_kernels.hip", 217.2e6 + 234.0e6),
+    "apply_pipe_kernel": ("lme_kernels.hip", 184.4e6 + 158.3e6),
+    "apply_rows_kernel": ("lme_kernels.hip", 154.4e6 + 104.9e6),
+    "mc_kernel": ("lme_mc.hip", 2328.3e6 + 3178.9e6),
+    "zgemm_kernel": ("lme_prop.hip", 2383.5e6 + 268.4e6),
+}
 
 
 def kernel_traffic(name):
-    """Counter-measured bytes per launch of `name`, or None if the kernels changed."""
+    """Counter-measured bytes per launch of `name`, or None if its source changed."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1110_0573_amd", "csrc", "lme_kernels.hip"), "rb") as f:
+    if name not in TRAFFIC:
+        return None
+    src, nbytes = TRAFFIC[name]
+    with open(os.path.join(ROOT, "paper_1110_0573_amd", "csrc", src), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
-    return TRAFFIC.get(name) if digest == TRAFFIC["sha256"] else None
+    return nbytes if digest == TRAFFIC_SOURCES[src] else None
+
+
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMD x 16 lanes x 2 flop/FMA x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
@@ -268,7 +284,7 @@ def mc_trilinear_bench(lme, systems, torch, reps=3):
             "jumps_mean": float(jumps.mean()), "status_ok": bool((st == 0).all()),
             "algorithmic_flops": flops, "achieved_tflops": flops / (kms * 1e-3) / 1e12,
             "frac_fp64_peak": flops / (kms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
-            "kernel": "mc_kernel"}
+            "kernel": "mc_kernel", "traffic": kernel_traffic("mc_kernel")}
 
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
@@ -334,6 +350,7 @@ def steady_state_bench(lme, systems, torch, reps=3):
                       "achieved_tflops": flops / (g_ms * 1e-3) / 1e12,
                       "peak": FP64_MFMA_PEAK_TFLOPS, "bound": "mfma",
                       "frac": flops / (g_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                      "traffic": kernel_traffic("zgemm_kernel"),
                       "note": "8 N^3 real flops per complex N x N product, N = 1024"}}
 
 

@@ -40,7 +40,8 @@ __global__ void prop_identity_kernel(double *U, const int64_t *off4, const int32
 // Tiles of instance b: (N/64 rounded up)^2, listed in tiles[] as (b, ti, tj).
 // The k dimension advances 16 at a time through LDS: A's 64 x 16 panel and
 // B's 16 x 64 panel (both stored k-major, B's rows padded by one element so
-// that its transposing store spreads over the banks).
+// that its transposing store spreads over the banks; padding A's rows as
+// well measured no faster).
 struct GemmTile {
   int32_t b, ti, tj, pad;
 };
@@ -180,7 +181,18 @@ __global__ __launch_bounds__(256) void prop_norm_diff_kernel(double *Un, const d
     d = (a > d || a != a) ? a : d;
     m = (c > m || c != c) ? c : m;
   }
+  // the four wavefronts' maxima, then one atomic per workgroup and quantity
+  __shared__ double wd[4], wm[4];
   if ((threadIdx.x & 63) == 0) {
+    wd[threadIdx.x >> 6] = d;
+    wm[threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      d = (wd[w] > d || wd[w] != wd[w]) ? wd[w] : d;
+      m = (wm[w] > m || wm[w] != wm[w]) ? wm[w] : m;
+    }
     // |NaN| so that its pattern is the positive quiet NaN, above +inf
     atomicMax(&dm[2 * b], (unsigned long long)__double_as_longlong(d != d ? __builtin_nan("") : d));
     atomicMax(&dm[2 * b + 1],
@@ -264,7 +276,9 @@ extern "C" hipError_t lme_internal_launch_prop_norm_diff(double *Un, const doubl
                      m);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((max_block + 1023) / 1024, 1), 1024);
+  // about 16 elements per thread: few enough workgroups that their atomics
+  // stay cheap, enough to fill the chip
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((max_block + 4095) / 4096, 1), 1024);
   hipLaunchKernelGGL(prop_norm_diff_kernel, dim3((unsigned)blocks, n_inst), dim3(256), 0, s, Un,
                      Uo, off4, dims, tau, m);
   return hipGetLastError();
