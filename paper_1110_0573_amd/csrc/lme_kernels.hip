@@ -1693,7 +1693,13 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
 #pragma unroll
       for (int s = 0; s < EPT; ++s) rho[s] = caxpy(h / 6.0, acc[s], rho[s]);
     }
-    // step back through the interval
+    // step back through the interval; the stage input of the next (earlier)
+    // stage is loaded into registers while this stage computes
+    double2 sbn[EPT];
+#pragma unroll
+    for (int s = 0; s < EPT; ++s)
+      sbn[s] = valid(s) ? SB[((int64_t)(s1 - 1 - s0) * 4 + 3) * SE + goff(bij[s])]
+                        : make_double2(0.0, 0.0);
     for (int st = s1 - 1; st >= s0; --st) {
       const int seg = a.seg_of_step[st];
       if (seg != cur_seg) {
@@ -1717,8 +1723,15 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
         if (stage == 3) set_u(st);
 #pragma unroll
         for (int s = 0; s < EPT; ++s)
-          if (valid(s))
-            L.Y[tid + s * T] = SB[((int64_t)(st - s0) * 4 + stage) * SE + goff(bij[s])];
+          if (valid(s)) L.Y[tid + s * T] = sbn[s];
+        {  // prefetch: stage - 1 of this step, or stage 3 of the step before
+          const int pst = stage > 0 ? st : st - 1, pstage = stage > 0 ? stage - 1 : 3;
+          if (pst >= s0) {
+#pragma unroll
+            for (int s = 0; s < EPT; ++s)
+              if (valid(s)) sbn[s] = SB[((int64_t)(pst - s0) * 4 + pstage) * SE + goff(bij[s])];
+          }
+        }
         __syncthreads();
         if (seg >= 0) {
 #pragma unroll
