@@ -443,8 +443,10 @@ int lme_mc_evolve(lme_mc_handle h, int32_t n_t, const double *tlist, int32_t nst
  * vec(rho(t1)) = U_b vec(rho(t0)), vec row-major (element i n + j of vec is
  * rho[i][j]) and U the fixed-step RK4 map of Eq. (master_equation) in
  * opt->nsteps steps.  Column c = i n + j of U_b is the solution from the
- * basis matrix |i><j|; the n^2 basis matrices of all instances are evolved
- * as one batch on the general (non-Hermitian) kernels.
+ * basis matrix |i><j|.  The map is linear, so the n^2 Hermitian matrices
+ * |a><a|, |a><b| + |b><a| and i(|b><a| - |a><b|) (a < b) are evolved
+ * instead, as one batch of all instances on the Hermitian kernels, and
+ * recombined: U|a><b| = (U X - i U Y)/2, U|b><a| = (U X + i U Y)/2.
  *   U_dev: device complex128, instance blocks of n_b^4 elements one after
  *          another (block b at sum_{b'<b} n_{b'}^4), each column-major:
  *          U_b[r][c] at element c n_b^2 + r of the block;

@@ -2892,9 +2892,12 @@ extern "C" int lme_correlation(lme_handle h, const lme_options *opt, int32_t n_t
 // ---------------------------------------------------------------------------
 // Propagators and the steady state of repeated propagation
 // ---------------------------------------------------------------------------
-extern "C" hipError_t lme_internal_launch_prop_identity(double *U, const int64_t *off4,
-                                                        const int32_t *dims, int n_inst,
-                                                        hipStream_t s);
+extern "C" hipError_t lme_internal_launch_prop_hbasis(double *U, const int64_t *off4,
+                                                      const int32_t *dims, int n_inst,
+                                                      hipStream_t s);
+extern "C" hipError_t lme_internal_launch_prop_combine(double *U, const int64_t *off4,
+                                                       const int32_t *dims, int n_inst,
+                                                       hipStream_t s);
 extern "C" hipError_t lme_internal_launch_zgemm(const void *tiles, int n_tiles, const int64_t *off4,
                                                 const int32_t *dims, const double *A,
                                                 const double *B, double *C, hipStream_t s);
@@ -2959,17 +2962,24 @@ static int propagator_run(lme_ctx *h, const lme_options *opt, double t0, double 
   if ((rc = cc->d_first.upload(first.data(), first.size() * 8, "replica ranges"))) return rc;
   if ((rc = dev_ensure(cc->d_p1, (size_t)total * 16, "basis matrices"))) return rc;
   if ((rc = dev_ensure(cc->d_pst, 4 * (size_t)first[h->n_inst], "status"))) return rc;
-  hipError_t e = lme_internal_launch_prop_identity(static_cast<double *>(cc->d_p1.p),
-                                                   static_cast<const int64_t *>(cc->d_off4.p),
-                                                   static_cast<const int32_t *>(cc->d_dims.p),
-                                                   h->n_inst, s);
+  // the n^2 Hermitian basis matrices (|a><a|, |a><b| + |b><a|,
+  // i(|b><a| - |a><b|)) are evolved on the Hermitian kernels (each pair
+  // {i, j} once), then combined into the columns of the |i><j| basis
+  hipError_t e = lme_internal_launch_prop_hbasis(static_cast<double *>(cc->d_p1.p),
+                                                 static_cast<const int64_t *>(cc->d_off4.p),
+                                                 static_cast<const int32_t *>(cc->d_dims.p),
+                                                 h->n_inst, s);
   if (e != hipSuccess) return hip_fail(e, "launch basis matrices");
   lme_options o = *opt;
-  o.hermitian = 0;   // the basis matrices |i><j| are not Hermitian
+  o.hermitian = 1;
   const double tl[2] = {t0, t1};
   if ((rc = evolve_impl(cc->prep.get(), &o, 2, tl, cc->d_p1.p, nullptr, nullptr, nullptr, U_dev,
                         nullptr, static_cast<int32_t *>(cc->d_pst.p), stream, false)))
     return rc;
+  e = lme_internal_launch_prop_combine(static_cast<double *>(U_dev),
+                                       static_cast<const int64_t *>(cc->d_off4.p),
+                                       static_cast<const int32_t *>(cc->d_dims.p), h->n_inst, s);
+  if (e != hipSuccess) return hip_fail(e, "launch propagator basis change");
   if (status_dev) {
     e = lme_internal_launch_range_status(static_cast<const int32_t *>(cc->d_pst.p),
                                          static_cast<const int64_t *>(cc->d_first.p), status_dev,

@@ -1,9 +1,10 @@
 // lme_prop.hip -- propagators and the steady state of repeated propagation.
 //
 // The propagator U of an instance (dimension n) is the n^2 x n^2 matrix
-// with vec(rho(t1)) = U vec(rho(t0)) (row-major vec); it is integrated as a
-// batch of the n^2 basis matrices, column c = vec of the solution from
-// |i><j|, c = i n + j, stored column-major.  The steady state of repeated
+// with vec(rho(t1)) = U vec(rho(t0)) (row-major vec), column c = vec of the
+// solution from |i><j|, c = i n + j, stored column-major.  It is integrated
+// as a batch of n^2 Hermitian basis matrices (so the Hermitian kernels,
+// which compute each pair {i, j} once, apply) and recombined.  The steady state of repeated
 // application is the limit of U^(2^k): the columns converge to Tr(X) rho_ss.
 // Squaring is a dense complex FP64 matrix product on the matrix cores
 // (v_mfma_f64_16x16x4f64): a 64 x 64 output tile per workgroup, panels
@@ -19,19 +20,57 @@ namespace {
 
 typedef double double4v __attribute__((ext_vector_type(4)));
 
-// Identity (the n^2 basis matrices) in every instance's propagator block:
-// block b at offset off4[b] (elements), N = n_b^2, column-major.
-__global__ void prop_identity_kernel(double *U, const int64_t *off4, const int32_t *dims,
-                                     int n_inst) {
+// Hermitian basis of the n^2 x n^2 block, column c = a n + b: |a><a| for
+// a = b; X = |a><b| + |b><a| for a < b; Y = i(|b><a| - |a><b|) for a > b
+// (the pair's second Hermitian combination).  Evolved with the Hermitian
+// kernels, the columns give U|p><q| = (U X - i U Y) / 2 and U|q><p| =
+// (U X + i U Y) / 2 (prop_combine_kernel).  Column-major blocks at off4[b].
+__global__ void prop_hbasis_kernel(double *U, const int64_t *off4, const int32_t *dims,
+                                   int n_inst) {
   const int b = blockIdx.y;
   if (b >= n_inst) return;
-  const int64_t N = (int64_t)dims[b] * dims[b];
-  double *Ub = U + 2 * off4[b];
+  const int n = dims[b];
+  const int64_t N = (int64_t)n * n;
+  double2 *Ub = reinterpret_cast<double2 *>(U) + off4[b];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * N;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / N, r = e - c * N;
-    Ub[2 * e] = (r == c) ? 1.0 : 0.0;
-    Ub[2 * e + 1] = 0.0;
+    const int ca = (int)(c / n), cb = (int)(c - (int64_t)ca * n);   // column c = |ca><cb|'s slot
+    const int ra = (int)(r / n), rb = (int)(r - (int64_t)ra * n);   // element (ra, rb)
+    double2 v = make_double2(0.0, 0.0);
+    if (ca == cb) {
+      if (ra == ca && rb == cb) v.x = 1.0;
+    } else if (ca < cb) {
+      if ((ra == ca && rb == cb) || (ra == cb && rb == ca)) v.x = 1.0;
+    } else {   // Y for the pair (cb, ca): i |cb><ca| - i |ca><cb|
+      if (ra == cb && rb == ca) v.y = 1.0;
+      if (ra == ca && rb == cb) v.y = -1.0;
+    }
+    Ub[e] = v;
+  }
+}
+
+// From the evolved Hermitian basis to the |i><j| basis, in place: for every
+// pair a < b the columns c = a n + b (X) and c' = b n + a (Y) become
+// (X - i Y) / 2 and (X + i Y) / 2.  Grid (blocks, n_inst); the thread of
+// element (row r, column c) with c = a n + b, a < b, updates both columns.
+__global__ void prop_combine_kernel(double *U, const int64_t *off4, const int32_t *dims,
+                                    int n_inst) {
+  const int b = blockIdx.y;
+  if (b >= n_inst) return;
+  const int n = dims[b];
+  const int64_t N = (int64_t)n * n;
+  double2 *Ub = reinterpret_cast<double2 *>(U) + off4[b];
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < N * N;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = w / N, r = w - c * N;
+    const int ca = (int)(c / n), cb = (int)(c - (int64_t)ca * n);
+    if (ca >= cb) continue;
+    double2 *X = Ub + c * N, *Y = Ub + ((int64_t)cb * n + ca) * N;
+    const double2 x = X[r], y = Y[r];
+    // -i y = (y.y, -y.x); +i y = (-y.y, y.x)
+    X[r] = make_double2(0.5 * (x.x + y.y), 0.5 * (x.y - y.x));
+    Y[r] = make_double2(0.5 * (x.x - y.y), 0.5 * (x.y + y.x));
   }
 }
 
@@ -249,10 +288,17 @@ extern "C" hipError_t lme_internal_launch_range_status(const int32_t *st, const 
   return hipGetLastError();
 }
 
-extern "C" hipError_t lme_internal_launch_prop_identity(double *U, const int64_t *off4,
-                                                        const int32_t *dims, int n_inst,
-                                                        hipStream_t s) {
-  hipLaunchKernelGGL(prop_identity_kernel, dim3(64, n_inst), dim3(256), 0, s, U, off4, dims,
+extern "C" hipError_t lme_internal_launch_prop_hbasis(double *U, const int64_t *off4,
+                                                      const int32_t *dims, int n_inst,
+                                                      hipStream_t s) {
+  hipLaunchKernelGGL(prop_hbasis_kernel, dim3(256, n_inst), dim3(256), 0, s, U, off4, dims, n_inst);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t lme_internal_launch_prop_combine(double *U, const int64_t *off4,
+                                                       const int32_t *dims, int n_inst,
+                                                       hipStream_t s) {
+  hipLaunchKernelGGL(prop_combine_kernel, dim3(256, n_inst), dim3(256), 0, s, U, off4, dims,
                      n_inst);
   return hipGetLastError();
 }
