@@ -115,21 +115,34 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmTile *tiles, int n
       re[a][b] = double4v{0, 0, 0, 0};
       im[a][b] = double4v{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < N; k0 += kGemmK) {
-    __syncthreads();   // the previous panel is consumed
+  // the next panels are loaded into registers while the current ones are
+  // multiplied, then stored to LDS
+  double2 pa[4], pb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
       // A panel: column k0 + ka, rows r0 .. r0 + 63 (contiguous in A)
       const int ka = idx >> 6, ra = idx & 63;
       const int row = r0 + ra, kk = k0 + ka;
-      As[ka][ra] = (row < N && kk < N) ? Ab[(int64_t)kk * N + row] : double2{0.0, 0.0};
+      pa[q] = (row < N && kk < N) ? Ab[(int64_t)kk * N + row] : double2{0.0, 0.0};
       // B panel: column c0 + cb, rows k0 .. k0 + 15 (contiguous in B)
       const int cb = idx >> 4, kb = idx & 15;
       const int col = c0 + cb, kr = k0 + kb;
-      Bs[kb][cb] = (col < N && kr < N) ? Bb[(int64_t)col * N + kr] : double2{0.0, 0.0};
+      pb[q] = (col < N && kr < N) ? Bb[(int64_t)col * N + kr] : double2{0.0, 0.0};
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < N; k0 += kGemmK) {
+    __syncthreads();   // the previous panel is consumed
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      As[idx >> 6][idx & 63] = pa[q];
+      Bs[idx & 15][idx >> 4] = pb[q];
     }
     __syncthreads();
+    if (k0 + kGemmK < N) fetch(k0 + kGemmK);
 #pragma unroll
     for (int ks = 0; ks < kGemmK; ks += 4) {
       double2 av[2], bv[2];
