@@ -77,7 +77,8 @@ __global__ void prop_combine_kernel(double *U, const int64_t *off4, const int32_
 // C = A B for one instance, one 64 x 64 output tile per workgroup of four
 // wavefronts (each a 32 x 32 quarter: 2 x 2 matrix-core tiles of 16 x 16).
 // Tiles of instance b: (N/64 rounded up)^2, listed in tiles[] as (b, ti, tj).
-// The k dimension advances 16 at a time through LDS: A's 64 x 16 panel and
+// The k dimension advances 16 at a time through LDS (32 measured slower:
+// half the workgroups per CU for its 66 KB of panels): A's 64 x 16 panel and
 // B's 16 x 64 panel (both stored k-major, B's rows padded by one element so
 // that its transposing store spreads over the banks; padding A's rows as
 // well measured no faster).
