@@ -1165,7 +1165,9 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
   stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, 0);
   __syncthreads();
 
-  double2 rho[EPT], yn[EPT], y5[EPT];
+  // yn: the current stage input; after the seventh stage it is the
+  // fifth-order solution (the last stage is evaluated at it)
+  double2 rho[EPT], yn[EPT];
   uint32_t bij[EPT];
   uint32_t vmask = 0;  // slots this thread owns
   const double2 *rho0 = reinterpret_cast<const double2 *>(a.rho0);
@@ -1260,7 +1262,7 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     for (int s = 0; s < EPT; ++s)
       if (valid(s)) L.Y[flat(s)] = rho[s];
     __syncthreads();
-    double2 (&f0)[EPT] = y5;  // the stage arrays are idle until the first step
+    double2 f0[EPT];
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
       f0[s] = make_double2(0.0, 0.0);
@@ -1371,7 +1373,6 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
               for (int jj = 0; jj < st; ++jj) acc = caxpy(kDpA[st][jj], K[jj * SE + g], acc);
               y = caxpy(c.h_try, acc, y);
             }
-            if (st == 6) y5[s] = y;
             yn[s] = y;
             L.Y[f] = y;
           }
@@ -1401,7 +1402,7 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
           for (int jj = 0; jj < 7; ++jj) e = caxpy(kDpE[jj], K[jj * SE + g], e);
           e = make_double2(c.h_try * e.x, c.h_try * e.y);
           const double sc =
-              a.atol + a.rtol * fmax(hypot(rho[s].x, rho[s].y), hypot(y5[s].x, y5[s].y));
+              a.atol + a.rtol * fmax(hypot(rho[s].x, rho[s].y), hypot(yn[s].x, yn[s].y));
           const double r = hypot(e.x, e.y) / sc;
           v = r * r;
         }
@@ -1449,7 +1450,7 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
 #pragma unroll
     for (int s = 0; s < EPT; ++s) {
       if (valid(s) && ctl[slot_b(bij[s])].accept) {
-        rho[s] = y5[s];
+        rho[s] = yn[s];
         const int64_t g = goff(bij[s]);
         K[g] = K[6 * SE + g];
       }
