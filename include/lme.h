@@ -349,7 +349,11 @@ int lme_cost_grad(lme_handle h, int32_t nsteps, int32_t ckpt_every, double t0, d
  *                (256, 512 or 1024; 0 = 1024);
  *   apply_path: column-layout application as pipelined tiles (0: one
  *               persistent workgroup per CU streaming row tiles through two
- *               LDS stages) or as packs of whole instances (1). */
+ *               LDS stages) or as packs of whole instances (1);
+ *   grad_layout: layout of lme_cost_grad, LME_LAYOUT_AUTO (the column layout
+ *                where it applies), LME_LAYOUT_ROW or LME_LAYOUT_COLUMN (one
+ *                control term, real structure, monomial jumps, one
+ *                off-diagonal per row of A; else LME_ENOTSUP). */
 typedef struct lme_tuning {
   int32_t rk4_layout;
   int32_t rk4_block;
@@ -364,6 +368,7 @@ typedef struct lme_tuning {
   double herm_ms_per_step;  /* lme_autotune (hermitian = 1): best trial time   */
   int32_t apply_block;
   int32_t apply_path;
+  int32_t grad_layout;
 } lme_tuning;
 
 int lme_get_tuning(lme_handle h, lme_tuning *t);

@@ -44,6 +44,9 @@ extern "C" int lme_internal_colown_has_shape(int wo, int nc, int nb);
 extern "C" int lme_internal_dp5_epts(int *ept, int cap);
 extern "C" hipError_t lme_internal_launch_grad(int T, int EPT, int nq, const lme::GradArgs *a,
                                                int n_packs, int lds, hipStream_t s);
+extern "C" hipError_t lme_internal_launch_grad_col(int T, int EPT, int wo, int nc,
+                                                   const lme::GradArgs *a, int n_packs, int lds,
+                                                   hipStream_t s);
 extern "C" int lme_internal_dp5_extra_lds(int m);
 extern "C" hipError_t lme_internal_launch_dp5_col(int EPT, int wo, int nc, int nb, int re,
                                                   const lme::Dp5Args *a, int n_packs, int lds,
@@ -2189,14 +2192,32 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
   if (rc) return rc;
   int max_n2 = 0;
   for (auto &d : h->inst) max_n2 = std::max(max_n2, d.n * d.n);
-  // 1024 threads (at most 4 elements each: twice the wavefronts of the
-  // 512-thread configuration at the same packing), else 512 x 8
+  // Column layout (512 threads, at most 4 rows each; one control term, real
+  // structure, the column kernels' operator shapes, adjoint of the same
+  // shape): the column data of both operators in registers.  Otherwise the
+  // row layout: 1024 threads (at most 4 elements each: twice the wavefronts
+  // of the 512-thread configuration at the same packing), else 512 x 8.
+  int wo = 0, nc = 0, nb = 0;
+  bool col = h->n_ctrl == 1 && column_eligible(h, &wo, &nc, &nb) && nb == 1 && wo == 1 &&
+             (nc == 2 || nc == 3) && real_structure(h) && column_fits(h, 512, 4, false);
+  for (auto &d : h->inst)
+    col = col && d.adj.wo == d.fwd.wo && d.adj.nc == d.fwd.nc && d.adj.wc == d.fwd.wc &&
+          d.adj.nb == d.fwd.nb && d.adj.wb == d.fwd.wb;
+  const int gl = h->tuning.grad_layout;
+  if (gl == LME_LAYOUT_COLUMN && !col)
+    return fail(LME_ENOTSUP, "the column layout of the gradient does not cover these operators");
+  col = col && gl != LME_LAYOUT_ROW;
   int T = 1024, EPT = 0;
-  for (int e : {1, 2, 4})
-    if (!EPT && 1024 * e >= max_n2) EPT = e;
-  if (!EPT && 512 * 8 >= max_n2) {
+  if (col) {
     T = 512;
-    EPT = 8;
+    EPT = 4;
+  } else {
+    for (int e : {1, 2, 4})
+      if (!EPT && 1024 * e >= max_n2) EPT = e;
+    if (!EPT && 512 * 8 >= max_n2) {
+      T = 512;
+      EPT = 8;
+    }
   }
   if (!EPT)
     return fail(LME_ENOTSUP, "largest instance (%d elements) exceeds the gradient workgroup",
@@ -2218,7 +2239,7 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
     h->d_ckpt.bytes = ck_bytes + sb_bytes;
   }
   Plan *plan;
-  if ((rc = plan_packs(h, T, EPT, 2, T * EPT, 0, 2, &plan))) return rc;
+  if ((rc = plan_packs(h, T, EPT, 2, T * EPT, col ? 1 : 0, 2, &plan))) return rc;
   lme::GradArgs a;
   std::memset(&a, 0, sizeof a);
   a.packs = static_cast<const PackDesc *>(plan->d_packs.p);
@@ -2240,8 +2261,10 @@ static int cost_grad_impl(lme_handle h, int32_t nsteps, int32_t ckpt_every, doub
   a.stages = reinterpret_cast<double *>(static_cast<uint8_t *>(h->d_ckpt.p) + ck_bytes);
   a.cost = cost_dev;
   a.grad = grad_dev;
-  hipError_t e = lme_internal_launch_grad(T, EPT, h->n_ctrl, &a, (int)plan->packs.size(),
-                                          plan->max_lds, s);
+  hipError_t e = col ? lme_internal_launch_grad_col(T, EPT, wo, nc, &a, (int)plan->packs.size(),
+                                                    plan->max_lds, s)
+                     : lme_internal_launch_grad(T, EPT, h->n_ctrl, &a, (int)plan->packs.size(),
+                                                plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch gradient");
   return LME_OK;
 }
@@ -2294,6 +2317,8 @@ extern "C" int lme_set_tuning(lme_handle h, const lme_tuning *t) {
   if (t->herm_block != 0 && t->herm_block != 256 && t->herm_block != 512 &&
       t->herm_block != 768 && t->herm_block != 1024)
     return fail(LME_EINVAL, "herm_block must be 0, 256, 512, 768 or 1024");
+  if (t->grad_layout < LME_LAYOUT_AUTO || t->grad_layout > LME_LAYOUT_COLUMN)
+    return fail(LME_EINVAL, "unknown layout %d", t->grad_layout);
   h->tuning = *t;
   h->apply_cap = t->apply_cap ? t->apply_cap : 4096;
   h->tuning.apply_cap = h->apply_cap;

@@ -421,6 +421,40 @@ __device__ __forceinline__ int field8(uint32_t v, int f) { return (int)((v >> (8
 // every product here is below 2^24.
 __device__ __forceinline__ int mul24(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
 
+// Control term q of the column layout, (B_q y + y B_q^+)_ij with the column-j
+// data in registers: the arithmetic of two_sided() in its order (exactly-zero
+// parts skipped under RE).  Yrow = Y + i n.
+template <int WO, int NC, int NB, bool RE>
+__device__ __forceinline__ double2 control_col(const OpView &op, const ColData<WO, NC, NB> &cd,
+                                               const double2 *Y, const double2 *Yrow, int i,
+                                               int j, double2 yij, int q) {
+  const int n = op.n, wb = op.wb;
+  const double2 *OB = op.OBval + q * wb * n;
+  const int32_t *OC = op.OBcol + q * wb * n;
+  double2 t = cmul(cadd(op.DB[q * n + i], cd.dbj[q]), yij);
+#pragma unroll
+  for (int w = 0; w < kColWB; ++w)
+    if (w < wb) {
+      const double2 yv = Y[mul24(OC[w * n + i], n) + j];
+      if (RE) {
+        const double o = reinterpret_cast<const double *>(OB + w * n + i)[1];
+        t = make_double2(fma(-o, yv.y, t.x), fma(o, yv.x, t.y));
+      } else {
+        t = cfma(OB[w * n + i], yv, t);
+      }
+    }
+#pragma unroll
+  for (int w = 0; w < kColWB; ++w)
+    if (w < wb) {
+      const double2 yv = Yrow[cd.obcol[q][w]];
+      if (RE)
+        t = make_double2(fma(-cd.obval[q][w].y, yv.y, t.x), fma(cd.obval[q][w].y, yv.x, t.y));
+      else
+        t = cfma(cd.obval[q][w], yv, t);
+    }
+  return t;
+}
+
 // (L y)_ij with the column-j data in registers; same operation order as
 // lindblad_elem().  RE: the off-diagonal entries of A (and of the control
 // terms) are purely imaginary and the jump coefficients real, which holds for
@@ -455,33 +489,7 @@ __device__ __forceinline__ double2 lindblad_col(const OpView &op, const ColData<
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const double u = uq[q];
-    if (u != 0.0) {
-      const int wb = op.wb;
-      const double2 *OB = op.OBval + q * wb * n;
-      const int32_t *OC = op.OBcol + q * wb * n;
-      double2 t = cmul(cadd(op.DB[q * n + i], cd.dbj[q]), yij);
-#pragma unroll
-      for (int w = 0; w < kColWB; ++w)
-        if (w < wb) {
-          const double2 yv = Y[mul24(OC[w * n + i], n) + j];
-          if (RE) {
-            const double o = reinterpret_cast<const double *>(OB + w * n + i)[1];
-            t = make_double2(fma(-o, yv.y, t.x), fma(o, yv.x, t.y));
-          } else {
-            t = cfma(OB[w * n + i], yv, t);
-          }
-        }
-#pragma unroll
-      for (int w = 0; w < kColWB; ++w)
-        if (w < wb) {
-          const double2 yv = Yrow[cd.obcol[q][w]];
-          if (RE)
-            t = make_double2(fma(-cd.obval[q][w].y, yv.y, t.x), fma(cd.obval[q][w].y, yv.x, t.y));
-          else
-            t = cfma(cd.obval[q][w], yv, t);
-        }
-      acc = caxpy(u, t, acc);
-    }
+    if (u != 0.0) acc = caxpy(u, control_col<WO, NC, NB, RE>(op, cd, Y, Yrow, i, j, yij, q), acc);
   }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -1492,8 +1500,13 @@ finish:
 // inner product Re Tr(X^+ Y)).  -i[H_q, Y] is the two-sided control term
 // B_q Y + Y B_q^+ of the forward operator blob.  The blobs of a pack hold the
 // forward operators followed by the adjoint ones.
+// COL: the column-owner layout of the column kernels (thread owns column j of
+// instance b and rows g, g+G, ...; real structure, monomial jumps, the
+// operator shape WO, NC, NQ a template parameter): the column-j data of the
+// forward and of the adjoint operator in registers, elements by
+// lindblad_col() and control_col(), which give the bits of the row layout.
 // ---------------------------------------------------------------------------
-template <int T, int EPT, int NQ>
+template <int T, int EPT, int NQ, int WO = 0, int NC = 0, bool COL = false>
 __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const PackDesc pk = a.packs[blockIdx.x];
@@ -1527,19 +1540,50 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
 
   double2 rho[EPT], acc[EPT], yn[EPT];
   uint32_t bij[EPT];
+  uint32_t vmask = 0;  // slots this thread owns
+  // column layout: this thread's column, its operator data and row indices
+  const int C = COL ? m * n : 0, G = COL ? pk.G : 1;
+  const bool cactive = COL && tid < C * G;
+  const int cg = cactive ? tid / C : 0, cc = cactive ? tid - cg * C : 0;
+  const int cb = cc / (COL ? n : 1), cj = cc - cb * n;
+  ColData<WO, NC, NQ> cdf, cda;
+  uint32_t rif[COL ? EPT : 1], ria[COL ? EPT : 1];
+  if constexpr (COL) {
+    const uint8_t *blob = L.blobs + (size_t)cb * pk.blob_stride;
+    load_column<WO, NC, NQ>(cdf, make_view(blob, BF), cj);
+    load_column<WO, NC, NQ>(cda, make_view(blob + pk.fwd_bytes, BA), cj);
+  }
 #pragma unroll
   for (int s = 0; s < EPT; ++s) {
-    const int f = tid + s * T;
     rho[s] = make_double2(0.0, 0.0);
     bij[s] = 0;
-    if (f < E) {
-      const int b = f / n2, r = f - b * n2;
-      const int i = r / n;
-      bij[s] = pack_bij(b, i, r - i * n);
-      rho[s] = reinterpret_cast<const double2 *>(a.rho0)[L.off[b] + r];
+    if constexpr (COL) {
+      const int i = cg + s * G, ic = min(i, n - 1);
+      const uint8_t *blob = L.blobs + (size_t)cb * pk.blob_stride;
+      rif[s] = row_indices<WO, NC>(make_view(blob, BF), ic);
+      ria[s] = row_indices<WO, NC>(make_view(blob + pk.fwd_bytes, BA), ic);
+      bij[s] = pack_bij(cb, ic, cj);
+      if (cactive && s < pk.ept && i < n) {
+        vmask |= 1u << s;
+        rho[s] = reinterpret_cast<const double2 *>(a.rho0)[L.off[cb] + i * n + cj];
+      }
+    } else {
+      const int f = tid + s * T;
+      if (f < E) {
+        vmask |= 1u << s;
+        const int b = f / n2, r = f - b * n2;
+        const int i = r / n;
+        bij[s] = pack_bij(b, i, r - i * n);
+        rho[s] = reinterpret_cast<const double2 *>(a.rho0)[L.off[b] + r];
+      }
     }
   }
-  auto valid = [&](int s) { return tid + s * T < E; };
+  auto valid = [&](int s) { return ((vmask >> s) & 1u) != 0; };
+  // pack element index of slot s
+  auto flat = [&](int s) {
+    if constexpr (COL) return slot_b(bij[s]) * n2 + slot_i(bij[s]) * n + slot_j(bij[s]);
+    else return tid + s * T;
+  };
   auto goff = [&](uint32_t v) { return L.off[slot_b(v)] + slot_i(v) * n + slot_j(v); };
   auto set_u = [&](int st) {  // between two barriers
     const int seg = a.seg_of_step[st];
@@ -1555,7 +1599,14 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
     const int b = slot_b(v);
     const uint8_t *blob = L.blobs + (size_t)b * pk.blob_stride;
     const OpView op = adjoint ? make_view(blob + pk.fwd_bytes, BA) : make_view(blob, BF);
-    return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), yij, L.u + b * pk.nb);
+    if constexpr (COL) {
+      uint32_t ri = adjoint ? ria[s] : rif[s];
+      asm volatile("" : "+v"(ri));
+      return lindblad_col<WO, NC, NQ, true>(op, adjoint ? cda : cdf, L.Y + b * n2, slot_i(v), ri,
+                                            slot_j(v), yij, L.u + b * pk.nb);
+    } else {
+      return lindblad_elem(op, L.Y + b * n2, slot_i(v), slot_j(v), yij, L.u + b * pk.nb);
+    }
   };
 
   // ---- forward pass with checkpoints
@@ -1578,7 +1629,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
       if (stage == 0) set_u(st);
 #pragma unroll
       for (int s = 0; s < EPT; ++s)
-        if (valid(s)) L.Y[tid + s * T] = yn[s];
+        if (valid(s)) L.Y[flat(s)] = yn[s];
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < EPT; ++s)
@@ -1596,7 +1647,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < EPT; ++s)
-    if (valid(s)) L.Y[tid + s * T] = rho[s];
+    if (valid(s)) L.Y[flat(s)] = rho[s];
   __syncthreads();
   const double2 *O = reinterpret_cast<const double2 *>(a.O);
   double2 lam[EPT];
@@ -1617,7 +1668,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < EPT; ++s)
-    if (valid(s)) red[tid + s * T] = part[s];
+    if (valid(s)) red[flat(s)] = part[s];
   __syncthreads();
   per_instance_sum<T>(red, m, n2, sums);
   __syncthreads();
@@ -1638,7 +1689,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < EPT; ++s)
-        if (valid(s)) red[tid + s * T] = gacc[s][q];
+        if (valid(s)) red[flat(s)] = gacc[s][q];
       __syncthreads();
       per_instance_sum<T>(red, m, n2, sums);
       __syncthreads();
@@ -1673,7 +1724,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
 #pragma unroll
         for (int s = 0; s < EPT; ++s)
           if (valid(s)) {
-            L.Y[tid + s * T] = yn[s];
+            L.Y[flat(s)] = yn[s];
             SB[((int64_t)(st - s0) * 4 + stage) * SE + goff(bij[s])] = yn[s];
           }
         __syncthreads();
@@ -1724,7 +1775,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
         if (stage == 3) set_u(st);
 #pragma unroll
         for (int s = 0; s < EPT; ++s)
-          if (valid(s)) L.Y[tid + s * T] = sbn[s];
+          if (valid(s)) L.Y[flat(s)] = sbn[s];
         {  // prefetch: stage - 1 of this step, or stage 3 of the step before
           const int pst = stage > 0 ? st : st - 1, pstage = stage > 0 ? stage - 1 : 3;
           if (pst >= s0) {
@@ -1745,8 +1796,12 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
               const double2 yij = Yb[i * n + j];
 #pragma unroll
               for (int q = 0; q < NQ; ++q) {
-                const double2 bq = two_sided(op.DB + q * n, op.OBval + q * op.wb * n,
-                                             op.OBcol + q * op.wb * n, op.wb, n, Yb, i, j, yij);
+                double2 bq;
+                if constexpr (COL)
+                  bq = control_col<WO, NC, NQ, true>(op, cdf, Yb, Yb + mul24(i, n), i, j, yij, q);
+                else
+                  bq = two_sided(op.DB + q * n, op.OBval + q * op.wb * n, op.OBcol + q * op.wb * n,
+                                 op.wb, n, Yb, i, j, yij);
                 gacc[s][q] += kap[s].x * bq.x + kap[s].y * bq.y;
               }
             }
@@ -1755,7 +1810,7 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < EPT; ++s)
-          if (valid(s)) L.Y[tid + s * T] = kap[s];
+          if (valid(s)) L.Y[flat(s)] = kap[s];
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < EPT; ++s)
@@ -3025,9 +3080,9 @@ extern "C" hipError_t lme_internal_launch_dp5(int EPT, const lme::Dp5Args *a, in
   return hipErrorInvalidValue;
 }
 
-template <int T, int EPT, int NQ>
+template <int T, int EPT, int NQ, int WO = 0, int NC = 0, bool COL = false>
 static hipError_t launch_grad_t(const lme::GradArgs &a, int n_packs, int lds, hipStream_t s) {
-  auto k = lme::grad_resident_kernel<T, EPT, NQ>;
+  auto k = lme::grad_resident_kernel<T, EPT, NQ, WO, NC, COL>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -3046,6 +3101,19 @@ extern "C" hipError_t lme_internal_launch_grad(int T, int EPT, int nq, const lme
   LME_G(1024, 1, 1) LME_G(1024, 2, 1) LME_G(1024, 4, 1)
   LME_G(1024, 1, 2) LME_G(1024, 2, 2) LME_G(1024, 4, 2)
 #undef LME_G
+  return hipErrorInvalidValue;
+}
+
+// Column-owner gradient kernel: T threads, EPT rows per thread, one control
+// term, real structure, operator shape (wo, nc) of the column kernels.
+extern "C" hipError_t lme_internal_launch_grad_col(int T, int EPT, int wo, int nc,
+                                                   const lme::GradArgs *a, int n_packs, int lds,
+                                                   hipStream_t s) {
+#define LME_GC(TT, E, W, K)                           \
+  if (T == TT && EPT == E && wo == W && nc == K)      \
+    return launch_grad_t<TT, E, 1, W, K, true>(*a, n_packs, lds, s);
+  LME_GC(512, 4, 1, 2) LME_GC(512, 4, 1, 3)
+#undef LME_GC
   return hipErrorInvalidValue;
 }
 

@@ -140,7 +140,7 @@ class Tuning(C.Structure):
                 ("apply_lds_kb", C.c_int32), ("rk4_ms_per_step", C.c_double),
                 ("apply_us", C.c_double), ("herm_layout", C.c_int32), ("herm_block", C.c_int32),
                 ("herm_ms_per_step", C.c_double), ("apply_block", C.c_int32),
-                ("apply_path", C.c_int32)]
+                ("apply_path", C.c_int32), ("grad_layout", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

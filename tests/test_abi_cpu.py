@@ -35,7 +35,8 @@ def test_default_options():
     assert o.hermitian == 0
     # the ctypes mirrors have the C layout (fields appended at the end)
     assert C.sizeof(lme.Options) == 72 and lme.Options.hermitian.offset == 64
-    assert C.sizeof(lme.Tuning) == 56 and lme.Tuning.apply_block.offset == 48
+    assert C.sizeof(lme.Tuning) == 64 and lme.Tuning.apply_block.offset == 48
+    assert lme.Tuning.grad_layout.offset == 56
 
 
 def _jc():
@@ -352,3 +353,16 @@ def test_propagator_and_steadystate_validation_before_device_use():
     import torch
     if not torch.cuda.is_available():
         assert prop() == lme.LME_EHIP and ss() == lme.LME_EHIP
+
+
+def test_tuning_grad_layout_roundtrip_and_range():
+    """lme_set_tuning takes grad_layout in {AUTO, ROW, COLUMN} and rejects
+    anything else without touching the handle's settings."""
+    h = lme.Handle([S.jc_system(3)])
+    h.set_tuning(grad_layout=lme.LME_LAYOUT_ROW)
+    assert h.get_tuning().grad_layout == lme.LME_LAYOUT_ROW
+    for bad in (-1, 3):
+        with pytest.raises(lme.LmeError) as e:
+            h.set_tuning(grad_layout=bad)
+        assert e.value.code == lme.LME_EINVAL
+    assert h.get_tuning().grad_layout == lme.LME_LAYOUT_ROW

@@ -117,3 +117,47 @@ def test_autograd_function():
     loss.backward()
     _, g = lme._cost_grad(h, rho0, O, u.detach(), 0.0, 1.2, w.nsteps, 5)
     assert torch.equal(u.grad, -g)
+
+
+def test_grad_column_layout_bitwise_row_layout_ragged():
+    """The column layout (each thread's column of the forward and adjoint
+    operators in registers) gives the bits of the row layout, on a ragged
+    batch (N = 3..10, several instances per pack) with a general observable;
+    asking for the column layout where it does not apply is an error."""
+    rng = np.random.default_rng(21)
+    systems, Os = [], []
+    for b in range(9):
+        N = 3 + (b * 5) % 8
+        s = S.jc_system(N, g=0.3, kappa=0.02, gamma=0.05, psi0=(0, 1))
+        a = S.jc_ops(N)[0]
+        s.H_ctrl = [S.tidy(a + S.dag(a))]
+        s.edges = np.linspace(0.0, 1.2, 5)
+        s.u = rng.normal(0, 0.4, size=(1, 4))
+        systems.append(s)
+        X = rng.normal(size=(s.n, s.n)) + 1j * rng.normal(size=(s.n, s.n))
+        Os.append(X + X.conj().T)
+    out = {}
+    for layout in (lme.LME_LAYOUT_COLUMN, lme.LME_LAYOUT_ROW, 0):
+        h = lme.Handle(systems)
+        h.set_tuning(grad_layout=layout)
+        cost, grad = lme._cost_grad(h, h.pack([s.rho0 for s in systems]), h.pack(Os), None,
+                                    0.0, 1.2, 24, 5)
+        torch.cuda.synchronize()
+        out[layout] = (cost.cpu().numpy(), grad.cpu().numpy())
+    for layout in (lme.LME_LAYOUT_ROW, 0):
+        assert np.array_equal(out[layout][0], out[lme.LME_LAYOUT_COLUMN][0])
+        assert np.array_equal(out[layout][1], out[lme.LME_LAYOUT_COLUMN][1])
+    for b in (0, 4, 8):
+        J, g = oracle.rk4_cost_grad(systems[b], systems[b].rho0, Os[b], 0.0, 1.2, 24)
+        assert abs(out[0][0][b] - J) <= 1e-12
+        assert np.max(np.abs(out[0][1][b] - g)) <= 1e-10 * max(1e-3, np.max(np.abs(g)))
+    # two control terms: no column layout
+    s2 = S.jc_system(3, g=0.4, kappa=0.1, gamma=0.05, psi0=(0, 1))
+    a = S.jc_ops(3)[0]
+    s2.H_ctrl = [S.tidy(a + S.dag(a)), S.tidy(1j * (S.dag(a) - a))]
+    s2.edges = np.linspace(0.0, 1.0, 3)
+    s2.u = np.zeros((2, 2))
+    h = lme.Handle([s2])
+    h.set_tuning(grad_layout=lme.LME_LAYOUT_COLUMN)
+    with pytest.raises(lme.LmeError):
+        lme._cost_grad(h, h.pack([s2.rho0]), h.pack([np.eye(6)]), None, 0.0, 1.0, 4, 2)
