@@ -164,7 +164,10 @@ struct Rk4Args {
 // Closed-form amplitude c0 + c1 t + c2 t^2 + c3 t^3 + a cos(w t + phi) with
 // p = (c0, c1, c2, c3, a, w, phi).
 LME_HD inline double coeff_fn_at(const double *p, double t) {
-  return p[0] + t * (p[1] + t * (p[2] + t * p[3])) + p[4] * cos(p[5] * t + p[6]);
+  // without a cosine term the polynomial alone (the cosine's product with a
+  // zero amplitude could only change the sign of a zero result)
+  const double poly = p[0] + t * (p[1] + t * (p[2] + t * p[3]));
+  return p[4] != 0.0 ? poly + p[4] * cos(p[5] * t + p[6]) : poly + 0.0;
 }
 
 // Monte-Carlo wave-function kernel (lme_mc.hip).  Operators of one system:

@@ -247,6 +247,19 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
   }
   stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, a.adjoint);
   __syncthreads();
+  // closed-form amplitudes with one (instance, term) pair per thread: the
+  // pair's seven coefficients are read once into registers, so a stage's
+  // amplitudes wait on no memory load
+  const bool fn_reg = a.fn != nullptr && pk.m * pk.nb <= T;
+  double cf[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) cf[k] = 0.0;
+  if (fn_reg && tid < pk.m * pk.nb) {
+    const int b = tid / pk.nb, q = tid - b * pk.nb;
+    const double *p = a.fn + 7 * ((int64_t)L.ids[b] * a.n_ctrl + q);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) cf[k] = p[k];
+  }
 
   double2 rho[EPT], acc[EPT], yn[EPT];
   uint32_t bij[EPT];
@@ -299,8 +312,15 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
       const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
       const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
       __syncthreads();  // every reader of the previous stage input is done
-      if (pk.nb > 0 && (stage == 0 || a.fn))
+      if (fn_reg) {
+        if (tid < pk.m * pk.nb) {  // the times of rk4_stage_controls()
+          const double tb = a.t0 + (double)st * a.h;
+          const double ts = stage == 0 ? tb : (stage == 3 ? tb + a.h : tb + 0.5 * a.h);
+          L.u[tid] = coeff_fn_at(cf, ts);
+        }
+      } else if (pk.nb > 0 && (stage == 0 || a.fn)) {
         rk4_stage_controls(a, pk, L.ids, L.u, st, stage, tid, T);
+      }
 #pragma unroll
       for (int s = 0; s < EPT; ++s) {
         const int f = tid + s * T;
