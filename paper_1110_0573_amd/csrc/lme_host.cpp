@@ -34,6 +34,9 @@ using lme::PackDesc;
 extern "C" int lme_internal_rk4_configs(int *T, int *EPT, int cap);
 extern "C" int lme_internal_pack_lds_bytes(int n, int m, int blob_bytes, int nb);
 extern "C" int lme_internal_blob_stride(int blob_bytes);
+extern "C" int lme_internal_lane_fits(int wo, int nb, int wb, int nc, int wc);
+extern "C" hipError_t lme_internal_launch_rk4_lane(const lme::Rk4Args *a, int n_packs, int lds,
+                                                   hipStream_t s);
 extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args *a,
                                               int n_packs, int lds, hipStream_t s);
 extern "C" hipError_t lme_internal_launch_rk4_colown(int cfg, int herm, int wo, int nc, int nb,
@@ -1600,9 +1603,16 @@ static int evolve_impl(lme_handle h, const lme_options *opt, int32_t n_t, const 
   a.expect = static_cast<double *>(expect_dev);
   a.counts = counts_dev;
   a.status = status_dev;
+  // one-wavefront packs of small instances: one element per lane, the stage
+  // input exchanged between lanes
+  bool lane = !column && T == 64 && EPT == 1;
+  for (auto &d : h->inst)
+    lane = lane && lme_internal_lane_fits(d.fwd.wo, d.fwd.nb, d.fwd.wb, d.fwd.nc, d.fwd.wc);
   if (column)
     e = lme_internal_launch_rk4_colown(col_cfg, column == 2, wo, nc, nb, re, &a,
                                        (int)plan->packs.size(), plan->max_lds, s);
+  else if (lane)
+    e = lme_internal_launch_rk4_lane(&a, (int)plan->packs.size(), plan->max_lds, s);
   else
     e = lme_internal_launch_rk4(T, EPT, &a, (int)plan->packs.size(), plan->max_lds, s);
   if (e != hipSuccess) return hip_fail(e, "launch resident RK4");

@@ -369,6 +369,213 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Resident fixed-step RK4 for small instances (n^2 <= 64): one wavefront per
+// pack, one element per lane, an instance's elements in consecutive lanes.
+// Each lane keeps its element's operator terms in registers (coefficients and
+// the lanes of their sources, in the order of lindblad_elem()) and reads the
+// stage input of its instance from the other lanes with cross-lane permutes,
+// so a stage touches no LDS and needs no barrier.  The terms are those of
+// lindblad_elem() in its order: without control terms, or with diagonal
+// ones, the results have the bits of rk4_resident_kernel; with off-diagonal
+// control terms and jumps they can differ from it in the last bit.
+// Operator widths: at most kLaneWO off-diagonals per row of A, kLaneNB
+// control terms of kLaneWB off-diagonals, kLaneJ jump products per element.
+// ---------------------------------------------------------------------------
+constexpr int kLaneWO = 2, kLaneNB = 2, kLaneWB = 2, kLaneJ = 4;
+
+// lane src's value of v (every lane of the wavefront takes part)
+__device__ __forceinline__ double2 lane_read(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+__global__ __launch_bounds__(64) void rk4_lane_kernel(Rk4Args a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const PackDesc pk = a.packs[blockIdx.x];
+  const int n = pk.n, n2 = n * n, E = pk.m * n2;
+  const PackLds L = carve(smem, pk);
+  const BlobLayout BL = blob_layout(n, pk.wo, pk.nb, pk.wb, pk.nc, pk.wc);
+  const int tid = threadIdx.x;
+
+  for (int b = tid; b < pk.m; b += 64) {
+    const int id = a.order[pk.first + b];
+    L.ids[b] = id;
+    L.off[b] = a.inst[id].rho_off;
+    if (a.status) a.status[id] = 0;
+  }
+  stage_blobs(L.blobs, pk, a.order, a.inst, a.ops, 0);
+  __syncthreads();
+
+  // this lane's element (i, j) of pack instance b; padding lanes (tid >= E)
+  // get zero coefficients and read themselves
+  const bool own = tid < E;
+  const int b = own ? tid / n2 : 0, r = own ? tid - b * n2 : 0;
+  const int i = r / n, j = r - i * n, base = b * n2;
+  const int wo = pk.wo, nb = pk.nb, wb = pk.wb, wc = pk.wc, nj = pk.nc * pk.wc * pk.wc;
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 dsum = zero, ao[kLaneWO], bo[kLaneWO], qd[kLaneNB], qa[kLaneNB][kLaneWB],
+          qb[kLaneNB][kLaneWB], jp[kLaneJ];
+  int as[kLaneWO], bs[kLaneWO], qas[kLaneNB][kLaneWB], qbs[kLaneNB][kLaneWB], js[kLaneJ];
+  double cf[kLaneNB][7];
+#pragma unroll
+  for (int w = 0; w < kLaneWO; ++w) {
+    ao[w] = bo[w] = zero;
+    as[w] = bs[w] = tid;
+  }
+#pragma unroll
+  for (int q = 0; q < kLaneNB; ++q) {
+    qd[q] = zero;
+#pragma unroll
+    for (int w = 0; w < kLaneWB; ++w) {
+      qa[q][w] = qb[q][w] = zero;
+      qas[q][w] = qbs[q][w] = tid;
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) cf[q][k] = 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < kLaneJ; ++t) {
+    jp[t] = zero;
+    js[t] = tid;
+  }
+  if (own) {
+    const OpView op = make_view(L.blobs + (size_t)b * pk.blob_stride, BL);
+    dsum = cadd(op.D[i], cconj(op.D[j]));
+#pragma unroll
+    for (int w = 0; w < kLaneWO; ++w)
+      if (w < wo) {
+        ao[w] = op.Oval[w * n + i];
+        as[w] = base + op.Ocol[w * n + i] * n + j;
+        bo[w] = op.Oval[w * n + j];
+        bs[w] = base + i * n + op.Ocol[w * n + j];
+      }
+#pragma unroll
+    for (int q = 0; q < kLaneNB; ++q)
+      if (q < nb) {
+        qd[q] = cadd(op.DB[q * n + i], cconj(op.DB[q * n + j]));
+        const double2 *OB = op.OBval + q * wb * n;
+        const int32_t *OC = op.OBcol + q * wb * n;
+#pragma unroll
+        for (int w = 0; w < kLaneWB; ++w)
+          if (w < wb) {
+            qa[q][w] = OB[w * n + i];
+            qas[q][w] = base + OC[w * n + i] * n + j;
+            qb[q][w] = OB[w * n + j];
+            qbs[q][w] = base + i * n + OC[w * n + j];
+          }
+        if (a.fn) {
+          const double *p = a.fn + 7 * ((int64_t)L.ids[b] * a.n_ctrl + q);
+#pragma unroll
+          for (int k = 0; k < 7; ++k) cf[q][k] = p[k];
+        }
+      }
+    // jump products p = J_k[i][w] conj(J_k[j][v]) with source (c_i, c_j),
+    // in the order k, w, v
+#pragma unroll
+    for (int t = 0; t < kLaneJ; ++t)
+      if (t < nj) {
+        const int k = t / (wc * wc), w = (t / wc) % wc, v = t % wc;
+        const double2 *Jv = op.Jval + k * wc * n;
+        const int32_t *Jc = op.Jcol + k * wc * n;
+        jp[t] = cmul(Jv[w * n + i], cconj(Jv[v * n + j]));
+        js[t] = base + Jc[w * n + i] * n + Jc[v * n + j];
+      }
+  }
+  double2 rho = own ? reinterpret_cast<const double2 *>(a.rho0)[L.off[b] + r] : zero;
+
+  const bool want_expect = a.expect != nullptr && a.n_e > 0;
+  int next_out = 0;
+  const double h = a.h;
+  for (int st = 0;; ++st) {
+    // outputs due after st steps (st = 0: the initial state)
+    while (next_out < a.n_t && a.out_step[next_out] == st) {
+      __syncthreads();
+      if (own) {
+        L.Y[tid] = rho;
+        if (a.states)
+          reinterpret_cast<double2 *>(a.states)[(int64_t)next_out * a.state_elems + L.off[b] + r] =
+              rho;
+      }
+      __syncthreads();
+      if (want_expect) write_outputs<64>(a, pk, L, next_out);
+      ++next_out;
+    }
+    if (st == a.nsteps) break;
+
+    // amplitudes: a piecewise-constant segment value for the whole step, or
+    // the closed form at each stage's time (those of rk4_stage_controls())
+    double u[kLaneNB];
+    const int seg = a.seg_of_step[st];
+#pragma unroll
+    for (int q = 0; q < kLaneNB; ++q)
+      u[q] = (own && q < nb && !a.fn && seg >= 0)
+                 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
+    double2 yn = rho, acc = zero;
+    for (int stage = 0; stage < 4; ++stage) {
+      const double cnext = stage < 2 ? 0.5 * h : (stage == 2 ? h : 0.0);
+      const double wgt = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+      if (a.fn) {
+        const double tb = a.t0 + (double)st * a.h;
+        const double ts = stage == 0 ? tb : (stage == 3 ? tb + a.h : tb + 0.5 * a.h);
+#pragma unroll
+        for (int q = 0; q < kLaneNB; ++q) u[q] = q < nb ? coeff_fn_at(cf[q], ts) : 0.0;
+      }
+      // the sources, read from their lanes before any product
+      double2 ya[kLaneWO], yb[kLaneWO], yqa[kLaneNB][kLaneWB], yqb[kLaneNB][kLaneWB], yj[kLaneJ];
+#pragma unroll
+      for (int w = 0; w < kLaneWO; ++w)
+        if (w < wo) {
+          ya[w] = lane_read(yn, as[w]);
+          yb[w] = lane_read(yn, bs[w]);
+        }
+#pragma unroll
+      for (int q = 0; q < kLaneNB; ++q)
+#pragma unroll
+        for (int w = 0; w < kLaneWB; ++w)
+          if (q < nb && w < wb) {
+            yqa[q][w] = lane_read(yn, qas[q][w]);
+            yqb[q][w] = lane_read(yn, qbs[q][w]);
+          }
+#pragma unroll
+      for (int t = 0; t < kLaneJ; ++t)
+        if (t < nj) yj[t] = lane_read(yn, js[t]);
+      // (L y)_ij in the order of lindblad_elem()
+      double2 kv = cmul(dsum, yn);
+#pragma unroll
+      for (int w = 0; w < kLaneWO; ++w)
+        if (w < wo) kv = cfma(ao[w], ya[w], kv);
+#pragma unroll
+      for (int w = 0; w < kLaneWO; ++w)
+        if (w < wo) kv = cfma_conj(bo[w], yb[w], kv);
+#pragma unroll
+      for (int q = 0; q < kLaneNB; ++q)
+        if (q < nb && u[q] != 0.0) {
+          double2 tq = cmul(qd[q], yn);
+#pragma unroll
+          for (int w = 0; w < kLaneWB; ++w)
+            if (w < wb) tq = cfma(qa[q][w], yqa[q][w], tq);
+#pragma unroll
+          for (int w = 0; w < kLaneWB; ++w)
+            if (w < wb) tq = cfma_conj(qb[q][w], yqb[q][w], tq);
+          kv = caxpy(u[q], tq, kv);
+        }
+#pragma unroll
+      for (int t = 0; t < kLaneJ; ++t)
+        if (t < nj) kv = cfma(jp[t], yj[t], kv);
+      acc = caxpy(wgt, kv, acc);
+      yn = caxpy(cnext, kv, rho);
+    }
+    rho = caxpy(h / 6.0, acc, rho);
+  }
+
+  if (a.rho_out && own) reinterpret_cast<double2 *>(a.rho_out)[L.off[b] + r] = rho;
+  if (a.counts)
+    for (int bb = tid; bb < pk.m; bb += 64) {
+      a.counts[2 * (int64_t)L.ids[bb]] = a.nsteps;
+      a.counts[2 * (int64_t)L.ids[bb] + 1] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Resident fixed-step RK4, column-owner layout.  The pack's m instances form
 // C = m*n columns; thread t < C*G owns column c = t mod C (instance b, column
 // j) and rows i = g, g+G, g+2G, ... with g = t div C.
@@ -3001,6 +3208,22 @@ extern "C" hipError_t lme_internal_launch_rk4(int T, int EPT, const lme::Rk4Args
   LME_RK4_CASE(1024, 1) LME_RK4_CASE(1024, 2) LME_RK4_CASE(1024, 4) LME_RK4_CASE(1024, 6)
 #undef LME_RK4_CASE
   return hipErrorInvalidValue;
+}
+
+// Small instances, one element per lane (the packs of the 64 x 1 row
+// configuration); the operator widths must be within the kLane* limits.
+extern "C" int lme_internal_lane_fits(int wo, int nb, int wb, int nc, int wc) {
+  return wo <= lme::kLaneWO && nb <= lme::kLaneNB && wb <= lme::kLaneWB &&
+         nc * wc * wc <= lme::kLaneJ;
+}
+
+extern "C" hipError_t lme_internal_launch_rk4_lane(const lme::Rk4Args *a, int n_packs, int lds,
+                                                   hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(lme::rk4_lane_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lme::rk4_lane_kernel, dim3(n_packs), dim3(64), lds, s, *a);
+  return hipGetLastError();
 }
 
 template <int T, int EPT, int WO, int NC, int NB, bool RE, bool HM>

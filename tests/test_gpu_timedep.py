@@ -122,3 +122,34 @@ def test_landau_zener_sweep_as_benchmarked_sampled():
         oex, ost = oracle.rk4(s, s.rho0, w.tlist, w.nsteps, store_states=True)
         assert brute.trace_distance(rho[b], ost[-1]) <= TD
         assert np.max(np.abs(ex[b] - oex)) <= TD
+
+
+def test_small_instances_lane_kernel_against_row_kernel():
+    """Batches of instances with n^2 <= 64 run one element per lane (one
+    wavefront per pack, the stage input exchanged between lanes, no LDS in a
+    stage).  Landau-Zener problems (closed-form amplitudes on a diagonal
+    control term, one jump) give the bits of the row kernel at 256 threads;
+    qubit x cavity systems (N = 2..4, two piecewise-constant off-diagonal
+    controls, three collapse operators) agree with it to 1e-15 (the last bit
+    can differ after many steps) and with the oracle."""
+    w = S.landau_zener_sweep(n_inst=40, seed=5, n_out=51, steps_per_out=120)
+    _, lane = evolve(w.systems, w.tlist, w.nsteps)
+    _, row = evolve(w.systems, w.tlist, w.nsteps, block=256)
+    for k in ("expect", "states", "rho"):
+        assert torch.equal(lane[k], row[k]), k
+    rng = np.random.default_rng(23)
+    systems = []
+    for b in range(10):
+        N = 2 + b % 3
+        s = S.jc_system(N, g=0.3 + 0.02 * b, kappa=0.1, gamma=0.05, n_th=0.2, psi0=(b % 2, 1))
+        a = S.jc_ops(N)[0]
+        s.H_ctrl = [S.tidy(a + S.dag(a)), S.tidy(1j * (S.dag(a) - a))]
+        s.edges = np.linspace(0.0, 2.0, 5)
+        s.u = rng.normal(0.0, 0.5, size=(2, 4))
+        systems.append(s)
+    tl = np.linspace(0.0, 2.0, 11)
+    hl, lane = evolve(systems, tl, 400)
+    _, row = evolve(systems, tl, 400, block=256)
+    for k in ("expect", "states", "rho"):
+        assert torch.max(torch.abs(lane[k] - row[k])).item() <= 1e-15, k
+    check(hl, lane, systems, tl, 400, every=3)
