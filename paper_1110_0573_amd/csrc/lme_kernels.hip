@@ -22,8 +22,12 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// a * b with the product fused into each sum written out: left to the
+// compiler, which product of a.x b.y + a.y b.x it fuses depends on the
+// surrounding code, and two kernels evaluating the same element could round
+// it differently
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 // c + a * b
 __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
@@ -375,9 +379,8 @@ __global__ __launch_bounds__(T) void rk4_resident_kernel(Rk4Args a) {
 // the lanes of their sources, in the order of lindblad_elem()) and reads the
 // stage input of its instance from the other lanes with cross-lane permutes,
 // so a stage touches no LDS and needs no barrier.  The terms are those of
-// lindblad_elem() in its order: without control terms, or with diagonal
-// ones, the results have the bits of rk4_resident_kernel; with off-diagonal
-// control terms and jumps they can differ from it in the last bit.
+// lindblad_elem() in its order, so the results have the bits of
+// rk4_resident_kernel.
 // Operator widths: at most kLaneWO off-diagonals per row of A, kLaneNB
 // control terms of kLaneWB off-diagonals, kLaneJ jump products per element.
 // ---------------------------------------------------------------------------
