@@ -47,7 +47,9 @@ def test_noalloc_dopri5_twice_second_smaller():
 
 def test_noalloc_rk4_twice_second_smaller_both_layouts():
     """Fixed step: step tables and pack tables in the scratch array; full and
-    Hermitian column kernels, then a smaller batch on the row kernel."""
+    Hermitian column kernels, then a smaller batch on the row kernel, then
+    small instances with two control terms on the one-element-per-lane
+    kernel."""
     w = S.jc_sweep(n_inst=64, seed=93, nsteps=200, t_end=5.0, n_out=11)
     for herm in (False, True):
         ref, got = both(w.systems, w.tlist, method="rk4", nsteps=w.nsteps, hermitian=herm)
@@ -56,6 +58,18 @@ def test_noalloc_rk4_twice_second_smaller_both_layouts():
     ref2, got2 = both(w2.systems, w2.tlist, method="rk4", nsteps=w2.nsteps,
                       layout=lme.LME_LAYOUT_ROW)
     assert_same(ref2, got2)
+    rng = np.random.default_rng(97)
+    small = []
+    for b in range(6):
+        N = 2 + b % 3
+        s = S.jc_system(N, g=0.3, kappa=0.1, gamma=0.05, psi0=(b % 2, 1))
+        a = S.jc_ops(N)[0]
+        s.H_ctrl = [S.tidy(a + S.dag(a)), S.tidy(1j * (S.dag(a) - a))]
+        s.edges = np.linspace(0.0, 1.0, 3)
+        s.u = rng.normal(0.0, 0.5, size=(2, 2))
+        small.append(s)
+    ref3, got3 = both(small, np.linspace(0.0, 1.0, 5), method="rk4", nsteps=100)
+    assert_same(ref3, got3)
 
 
 def test_noalloc_kerr_dopri5_matches():
