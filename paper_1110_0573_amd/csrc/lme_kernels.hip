@@ -1596,20 +1596,44 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     }
     if (!__syncthreads_or(any)) break;
 
-    // ---- seven stages
+    // ---- seven stages.  In the column layout every slot of a thread belongs
+    // to instance cb, whose step control the stages only read: it is read
+    // once per step instead of once per slot and stage.
+    int c_active = 0, c_need_k1 = 0;
+    double c_h_try = 0.0;
+    if constexpr (COL) {
+      const DpCtl &c = ctl[cb];
+      c_active = c.active;
+      c_need_k1 = c.need_k1;
+      c_h_try = c.h_try;
+    }
+    auto ctl_of = [&](int s, int &act, int &nk1, double &ht) {
+      if constexpr (COL) {
+        act = c_active;
+        nk1 = c_need_k1;
+        ht = c_h_try;
+      } else {
+        const DpCtl &c = ctl[slot_b(bij[s])];
+        act = c.active;
+        nk1 = c.need_k1;
+        ht = c.h_try;
+      }
+    };
     for (int st = 0; st < 7; ++st) {
 #pragma unroll
       for (int s = 0; s < EPT; ++s) {
         if (valid(s)) {
           const int f = flat(s);
-          const DpCtl &c = ctl[slot_b(bij[s])];
-          if (c.active) {
+          int act, nk1;
+          double ht;
+          ctl_of(s, act, nk1, ht);
+          if (act) {
             double2 y = rho[s];
             if (st > 0) {
               const int64_t g = goff(bij[s]);
               double2 acc = make_double2(0.0, 0.0);
               for (int jj = 0; jj < st; ++jj) acc = caxpy(kDpA[st][jj], K[jj * SE + g], acc);
-              y = caxpy(c.h_try, acc, y);
+              y = caxpy(ht, acc, y);
             }
             yn[s] = y;
             L.Y[f] = y;
@@ -1620,8 +1644,10 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
 #pragma unroll
       for (int s = 0; s < EPT; ++s) {
         if (valid(s)) {
-          const DpCtl &c = ctl[slot_b(bij[s])];
-          if (c.active && (st > 0 || c.need_k1)) K[st * SE + goff(bij[s])] = elem(s, yn[s]);
+          int act, nk1;
+          double ht;
+          ctl_of(s, act, nk1, ht);
+          if (act && (st > 0 || nk1)) K[st * SE + goff(bij[s])] = elem(s, yn[s]);
         }
       }
       __syncthreads();
@@ -1632,13 +1658,15 @@ __global__ __launch_bounds__(T) void dp5_resident_kernel(Dp5Args a) {
     for (int s = 0; s < EPT; ++s) {
       if (valid(s)) {
         const int f = flat(s);
-        const DpCtl &c = ctl[slot_b(bij[s])];
+        int act, nk1;
+        double ht;
+        ctl_of(s, act, nk1, ht);
         double v = 0.0;
-        if (c.active) {
+        if (act) {
           const int64_t g = goff(bij[s]);
           double2 e = make_double2(0.0, 0.0);
           for (int jj = 0; jj < 7; ++jj) e = caxpy(kDpE[jj], K[jj * SE + g], e);
-          e = make_double2(c.h_try * e.x, c.h_try * e.y);
+          e = make_double2(ht * e.x, ht * e.y);
           const double sc =
               a.atol + a.rtol * fmax(hypot(rho[s].x, rho[s].y), hypot(yn[s].x, yn[s].y));
           const double r = hypot(e.x, e.y) / sc;
