@@ -1843,8 +1843,13 @@ __global__ __launch_bounds__(T) void grad_resident_kernel(GradArgs a) {
     else return tid + s * T;
   };
   auto goff = [&](uint32_t v) { return L.off[slot_b(v)] + slot_i(v) * n + slot_j(v); };
+  // the segment whose amplitudes L.u holds: they are loaded again only when
+  // a step lies in another segment (the same for every thread)
+  int u_seg = -2;
   auto set_u = [&](int st) {  // between two barriers
     const int seg = a.seg_of_step[st];
+    if (seg == u_seg) return;
+    u_seg = seg;
     for (int idx = tid; idx < m * pk.nb; idx += T) {
       const int b = idx / pk.nb, q = idx - b * pk.nb;
       L.u[idx] = seg >= 0 ? a.u[((int64_t)L.ids[b] * a.n_ctrl + q) * a.n_seg + seg] : 0.0;
